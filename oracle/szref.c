@@ -242,7 +242,7 @@ static int check_params(const szref_params* p) {
   if (p->layers < 1 || p->layers > 4) return SZREF_EINVAL;
   if (p->quant_bits > 16) return SZREF_EINVAL;
   if (p->eb_mode > 2) return SZREF_EINVAL;
-  if (p->chunk != 0 && (p->chunk < 64 || p->chunk > 65536)) return SZREF_EINVAL;
+  if (p->chunk != 0 && (p->chunk < 256 || p->chunk > 4096 || p->chunk % 256)) return SZREF_EINVAL;
   if (p->theta < 0 || p->theta > 1 || p->theta != p->theta) return SZREF_EINVAL;
   return SZREF_OK;
 }

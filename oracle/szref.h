@@ -41,7 +41,7 @@ typedef struct {
   uint32_t layers;     /* n in [1,4] */
   uint32_t quant_bits; /* m in [1,16]; 0 = adaptive */
   uint32_t eb_mode;    /* 0 abs, 1 value-range relative, 2 both (minimum) */
-  uint32_t chunk;      /* symbols per decode chunk, 0 = default (1024) */
+  uint32_t chunk;      /* symbols per decode chunk: 0 = 1024, else a multiple of 256 in [256, 4096] */
   double eb_abs;
   double eb_rel;
   double theta;        /* hit-rate threshold for the adaptive rule, 0 = 0.9 */

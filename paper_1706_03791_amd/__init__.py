@@ -1,0 +1,250 @@
+"""MI355X (gfx950) error-bounded lossy compressor of arXiv 1706.03791 (SZ-1.4).
+
+Thin ctypes binding of the C ABI in ``include/szhip.h``: the functions named
+``sz_*`` mirror the C entry points one to one (argument marshalling only);
+``compress`` / ``decompress`` are conveniences over torch tensors on the GPU.
+Every step of the method runs in the HIP kernels of ``libszhip.so``; there is
+no CPU fallback -- importing the binding without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libszhip.so")
+
+SZ_OK, SZ_EINVAL, SZ_ECAPACITY, SZ_ECORRUPT, SZ_ENONFINITE, SZ_ENOMEM, SZ_EHIP, SZ_ESTALL = 0, -1, -2, -3, -4, -5, -6, -7
+SZ_F32, SZ_F64 = 0, 1
+SZ_EB_ABS, SZ_EB_REL, SZ_EB_ABS_AND_REL = 0, 1, 2
+HEADER_BYTES = 192
+
+EXPORTS = ("sz_ctx_create", "sz_ctx_destroy", "sz_compress_bound", "sz_compress", "sz_compress_async",
+           "sz_inspect", "sz_decompress", "sz_quantize", "sz_strerror", "sz_ctx_profile",
+           "sz_ctx_profile_read")
+STAGES = ("range", "sweep_compress", "codebook", "encode", "dectab", "decode", "unpred", "sweep_decompress")
+
+
+class SzParams(C.Structure):
+    _fields_ = [("dtype", C.c_uint32), ("ndim", C.c_uint32), ("dims", C.c_uint64 * 3),
+                ("block", C.c_uint64 * 3), ("layers", C.c_uint32), ("quant_bits", C.c_uint32),
+                ("eb_mode", C.c_uint32), ("chunk", C.c_uint32), ("eb_abs", C.c_double),
+                ("eb_rel", C.c_double), ("theta", C.c_double)]
+
+
+class SzStats(C.Structure):
+    _fields_ = [("n_points", C.c_uint64), ("n_unpred", C.c_uint64), ("huff_bits", C.c_uint64),
+                ("tail_bits", C.c_uint64), ("compressed_bytes", C.c_uint64), ("ebT_bits", C.c_uint64),
+                ("eb_used", C.c_double), ("hit_rate", C.c_double), ("value_min", C.c_double),
+                ("value_max", C.c_double), ("m_used", C.c_uint32), ("m_suggested", C.c_uint32),
+                ("raw_fallback", C.c_uint32), ("n_used_syms", C.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SzError(RuntimeError):
+    def __init__(self, code: int, where: str = ""):
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+        self.code = code
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """The loaded HIP library (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"HIP library missing: {LIB_PATH} (run paper_1706_03791_amd.build.build())")
+            L = C.CDLL(LIB_PATH)
+            vp, P = C.c_void_p, C.POINTER
+            L.sz_ctx_create.argtypes = [P(vp), C.c_int]
+            L.sz_ctx_destroy.argtypes = [vp]
+            L.sz_ctx_destroy.restype = None
+            L.sz_compress_bound.argtypes = [P(SzParams)]
+            L.sz_compress_bound.restype = C.c_size_t
+            L.sz_compress.argtypes = [vp, P(SzParams), vp, vp, C.c_size_t, P(C.c_size_t), P(SzStats), vp]
+            L.sz_compress_async.argtypes = [vp, P(SzParams), vp, vp, C.c_size_t, vp, vp, vp]
+            L.sz_inspect.argtypes = [vp, C.c_size_t, P(SzParams), P(SzStats)]
+            L.sz_decompress.argtypes = [vp, vp, C.c_size_t, vp, C.c_size_t, vp]
+            L.sz_quantize.argtypes = [vp, P(SzParams), vp, vp, vp, P(SzStats), vp]
+            L.sz_strerror.argtypes = [C.c_int]
+            L.sz_strerror.restype = C.c_char_p
+            L.sz_ctx_profile.argtypes = [vp, C.c_int]
+            L.sz_ctx_profile_read.argtypes = [vp, vp, vp, C.c_int]
+            _lib = L
+        return _lib
+
+
+def sz_strerror(code: int) -> str:
+    return lib().sz_strerror(int(code)).decode()
+
+
+def strerror(code: int) -> str:
+    try:
+        return sz_strerror(code)
+    except RuntimeError:
+        return f"error {code}"
+
+
+# ------------------------------------------------------------ C ABI mirror
+def sz_ctx_create(device: int = 0) -> int:
+    h = C.c_void_p()
+    rc = lib().sz_ctx_create(C.byref(h), int(device))
+    if rc:
+        raise SzError(rc, "sz_ctx_create")
+    return h.value
+
+
+def sz_ctx_destroy(ctx: int) -> None:
+    lib().sz_ctx_destroy(C.c_void_p(ctx))
+
+
+def sz_compress_bound(p: SzParams) -> int:
+    return lib().sz_compress_bound(C.byref(p))
+
+
+def sz_compress(ctx, p: SzParams, d_in: int, d_out: int, cap: int, stream: int = 0):
+    """Returns (rc, out_size, stats)."""
+    size = C.c_size_t(0)
+    st = SzStats()
+    rc = lib().sz_compress(C.c_void_p(ctx), C.byref(p), C.c_void_p(d_in), C.c_void_p(d_out), cap,
+                           C.byref(size), C.byref(st), C.c_void_p(stream))
+    return rc, size.value, st
+
+
+def sz_compress_async(ctx, p: SzParams, d_in: int, d_out: int, cap: int, d_out_size: int, d_status: int,
+                      stream: int = 0) -> int:
+    return lib().sz_compress_async(C.c_void_p(ctx), C.byref(p), C.c_void_p(d_in), C.c_void_p(d_out), cap,
+                                   C.c_void_p(d_out_size), C.c_void_p(d_status), C.c_void_p(stream))
+
+
+def sz_inspect(header: bytes):
+    """Returns (rc, params, stats) of a container header held in host memory."""
+    buf = (C.c_uint8 * len(header)).from_buffer_copy(header)
+    p, s = SzParams(), SzStats()
+    rc = lib().sz_inspect(buf, len(header), C.byref(p), C.byref(s))
+    return rc, p, s
+
+
+def sz_decompress(ctx, d_comp: int, comp_size: int, d_out: int, cap: int, stream: int = 0) -> int:
+    return lib().sz_decompress(C.c_void_p(ctx), C.c_void_p(d_comp), comp_size, C.c_void_p(d_out), cap,
+                               C.c_void_p(stream))
+
+
+def sz_quantize(ctx, p: SzParams, d_in: int, d_codes: int, d_xprime: int = 0, stream: int = 0):
+    st = SzStats()
+    rc = lib().sz_quantize(C.c_void_p(ctx), C.byref(p), C.c_void_p(d_in), C.c_void_p(d_codes),
+                           C.c_void_p(d_xprime or None), C.byref(st), C.c_void_p(stream))
+    return rc, st
+
+
+def sz_ctx_profile(ctx, enable: bool = True) -> int:
+    return lib().sz_ctx_profile(C.c_void_p(ctx), int(enable))
+
+
+def sz_ctx_profile_read(ctx):
+    """Accumulated per-stage milliseconds and call counts as a dict."""
+    ms = (C.c_double * 16)()
+    calls = (C.c_uint64 * 16)()
+    n = lib().sz_ctx_profile_read(C.c_void_p(ctx), ms, calls, 16)
+    return {STAGES[i]: (ms[i], calls[i]) for i in range(min(n, len(STAGES)))}
+
+
+# ------------------------------------------------------- torch conveniences
+_ctx = {}
+
+
+def context(device: int = 0) -> int:
+    with _lock:
+        pass
+    if device not in _ctx:
+        _ctx[device] = sz_ctx_create(device)
+    return _ctx[device]
+
+
+def make_params(shape, dtype="float32", layers=1, m=8, eb_mode="rel", eb_abs=0.0, eb_rel=0.0,
+                block=None, chunk=0, theta=0.0) -> SzParams:
+    p = SzParams()
+    p.dtype = SZ_F32 if str(dtype).endswith("float32") else SZ_F64
+    p.ndim = len(shape)
+    for d, s in enumerate(shape):
+        p.dims[d] = int(s)
+    if block is not None:
+        for d, b in enumerate(block):
+            p.block[d] = int(b)
+    p.layers = int(layers)
+    p.quant_bits = int(m)
+    p.eb_mode = {"abs": SZ_EB_ABS, "rel": SZ_EB_REL, "both": SZ_EB_ABS_AND_REL}[eb_mode] \
+        if isinstance(eb_mode, str) else int(eb_mode)
+    p.chunk = int(chunk)
+    p.eb_abs = float(eb_abs)
+    p.eb_rel = float(eb_rel)
+    p.theta = float(theta)
+    return p
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def compress(x, stream=None, out=None, **kw):
+    """Compress a contiguous float32/float64 CUDA tensor.
+
+    Returns (container uint8 tensor view, stats dict).  Keyword arguments are
+    those of ``make_params`` (layers, m, eb_mode, eb_abs, eb_rel, block,
+    chunk, theta).
+    """
+    import torch
+    if not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous device tensor")
+    p = make_params(tuple(x.shape), x.dtype, **kw)
+    cap = sz_compress_bound(p)
+    if cap == 0:
+        raise SzError(SZ_EINVAL, "compress")
+    if out is None:
+        out = torch.empty(cap, dtype=torch.uint8, device=x.device)
+    rc, size, st = sz_compress(context(x.device.index or 0), p, x.data_ptr(), out.data_ptr(), out.numel(),
+                               _stream(stream))
+    if rc:
+        raise SzError(rc, "sz_compress")
+    return out[:size], st.as_dict()
+
+
+def decompress(comp, stream=None, out=None):
+    """Decompress a container held in a CUDA uint8 tensor; returns the field."""
+    import torch
+    hdr = bytes(comp[:HEADER_BYTES].cpu().numpy().tobytes())
+    rc, p, _ = sz_inspect(hdr)
+    if rc:
+        raise SzError(rc, "sz_inspect")
+    shape = tuple(int(p.dims[d]) for d in range(p.ndim))
+    dt = torch.float32 if p.dtype == SZ_F32 else torch.float64
+    if out is None:
+        out = torch.empty(shape, dtype=dt, device=comp.device)
+    rc = sz_decompress(context(comp.device.index or 0), comp.data_ptr(), comp.numel(), out.data_ptr(),
+                       out.numel() * out.element_size(), _stream(stream))
+    if rc:
+        raise SzError(rc, "sz_decompress")
+    return out
+
+
+def quantize(x, m=8, stream=None, want_xprime=False, **kw):
+    """Debug: codes (int32 tensor of the uint16 codes) of one sweep at fixed m."""
+    import torch
+    p = make_params(tuple(x.shape), x.dtype, m=m, **kw)
+    codes = torch.empty(x.numel() + 8, dtype=torch.int16, device=x.device)
+    xp = torch.empty_like(x) if want_xprime else None
+    rc, st = sz_quantize(context(x.device.index or 0), p, x.data_ptr(), codes.data_ptr(),
+                         xp.data_ptr() if xp is not None else 0, _stream(stream))
+    if rc:
+        raise SzError(rc, "sz_quantize")
+    c = codes[: x.numel()].view(x.shape).to(torch.int32) & 0xFFFF
+    return (c, xp, st.as_dict()) if want_xprime else (c, st.as_dict())

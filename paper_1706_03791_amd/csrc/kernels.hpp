@@ -1,0 +1,1014 @@
+// Kernels around the wavefront sweep: value range and error bound
+// (Metric 1), adaptive interval count (Sec. IV-B), Huffman codebook,
+// encoding and decoding (Sec. IV-A), storage of unpredictable values
+// (Sec. IV-B, Algorithm 1) and the container writer/reader.
+#pragma once
+
+#include "common.hpp"
+#include "sweep.hpp"
+
+namespace szh {
+
+// ------------------------------------------------------------ block scans
+// Exclusive scan over a workgroup of NT threads (NT a multiple of 64).
+template <int NT, typename V>
+__device__ __forceinline__ V block_exscan(V v, V* lds, V* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  V x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    V y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds[wid] = x;
+  __syncthreads();
+  if (wid == 0) {
+    V w = (lane < NT / 64) ? lds[lane] : V(0);
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      V y = __shfl_up(w, o, 64);
+      if (lane >= o) w += y;
+    }
+    if (lane < NT / 64) lds[lane] = w;
+  }
+  __syncthreads();
+  const V off = wid ? lds[wid - 1] : V(0);
+  const V tot = lds[NT / 64 - 1];
+  __syncthreads();
+  if (total) *total = tot;
+  return off + x - v;
+}
+
+template <int NT, typename V>
+__device__ __forceinline__ V block_sum(V v, V* lds) {
+  V tot;
+  block_exscan<NT, V>(v, lds, &tot);
+  return tot;
+}
+
+__device__ __forceinline__ void set_status(DevPlan* P, int code) {
+  atomicCAS(&P->status, 0, code);
+}
+
+// ------------------------------------------------------------- utilities
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Zero the first plan->total bytes of the container (sections are written
+// with OR operations and padding must read as zero).
+__global__ void zero_container_kernel(uint32_t* out, const DevPlan* P) {
+  if (P->status || P->raw) return;
+  const uint64_t nw = (P->total + 3) / 4;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = 0;
+}
+
+struct PlanInit {
+  uint32_t m;        // 16 for the first adaptive sweep
+  uint32_t eb_mode;
+  double eb_abs, eb_rel;
+  uint32_t dtype;
+  uint64_t cap;
+};
+
+__global__ void plan_init_kernel(DevPlan* P, PlanInit I) {
+  if (threadIdx.x == 0) {
+    DevPlan z = {};
+    z.m = I.m;
+    z.minmax_bits[0] = 0xFFFFFFFFu;
+    z.minmax_bits[1] = 0;
+    z.minmax64[0] = ~0ull;
+    z.minmax64[1] = 0;
+    z.out_cap = I.cap;
+    *P = z;
+  }
+}
+
+// Order-preserving integer images of floating-point values.
+__device__ __forceinline__ uint32_t ord32(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float unord32(uint32_t o) {
+  uint32_t u = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+  return __builtin_bit_cast(float, u);
+}
+__device__ __forceinline__ uint64_t ord64(double f) {
+  uint64_t u = __builtin_bit_cast(uint64_t, f);
+  return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+__device__ __forceinline__ double unord64(uint64_t o) {
+  uint64_t u = (o >> 63) ? (o & ~(1ull << 63)) : ~o;
+  return __builtin_bit_cast(double, u);
+}
+
+// ----------------------------------------------------- K1: value range
+template <typename T>
+__global__ void __launch_bounds__(256) minmax_kernel(const T* __restrict__ x, uint64_t n, DevPlan* P) {
+  __shared__ uint64_t lmin[4], lmax[4];
+  __shared__ uint32_t lnf;
+  if (threadIdx.x == 0) lnf = 0;
+  uint64_t mn = ~0ull, mx = 0;
+  uint32_t nf = 0;
+  constexpr int V = 16 / sizeof(T);
+  const uint64_t nv = n / V;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
+    uint4 raw = ((const uint4*)x)[i];
+    const T* v = (const T*)&raw;
+#pragma unroll
+    for (int e = 0; e < V; e++) {
+      const T f = v[e];
+      nf |= !isfinite(f);
+      const uint64_t o = (sizeof(T) == 4) ? (uint64_t)ord32((float)f) : ord64((double)f);
+      mn = o < mn ? o : mn;
+      mx = o > mx ? o : mx;
+    }
+  }
+  for (uint64_t i = nv * V + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const T f = x[i];
+    nf |= !isfinite(f);
+    const uint64_t o = (sizeof(T) == 4) ? (uint64_t)ord32((float)f) : ord64((double)f);
+    mn = o < mn ? o : mn;
+    mx = o > mx ? o : mx;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint64_t a = __shfl_xor(mn, o, 64), b = __shfl_xor(mx, o, 64);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (nf) atomicOr(&lnf, 1u);
+  if (lane == 0) {
+    lmin[wid] = mn;
+    lmax[wid] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; w++) {
+      mn = lmin[w] < mn ? lmin[w] : mn;
+      mx = lmax[w] > mx ? lmax[w] : mx;
+    }
+    if (sizeof(T) == 4) {
+      atomicMin(&P->minmax_bits[0], (uint32_t)mn);
+      atomicMax(&P->minmax_bits[1], (uint32_t)mx);
+    } else {
+      atomicMin((unsigned long long*)&P->minmax64[0], (unsigned long long)mn);
+      atomicMax((unsigned long long*)&P->minmax64[1], (unsigned long long)mx);
+    }
+    if (lnf) atomicOr(&P->nonfinite, 1u);
+  }
+}
+
+// Error bound in the element type: eb (double) rounded toward zero into T,
+// 2eb = eb + eb and 1/(2eb), each one IEEE operation in T (Metric 1).
+template <typename T>
+__global__ void eb_resolve_kernel(DevPlan* P, PlanInit I) {
+  using U = typename FTr<T>::U;
+  if (threadIdx.x != 0 || P->status) return;
+  double eb = I.eb_abs;
+  if (I.eb_mode != SZ_EB_ABS) {
+    if (P->nonfinite) {
+      P->status = SZ_ENONFINITE;
+      return;
+    }
+    double lo, hi;
+    if (sizeof(T) == 4) {
+      lo = (double)unord32(P->minmax_bits[0]);
+      hi = (double)unord32(P->minmax_bits[1]);
+    } else {
+      lo = unord64(P->minmax64[0]);
+      hi = unord64(P->minmax64[1]);
+    }
+    P->vmin = lo;
+    P->vmax = hi;
+    const double range = hi - lo;
+    const double rel = I.eb_rel * range;
+    eb = (I.eb_mode == SZ_EB_REL) ? rel : (I.eb_abs < rel ? I.eb_abs : rel);
+  }
+  const double tmax = (sizeof(T) == 4) ? 3.4028234663852886e38 : 1.7976931348623157e308;
+  if (!(eb <= tmax / 4)) {
+    P->status = SZ_EINVAL;
+    return;
+  }
+  T e = (T)eb;
+  if ((double)e > eb) e = bits_to<T>(to_bits<T>(e) - 1);
+  const T two = e + e;
+  const T inv = T(1) / two;
+  P->eb = (double)e;
+  P->ebT_bits = (uint64_t)to_bits<T>(e);
+  P->twoeb_bits = (uint64_t)to_bits<T>(two);
+  P->inv2eb_bits = (uint64_t)to_bits<T>(inv);
+}
+
+// Adaptive interval count (Sec. IV-B): from the 2^16-code histogram, the
+// smallest m whose intervals |k| <= 2^(m-1) - 1 hold theta * N points.
+__global__ void __launch_bounds__(1024) pick_m_kernel(uint32_t* hist, DevPlan* P, uint64_t n, double theta) {
+  __shared__ unsigned long long bucket[17];
+  if (P->status) return;
+  if (threadIdx.x < 17) bucket[threadIdx.x] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x + 1; i < 65536; i += blockDim.x) {
+    const uint32_t h = hist[i];
+    if (!h) continue;
+    const int k = i - 32768;
+    const uint32_t a = (uint32_t)(k < 0 ? -k : k) + 1u;  // |k| + 1
+    // smallest m with a <= 2^(m-1)
+    int mk = 1;
+    while ((1u << (mk - 1)) < a) mk++;
+    atomicAdd(&bucket[mk], (unsigned long long)h);
+  }
+  __syncthreads();
+  __shared__ uint32_t s_m;
+  if (threadIdx.x == 0) {
+    uint32_t mstar = 16;
+    unsigned long long cov = 0;
+    for (int m = 1; m <= 16; m++) {
+      cov += bucket[m];
+      if ((double)cov >= theta * (double)n) {
+        mstar = m;
+        break;
+      }
+    }
+    s_m = mstar;
+    P->m = mstar;
+    P->rerun = mstar < 16;
+  }
+  __syncthreads();
+  if (s_m < 16)
+    for (int i = threadIdx.x; i < 65536; i += blockDim.x) hist[i] = 0;
+}
+
+// ------------------------------------------------------------ sorting
+// Bitonic sort of n (power of two) 64-bit keys held at `k` (LDS or global)
+// by one workgroup.
+template <int NT>
+__device__ void bitonic_sort(uint64_t* k, uint32_t n) {
+  for (uint32_t size = 2; size <= n; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t t = threadIdx.x; t < n / 2; t += NT) {
+        const uint32_t lo = 2 * t - (t & (stride - 1));
+        const uint32_t hi = lo + stride;
+        const bool up = ((lo & size) == 0);
+        const uint64_t a = k[lo], b = k[hi];
+        if ((a > b) == up) {
+          k[lo] = b;
+          k[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// --------------------------------------------------- K4: Huffman codebook
+struct CodebookArgs {
+  const uint32_t* hist;
+  uint8_t* len;        // 2^m
+  uint32_t* cw;        // 2^m
+  uint64_t* gkeys;     // 65536 (global sort scratch)
+  uint64_t* gw;        // 131072 (global merge scratch)
+  uint32_t* gpar;      // 131072
+  uint32_t* ganc;      // 2 x 131072
+  uint32_t* gdep;      // 2 x 131072
+  DevPlan* plan;
+  uint64_t n;
+  double theta;
+};
+
+constexpr int kCbNT = 1024;
+constexpr uint32_t kCbLdsSyms = 2048;
+
+// Code lengths by the two-queue construction over leaves sorted by
+// (frequency, symbol), the leaf queue winning ties; depths by pointer
+// jumping over the parent links; lengths above 27 are repaired by halving
+// every frequency (keeping it >= 1) and rebuilding.  Canonical codes follow
+// in (length, symbol) order.
+__global__ void __launch_bounds__(kCbNT) codebook_kernel(CodebookArgs A) {
+  DevPlan* P = A.plan;
+  if (P->status) return;
+  __shared__ uint64_t s_keys[kCbLdsSyms];
+  __shared__ uint64_t s_w[2 * kCbLdsSyms];
+  __shared__ uint32_t s_par[2 * kCbLdsSyms];
+  __shared__ uint32_t s_dep[2 * kCbLdsSyms];
+  __shared__ uint32_t s_par2[2 * kCbLdsSyms];
+  __shared__ uint32_t s_red[64];
+  __shared__ uint32_t s_cnt[32], s_first[32], s_start[32];
+  __shared__ uint32_t s_s, s_maxd;
+
+  const uint32_t m = P->m;
+  const uint32_t nsym = 1u << m;
+  const int tid = threadIdx.x;
+
+  // used symbols, compacted in symbol order
+  const uint32_t per = (nsym + kCbNT - 1) / kCbNT;
+  const uint32_t lo = min(nsym, tid * per), hi = min(nsym, lo + per);
+  uint32_t cnt = 0;
+  for (uint32_t q = lo; q < hi; q++) cnt += A.hist[q] != 0;
+  uint32_t total;
+  uint32_t pos = block_exscan<kCbNT, uint32_t>(cnt, s_red, &total);
+  const uint32_t s = total;
+  const bool in_lds = s <= kCbLdsSyms;
+  uint64_t* K = in_lds ? s_keys : A.gkeys;
+  uint64_t* W = in_lds ? s_w : A.gw;
+  uint32_t* PAR = in_lds ? s_par : A.gpar;
+  uint32_t np2 = 1;
+  while (np2 < s) np2 <<= 1;
+  for (uint32_t q = lo; q < hi; q++) {
+    const uint32_t f = A.hist[q];
+    if (f) K[pos++] = ((uint64_t)f << 16) | q;
+  }
+  for (uint32_t i = s + tid; i < np2; i += kCbNT) K[i] = ~0ull;
+  for (uint32_t q = lo; q < hi; q++) A.len[q] = 0;
+  __syncthreads();
+
+  if (s == 1) {
+    if (tid == 0) {
+      const uint32_t sym = (uint32_t)(K[0] & 0xFFFF);
+      A.len[sym] = 1;
+      A.cw[sym] = 0;
+      P->n_used = 1;
+      P->max_len = 1;
+    }
+  } else {
+    for (int attempt = 0; attempt < 64; attempt++) {
+      bitonic_sort<kCbNT>(K, np2);
+      if (tid == 0) {
+        // two-queue merge: leaves 0..s-1, internal nodes s..2s-2
+        uint32_t i = 0, j = s, next = s;
+        for (uint32_t step = 0; step + 1 < s; step++) {
+          uint32_t pk[2];
+          uint64_t wk[2];
+          for (int q = 0; q < 2; q++) {
+            const uint64_t wl = (i < s) ? (K[i] >> 16) : ~0ull;
+            const uint64_t wi = (j < next) ? W[j] : ~0ull;
+            if (i < s && (j >= next || wl <= wi)) {
+              pk[q] = i;
+              wk[q] = wl;
+              i++;
+            } else {
+              pk[q] = j;
+              wk[q] = wi;
+              j++;
+            }
+          }
+          W[next] = wk[0] + wk[1];
+          PAR[pk[0]] = next;
+          PAR[pk[1]] = next;
+          next++;
+        }
+        PAR[2 * s - 2] = 2 * s - 2;
+      }
+      __syncthreads();
+      // depths by pointer jumping (double-buffered ancestor/depth arrays)
+      const uint32_t nn = 2 * s - 1;
+      uint32_t *ANC, *DEP, *ANC2, *DEP2;
+      if (in_lds) {
+        ANC = (uint32_t*)s_w;  // merge weights are no longer needed
+        ANC2 = (uint32_t*)s_w + 2 * kCbLdsSyms;
+        DEP = s_dep;
+        DEP2 = s_par2;
+      } else {
+        ANC = A.ganc;
+        ANC2 = A.ganc + 131072;
+        DEP = A.gdep;
+        DEP2 = A.gdep + 131072;
+      }
+      for (uint32_t v = tid; v < nn; v += kCbNT) {
+        ANC[v] = PAR[v];
+        DEP[v] = (v == nn - 1) ? 0u : 1u;
+      }
+      __syncthreads();
+      for (uint32_t span = 1; span < nn; span <<= 1) {
+        for (uint32_t v = tid; v < nn; v += kCbNT) {
+          const uint32_t a = ANC[v];
+          DEP2[v] = DEP[v] + DEP[a];
+          ANC2[v] = ANC[a];
+        }
+        __syncthreads();
+        uint32_t* t0 = ANC; ANC = ANC2; ANC2 = t0;
+        uint32_t* t1 = DEP; DEP = DEP2; DEP2 = t1;
+      }
+      uint32_t md = 0;
+      for (uint32_t v = tid; v < s; v += kCbNT) md = max(md, DEP[v]);
+      for (int o = 32; o >= 1; o >>= 1) md = max(md, (uint32_t)__shfl_xor(md, o, 64));
+      if (tid == 0) s_maxd = 0;
+      __syncthreads();
+      if ((tid & 63) == 0) atomicMax(&s_maxd, md);
+      __syncthreads();
+      const uint32_t maxd = s_maxd;
+      if (maxd <= (uint32_t)kLmax) {
+        for (uint32_t v = tid; v < s; v += kCbNT) A.len[K[v] & 0xFFFF] = (uint8_t)DEP[v];
+        if (tid == 0) {
+          P->n_used = s;
+          P->max_len = maxd;
+        }
+        __syncthreads();
+        break;
+      }
+      // halve frequencies, keep >= 1
+      for (uint32_t v = tid; v < s; v += kCbNT) {
+        uint64_t f = K[v] >> 16;
+        f >>= 1;
+        if (!f) f = 1;
+        K[v] = (f << 16) | (K[v] & 0xFFFF);
+      }
+      __syncthreads();
+    }
+    // canonical codes: sort used symbols by (length, symbol)
+    if (tid < 32) s_cnt[tid] = 0;
+    __syncthreads();
+    for (uint32_t v = tid; v < s; v += kCbNT) {
+      const uint32_t sym = (uint32_t)(K[v] & 0xFFFF);
+      const uint32_t l = A.len[sym];
+      K[v] = ((uint64_t)l << 16) | sym;
+      atomicAdd(&s_cnt[l], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t code = 0, start = 0;
+      for (int l = 1; l <= kLmax; l++) {
+        s_first[l] = code;
+        s_start[l] = start;
+        code = (code + s_cnt[l]) << 1;
+        start += s_cnt[l];
+      }
+    }
+    bitonic_sort<kCbNT>(K, np2);
+    for (uint32_t v = tid; v < s; v += kCbNT) {
+      const uint32_t sym = (uint32_t)(K[v] & 0xFFFF);
+      const uint32_t l = (uint32_t)(K[v] >> 16);
+      A.cw[sym] = s_first[l] + (v - s_start[l]);
+    }
+  }
+  if (tid == 0) {
+    const double hr = 1.0 - (double)A.hist[0] / (double)A.n;
+    P->m_suggested = (hr < A.theta && m < 16) ? m + 1 : m;
+  }
+}
+
+// ---------------------------------------------------------- bit helpers
+// Stream bit b sits in word b/32 at bit 31 - b%32 (MSB first).
+__device__ __forceinline__ void or_bits(uint32_t* words, uint64_t pos, uint64_t val, int nb) {
+  // nb <= 57
+  while (nb > 0) {
+    const uint64_t w = pos >> 5;
+    const int off = (int)(pos & 31);
+    const int take = min(nb, 32 - off);
+    const uint32_t chunk = (uint32_t)((val >> (nb - take)) & ((1ull << take) - 1));
+    atomicOr(&words[w], chunk << (32 - off - take));
+    pos += take;
+    nb -= take;
+  }
+}
+
+__device__ __forceinline__ uint64_t read_bits(const uint32_t* words, uint64_t nwords, uint64_t pos, int nb) {
+  uint64_t v = 0;
+  while (nb > 0) {
+    const uint64_t w = pos >> 5;
+    const int off = (int)(pos & 31);
+    const int take = min(nb, 32 - off);
+    const uint32_t word = (w < nwords) ? words[w] : 0u;
+    v = (v << take) | ((word >> (32 - off - take)) & (uint32_t)((1ull << take) - 1));
+    pos += take;
+    nb -= take;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ int kept_bits(T x, typename FTr<T>::U ebT_bits) {
+  using U = typename FTr<T>::U;
+  constexpr int MANT = FTr<T>::MANT, EMAX = FTr<T>::EMAX;
+  const int e = (int)((to_bits<T>(x) >> MANT) & (U)EMAX);
+  const int e_eb = (int)((ebT_bits >> MANT) & (U)EMAX);
+  if (e_eb == 0 || e == EMAX) return MANT;
+  if (e == 0 || e < e_eb) return 0;
+  return min(e - e_eb, MANT);
+}
+
+// ------------------------------------------------- K5a: per-chunk totals
+template <typename T, typename CT>
+__global__ void __launch_bounds__(256) chunk_stats_kernel(const CT* __restrict__ codes, const T* __restrict__ x,
+                                                          const uint8_t* __restrict__ len, uint64_t n,
+                                                          uint32_t C, uint32_t* cbits, uint32_t* cu,
+                                                          uint32_t* ctb, const DevPlan* P) {
+  using U = typename FTr<T>::U;
+  __shared__ uint32_t red[8];
+  if (P->status) return;
+  const uint64_t c = blockIdx.x;
+  const uint64_t i0 = c * C, i1 = min(n, i0 + C);
+  const U ebb = (U)P->ebT_bits;
+  uint32_t b = 0, z = 0, tb = 0;
+  for (uint64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+    const uint32_t code = codes[i];
+    b += len[code];
+    if (code == 0) {
+      z++;
+      tb += (uint32_t)kept_bits<T>(x[i], ebb);
+    }
+  }
+  b = block_sum<256, uint32_t>(b, red);
+  z = block_sum<256, uint32_t>(z, red);
+  tb = block_sum<256, uint32_t>(tb, red);
+  if (threadIdx.x == 0) {
+    cbits[c] = b;
+    cu[c] = z;
+    ctb[c] = tb;
+  }
+}
+
+// ------------------------------------------ device-wide exclusive scans
+// Phase 1: per-workgroup sums of 4096-element tiles.
+__global__ void __launch_bounds__(1024) scan_tile_sums(const uint32_t* __restrict__ in, uint64_t n, uint64_t* tsum) {
+  __shared__ uint64_t red[16];
+  const uint64_t t0 = (uint64_t)blockIdx.x * 4096;
+  uint64_t s = 0;
+  for (int k = 0; k < 4; k++) {
+    const uint64_t i = t0 + (uint64_t)k * 1024 + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  s = block_sum<1024, uint64_t>(s, red);
+  if (threadIdx.x == 0) tsum[blockIdx.x] = s;
+}
+// Phase 2: one workgroup scans the tile sums in place; total to *total.
+__global__ void __launch_bounds__(1024) scan_tile_offsets(uint64_t* tsum, uint64_t ntiles, uint64_t* total) {
+  __shared__ uint64_t red[16];
+  const uint64_t per = (ntiles + 1023) / 1024;
+  const uint64_t lo = min(ntiles, (uint64_t)threadIdx.x * per), hi = min(ntiles, lo + per);
+  uint64_t s = 0;
+  for (uint64_t i = lo; i < hi; i++) s += tsum[i];
+  uint64_t tot;
+  uint64_t off = block_exscan<1024, uint64_t>(s, red, &tot);
+  for (uint64_t i = lo; i < hi; i++) {
+    const uint64_t v = tsum[i];
+    tsum[i] = off;
+    off += v;
+  }
+  if (threadIdx.x == 0 && total) *total = tot;
+}
+// Phase 3: exclusive prefix of every element.
+__global__ void __launch_bounds__(1024) scan_apply(const uint32_t* __restrict__ in, uint64_t n, const uint64_t* tsum,
+                                                   uint64_t* out) {
+  __shared__ uint64_t red[16];
+  const uint64_t t0 = (uint64_t)blockIdx.x * 4096;
+  uint64_t base = tsum[blockIdx.x];
+  for (int k = 0; k < 4; k++) {
+    const uint64_t i = t0 + (uint64_t)k * 1024 + threadIdx.x;
+    const uint64_t v = (i < n) ? in[i] : 0;
+    uint64_t tot;
+    const uint64_t ex = block_exscan<1024, uint64_t>(v, red, &tot);
+    if (i < n) out[i] = base + ex;
+    base += tot;
+  }
+}
+
+// --------------------------------------- container layout (after scans)
+struct LayoutArgs {
+  DevPlan* plan;
+  const uint64_t* tot_bits;
+  const uint64_t* tot_u;
+  const uint64_t* tot_tb;
+  uint64_t n_chunks;
+  uint64_t raw_size;  // header + S
+  uint32_t head_bits;
+};
+__device__ __forceinline__ uint64_t align64(uint64_t v) { return (v + 63) & ~63ull; }
+
+__global__ void layout_kernel(LayoutArgs A) {
+  DevPlan* P = A.plan;
+  if (threadIdx.x || P->status) return;
+  P->huff_bits = *A.tot_bits;
+  P->n_unpred = *A.tot_u;
+  P->tail_bits = *A.tot_tb;
+  P->off_cb = kHdr;
+  P->off_ch = align64(kHdr + 3ull * P->n_used);
+  P->off_bs = align64(P->off_ch + 4ull * A.n_chunks);
+  P->off_hd = align64(P->off_bs + 4ull * ((P->huff_bits + 31) / 32));
+  P->off_tl = align64(P->off_hd + 4ull * ((P->n_unpred * A.head_bits + 31) / 32));
+  P->total = P->off_tl + 4ull * ((P->tail_bits + 31) / 32);
+  P->raw = P->total >= A.raw_size;
+  if (P->raw) P->total = A.raw_size;
+  if (P->total > P->out_cap) P->status = SZ_ECAPACITY;
+}
+
+// ------------------------------------------------------- K5c: encoding
+constexpr int kEncNT = 256;
+constexpr int kMaxChunk = 4096;
+
+template <typename T, typename CT>
+__global__ void __launch_bounds__(kEncNT) encode_kernel(const CT* __restrict__ codes, const T* __restrict__ x,
+                                                        const uint8_t* __restrict__ len,
+                                                        const uint32_t* __restrict__ cw, uint64_t n, uint32_t C,
+                                                        const uint32_t* cbits, const uint64_t* boff,
+                                                        const uint64_t* uoff, const uint64_t* toff,
+                                                        uint8_t* out, const DevPlan* P) {
+  using U = typename FTr<T>::U;
+  constexpr int MANT = FTr<T>::MANT;
+  constexpr int HB = 1 + FTr<T>::EXPB;
+  __shared__ uint32_t words[kMaxChunk * kLmax / 32 + 2];
+  __shared__ uint64_t red[8];
+  if (P->status || P->raw) return;
+  const uint64_t c = blockIdx.x;
+  const uint64_t i0 = c * C, i1 = min(n, i0 + C);
+  const uint32_t nb = cbits[c];
+  const uint64_t b0 = boff[c];
+  const uint32_t nw = (uint32_t)((((b0 & 31) + nb) + 31) / 32);
+  for (uint32_t w = threadIdx.x; w < nw; w += kEncNT) words[w] = 0;
+  uint32_t* bs = (uint32_t*)(out + P->off_bs);
+  uint32_t* hd = (uint32_t*)(out + P->off_hd);
+  uint32_t* tl = (uint32_t*)(out + P->off_tl);
+  const U ebb = (U)P->ebT_bits;
+  // each thread takes a contiguous run of symbols (raster order preserved)
+  const uint32_t per = (C + kEncNT - 1) / kEncNT;
+  const uint64_t lo = min(i1, i0 + (uint64_t)threadIdx.x * per), hi = min(i1, lo + per);
+  uint64_t mybits = 0, myz = 0, mytb = 0;
+  for (uint64_t i = lo; i < hi; i++) {
+    const uint32_t code = codes[i];
+    mybits += len[code];
+    if (code == 0) {
+      myz++;
+      mytb += kept_bits<T>(x[i], ebb);
+    }
+  }
+  uint64_t bpos = block_exscan<kEncNT, uint64_t>(mybits, red, nullptr);
+  uint64_t zpos = block_exscan<kEncNT, uint64_t>(myz, red, nullptr);
+  uint64_t tpos = block_exscan<kEncNT, uint64_t>(mytb, red, nullptr);
+  bpos += (b0 & 31);
+  zpos += uoff[c];
+  tpos += toff[c];
+  for (uint64_t i = lo; i < hi; i++) {
+    const uint32_t code = codes[i];
+    const int l = len[code];
+    const uint32_t v = cw[code];
+    // at most two LDS words per code (l <= 27)
+    const uint32_t w = (uint32_t)(bpos >> 5);
+    const int off = (int)(bpos & 31);
+    if (off + l <= 32) {
+      atomicOr(&words[w], v << (32 - off - l));
+    } else {
+      const int first = 32 - off;
+      atomicOr(&words[w], v >> (l - first));
+      atomicOr(&words[w + 1], v << (32 - (l - first)));
+    }
+    bpos += l;
+    if (code == 0) {
+      const T xt = truncate_unpred<T>(x[i], ebb);
+      const U ub = to_bits<T>(xt);
+      const int r = kept_bits<T>(x[i], ebb);
+      or_bits(hd, zpos * HB, (uint64_t)(ub >> MANT), HB);
+      if (r > 0) or_bits(tl, tpos, (uint64_t)((ub & ((((U)1) << MANT) - 1)) >> (MANT - r)), r);
+      zpos++;
+      tpos += r;
+    }
+  }
+  __syncthreads();
+  const uint64_t gw0 = b0 >> 5;
+  const uint64_t bend = b0 + nb;
+  for (uint32_t w = threadIdx.x; w < nw; w += kEncNT) {
+    const uint64_t gw = gw0 + w;
+    const bool full = (gw * 32 >= b0) && (gw * 32 + 32 <= bend);
+    if (full)
+      bs[gw] = words[w];
+    else if (words[w])
+      atomicOr(&bs[gw], words[w]);
+  }
+  // chunk table entry
+  if (threadIdx.x == 0) ((uint32_t*)(out + P->off_ch))[c] = nb;
+}
+
+// -------------------------------------------------- K7: header + codebook
+struct HeaderArgs {
+  uint8_t* out;
+  const uint8_t* len;
+  const DevPlan* plan;
+  uint32_t dtype, ndim, layers, eb_mode, m_req, chunk;
+  uint64_t dims[3], block[3];
+  double eb_abs, eb_rel;
+  uint64_t n, n_chunks;
+};
+
+__device__ __forceinline__ void put64(uint8_t* b, uint64_t v) {
+  for (int i = 0; i < 8; i++) b[i] = (uint8_t)(v >> (8 * i));
+}
+
+__global__ void __launch_bounds__(256) header_kernel(HeaderArgs A) {
+  __shared__ uint8_t h[kHdr];
+  __shared__ uint32_t red[8];
+  const DevPlan* P = A.plan;
+  if (P->status) return;
+  const int tid = threadIdx.x;
+  if (tid < (int)kHdr) h[tid] = 0;
+  __syncthreads();
+  if (tid == 0) {
+    const bool raw = P->raw;
+    put64(h + 0, kMagic | ((uint64_t)kVersion << 32) | ((uint64_t)(raw ? 1 : 0) << 48));
+    h[8] = (uint8_t)A.dtype;
+    h[9] = (uint8_t)A.ndim;
+    h[10] = (uint8_t)A.layers;
+    h[11] = (uint8_t)P->m;
+    h[12] = (uint8_t)A.eb_mode;
+    h[13] = (uint8_t)A.m_req;
+    for (int d = 0; d < 3; d++) put64(h + 16 + 8 * d, A.dims[d]);
+    for (int d = 0; d < 3; d++) put64(h + 40 + 8 * d, A.block[d]);
+    put64(h + 64, __builtin_bit_cast(uint64_t, A.eb_abs));
+    put64(h + 72, __builtin_bit_cast(uint64_t, A.eb_rel));
+    put64(h + 80, P->ebT_bits);
+    put64(h + 88, A.n);
+    put64(h + 96, raw ? 0 : P->n_unpred);
+    put64(h + 104, raw ? 0 : P->huff_bits);
+    put64(h + 112, raw ? 0 : P->tail_bits);
+    put64(h + 120, (uint64_t)A.chunk | ((uint64_t)(raw ? 0 : P->n_used) << 32));
+    put64(h + 128, raw ? 0 : A.n_chunks);
+    put64(h + 136, raw ? kHdr : P->off_cb);
+    put64(h + 144, raw ? kHdr : P->off_ch);
+    put64(h + 152, raw ? kHdr : P->off_bs);
+    put64(h + 160, raw ? kHdr : P->off_hd);
+    put64(h + 168, raw ? kHdr : P->off_tl);
+    put64(h + 176, P->total);
+  }
+  __syncthreads();
+  if (tid < (int)kHdr / 4) ((uint32_t*)A.out)[tid] = ((uint32_t*)h)[tid];
+  if (P->raw) return;
+  // codebook section: (u16 symbol, u8 length) sorted by symbol
+  const uint32_t nsym = 1u << P->m;
+  const uint32_t per = (nsym + 255) / 256;
+  const uint32_t lo = min(nsym, tid * per), hi = min(nsym, lo + per);
+  uint32_t cnt = 0;
+  for (uint32_t q = lo; q < hi; q++) cnt += A.len[q] != 0;
+  uint32_t pos = block_exscan<256, uint32_t>(cnt, red, nullptr);
+  uint8_t* cb = A.out + P->off_cb;
+  for (uint32_t q = lo; q < hi; q++) {
+    const uint8_t l = A.len[q];
+    if (!l) continue;
+    cb[3 * pos + 0] = (uint8_t)(q & 0xFF);
+    cb[3 * pos + 1] = (uint8_t)(q >> 8);
+    cb[3 * pos + 2] = l;
+    pos++;
+  }
+}
+
+template <typename T>
+__global__ void raw_copy_kernel(const T* __restrict__ x, uint8_t* out, uint64_t n, const DevPlan* P) {
+  if (P->status || !P->raw) return;
+  const uint64_t bytes = n * sizeof(T);
+  uint8_t* dst = out + kHdr;
+  const uint8_t* src = (const uint8_t*)x;
+  const uint64_t nv = bytes / 16;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += (uint64_t)gridDim.x * blockDim.x)
+    ((uint4*)dst)[i] = ((const uint4*)src)[i];
+  for (uint64_t i = nv * 16 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < bytes;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// Final status/size words for the asynchronous entry point.
+__global__ void finish_kernel(const DevPlan* P, uint64_t* d_size, int32_t* d_status) {
+  if (threadIdx.x) return;
+  if (d_status) *d_status = P->status;
+  if (d_size) *d_size = P->status ? 0 : P->total;
+}
+
+// =================================================================== decode
+struct DecTables {
+  uint32_t lut[4096];       // (len << 16) | sym for codes of length <= 12, 0 if longer
+  uint32_t first[32], count[32], start[32];
+  uint32_t nsorted;
+};
+constexpr int kLutBits = 12;
+
+// Decode tables from the codebook section; checks symbols strictly
+// increasing and the Kraft condition of the canonical code.
+__global__ void __launch_bounds__(1024) dectab_kernel(const uint8_t* comp, uint64_t off_cb, uint32_t n_used,
+                                                      uint32_t m, DecTables* D, uint64_t* gkeys,
+                                                      uint32_t* sorted_syms, DevPlan* P) {
+  __shared__ uint64_t s_keys[4096];
+  __shared__ uint32_t s_cnt[32], s_first[32], s_start[32];
+  __shared__ int s_bad;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_bad = 0;
+  if (tid < 32) s_cnt[tid] = 0;
+  for (int i = tid; i < 4096; i += 1024) D->lut[i] = 0;
+  __syncthreads();
+  const uint32_t nsym = 1u << m;
+  if (n_used == 0 || n_used > nsym) {
+    if (tid == 0) set_status(P, SZ_ECORRUPT);
+    return;
+  }
+  uint32_t np2 = 1;
+  while (np2 < n_used) np2 <<= 1;
+  uint64_t* K = (np2 <= 4096) ? s_keys : gkeys;
+  for (uint32_t e = tid; e < np2; e += 1024) {
+    if (e < n_used) {
+      const uint8_t* b = comp + off_cb + 3ull * e;
+      const uint32_t sym = b[0] | (b[1] << 8);
+      const uint32_t l = b[2];
+      if (sym >= nsym || l == 0 || l > kLmax) s_bad = 1;
+      if (e > 0) {
+        const uint8_t* pb = b - 3;
+        if ((uint32_t)(pb[0] | (pb[1] << 8)) >= sym) s_bad = 1;
+      }
+      K[e] = ((uint64_t)l << 16) | sym;
+      if (l >= 1 && l <= kLmax) atomicAdd(&s_cnt[l], 1u);
+    } else {
+      K[e] = ~0ull;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t code = 0;
+    uint32_t start = 0;
+    for (int l = 1; l <= kLmax; l++) {
+      s_first[l] = (uint32_t)code;
+      s_start[l] = start;
+      if (code + s_cnt[l] > (1ull << l)) s_bad = 1;
+      code = (code + s_cnt[l]) << 1;
+      start += s_cnt[l];
+    }
+    for (int l = 0; l < 32; l++) {
+      D->first[l] = (l >= 1 && l <= kLmax) ? s_first[l] : 0;
+      D->count[l] = s_cnt[l];
+      D->start[l] = (l >= 1 && l <= kLmax) ? s_start[l] : 0;
+    }
+    D->nsorted = n_used;
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) set_status(P, SZ_ECORRUPT);
+    return;
+  }
+  bitonic_sort<1024>(K, np2);
+  for (uint32_t v = tid; v < n_used; v += 1024) {
+    const uint32_t sym = (uint32_t)(K[v] & 0xFFFF);
+    const uint32_t l = (uint32_t)(K[v] >> 16);
+    sorted_syms[v] = sym;
+    if (l <= (uint32_t)kLutBits) {
+      const uint32_t code = s_first[l] + (v - s_start[l]);
+      const uint32_t a = code << (kLutBits - l), b = (code + 1) << (kLutBits - l);
+      for (uint32_t q = a; q < b; q++) D->lut[q] = (l << 16) | sym;
+    }
+  }
+}
+
+// K8: one lane per chunk decodes its symbols sequentially from the chunk's
+// bit offset; the canonical code is resolved by a 12-bit table in LDS with a
+// first-code-per-length fallback for longer codes.
+template <typename CT>
+__global__ void __launch_bounds__(256) decode_kernel(const uint8_t* __restrict__ comp, uint64_t off_bs,
+                                                     uint64_t nwords, uint64_t n, uint32_t C, uint64_t n_chunks,
+                                                     const uint32_t* cbits, const uint64_t* boff,
+                                                     const DecTables* D, const uint32_t* sorted_syms,
+                                                     CT* codes, uint32_t* segcnt, int64_t X, int64_t Bx,
+                                                     int32_t nbx, int ndim, DevPlan* P) {
+  __shared__ uint32_t lut[4096];
+  __shared__ uint32_t s_first[32], s_count[32], s_start[32];
+  for (int i = threadIdx.x; i < 4096; i += 256) lut[i] = D->lut[i];
+  if (threadIdx.x < 32) {
+    s_first[threadIdx.x] = D->first[threadIdx.x];
+    s_count[threadIdx.x] = D->count[threadIdx.x];
+    s_start[threadIdx.x] = D->start[threadIdx.x];
+  }
+  __syncthreads();
+  if (P->status) return;
+  const uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= n_chunks) return;
+  const uint32_t* words = (const uint32_t*)(comp + off_bs);
+  uint64_t pos = boff[c];
+  const uint64_t end = pos + cbits[c];
+  const uint64_t i0 = c * C, i1 = min(n, i0 + C);
+  // bit buffer: `buf` holds `nb` valid bits MSB-aligned
+  uint64_t wi = pos >> 5;
+  uint64_t buf = 0;
+  int nb = 0;
+  {
+    const uint32_t w0 = (wi < nwords) ? words[wi] : 0u;
+    buf = (uint64_t)w0 << 32;
+    buf <<= (pos & 31);
+    nb = 32 - (int)(pos & 31);
+    wi++;
+  }
+  uint32_t pack = 0;
+  int npack = 0;
+  constexpr int PER = 4 / sizeof(CT);
+  bool bad = false;
+  for (uint64_t i = i0; i < i1; i++) {
+    if (nb < 32) {
+      const uint32_t w = (wi < nwords) ? words[wi] : 0u;
+      buf |= (uint64_t)w << (32 - nb);
+      nb += 32;
+      wi++;
+    }
+    const uint32_t top = (uint32_t)(buf >> (64 - kLutBits));
+    uint32_t e = lut[top];
+    uint32_t sym, l;
+    if (e) {
+      sym = e & 0xFFFF;
+      l = e >> 16;
+    } else {
+      const uint32_t v27 = (uint32_t)(buf >> (64 - kLmax));
+      l = 0;
+      sym = 0;
+      for (int q = kLutBits + 1; q <= kLmax; q++) {
+        const uint32_t code = v27 >> (kLmax - q);
+        if (s_count[q] && code >= s_first[q] && code - s_first[q] < s_count[q]) {
+          l = q;
+          sym = sorted_syms[s_start[q] + (code - s_first[q])];
+          break;
+        }
+      }
+      if (!l) {
+        bad = true;
+        break;
+      }
+    }
+    buf <<= l;
+    nb -= (int)l;
+    pos += l;
+    pack |= sym << (8 * sizeof(CT) * npack);
+    if (++npack == PER) {
+      ((uint32_t*)codes)[(i - (PER - 1)) / PER] = pack;
+      pack = 0;
+      npack = 0;
+    }
+    if (sym == 0) {
+      uint64_t seg;
+      if (ndim == 1) {
+        seg = i / (uint64_t)Bx;
+      } else {
+        const uint64_t row = i / (uint64_t)X;
+        seg = row * nbx + (i % (uint64_t)X) / (uint64_t)Bx;
+      }
+      atomicAdd(&segcnt[seg], 1u);
+    }
+  }
+  if (!bad && npack) {
+    // ragged tail of the array: write the remaining codes one by one
+    for (int q = 0; q < npack; q++) codes[i1 - npack + q] = (CT)((pack >> (8 * sizeof(CT) * q)) & ((1u << (8 * sizeof(CT))) - 1));
+  }
+  if (bad || pos != end) set_status(P, SZ_ECORRUPT);
+}
+
+// K9a: kept-bit count of every unpredictable value, summed per group of 1024.
+template <typename T>
+__global__ void __launch_bounds__(1024) unpred_sums_kernel(const uint8_t* comp, uint64_t off_hd, uint64_t hd_words,
+                                                           uint64_t U, uint64_t ebT_bits, uint32_t* rsum,
+                                                           const DevPlan* P) {
+  constexpr int HB = 1 + FTr<T>::EXPB, MANT = FTr<T>::MANT, EMAX = FTr<T>::EMAX;
+  __shared__ uint32_t red[16];
+  if (P->status) return;
+  const uint64_t j = (uint64_t)blockIdx.x * 1024 + threadIdx.x;
+  uint32_t r = 0;
+  if (j < U) {
+    const uint64_t head = read_bits((const uint32_t*)(comp + off_hd), hd_words, j * HB, HB);
+    const int e = (int)(head & EMAX);
+    const int e_eb = (int)((ebT_bits >> MANT) & (uint64_t)EMAX);
+    if (e_eb == 0 || e == EMAX) r = MANT;
+    else if (e == 0 || e < e_eb) r = 0;
+    else r = (uint32_t)min(e - e_eb, MANT);
+  }
+  r = block_sum<1024, uint32_t>(r, red);
+  if (threadIdx.x == 0) rsum[blockIdx.x] = r;
+}
+
+// K9b: rebuild each unpredictable value from its head and kept tail bits.
+template <typename T>
+__global__ void __launch_bounds__(1024) unpred_values_kernel(const uint8_t* comp, uint64_t off_hd, uint64_t hd_words,
+                                                             uint64_t off_tl, uint64_t tl_words, uint64_t U,
+                                                             uint64_t ebT_bits, const uint64_t* roff,
+                                                             uint64_t tail_bits, T* vals, DevPlan* P) {
+  using UT = typename FTr<T>::U;
+  constexpr int HB = 1 + FTr<T>::EXPB, MANT = FTr<T>::MANT, EMAX = FTr<T>::EMAX;
+  __shared__ uint64_t red[16];
+  if (P->status) return;
+  const uint64_t j = (uint64_t)blockIdx.x * 1024 + threadIdx.x;
+  uint64_t head = 0;
+  int r = 0;
+  if (j < U) {
+    head = read_bits((const uint32_t*)(comp + off_hd), hd_words, j * HB, HB);
+    const int e = (int)(head & EMAX);
+    const int e_eb = (int)((ebT_bits >> MANT) & (uint64_t)EMAX);
+    if (e_eb == 0 || e == EMAX) r = MANT;
+    else if (e == 0 || e < e_eb) r = 0;
+    else r = min(e - e_eb, MANT);
+  }
+  uint64_t tot;
+  const uint64_t pos = roff[blockIdx.x] + block_exscan<1024, uint64_t>((uint64_t)r, red, &tot);
+  if (j < U) {
+    const uint64_t tail = r ? read_bits((const uint32_t*)(comp + off_tl), tl_words, pos, r) : 0;
+    const UT u = ((UT)head << MANT) | ((UT)tail << (MANT - r));
+    vals[j] = bits_to<T>(u);
+    if (j == U - 1 && pos + r != tail_bits) set_status(P, SZ_ECORRUPT);
+  }
+}
+
+__global__ void check_total_kernel(const uint64_t* got, uint64_t want, DevPlan* P) {
+  if (threadIdx.x == 0 && *got != want) set_status(P, SZ_ECORRUPT);
+}
+
+}  // namespace szh

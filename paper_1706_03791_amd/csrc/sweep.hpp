@@ -1,0 +1,556 @@
+// Wavefront sweep of the multilayer predictor (arXiv 1706.03791, Sec. III-A,
+// Eq. predmodel) with error-controlled quantization (Sec. IV-A) and the
+// per-point loop of Algorithm 1, for gfx950.
+//
+// Every point is predicted from already *decompressed* neighbours, so the
+// loop carries a dependence along every axis.  The sweep keeps the exact
+// sequential result by processing point (z, y, x) at step x + s(z, y): a
+// workgroup owns a tile of RZ x RY rows (a row is one (z, y) line along the
+// contiguous X axis) and row (rz, ry) of the tile lags by s = rz + ry steps,
+// so all neighbours (z-a, y-b, x-c) were produced at strictly earlier steps.
+// Decompressed values live in an LDS ring of R slots along X; rows owned by
+// the neighbouring tiles ("halo rows") are copied into the same ring from a
+// global array that those tiles publish group by group (progress flags with
+// agent-scope release/acquire).  Tiles are claimed through an atomic ticket
+// in dependence order, so every tile a workgroup waits on is already running.
+//
+// Input and output rows stream through per-row LDS rings in aligned chunks of
+// kG elements, loaded and stored cooperatively (several lanes per row) so a
+// wave instruction touches few cache lines.  The arithmetic of one point is
+// the sequence of IEEE operations fixed by the format (no contraction: the
+// library is compiled with -ffp-contract=off).
+#pragma once
+
+#include "common.hpp"
+
+namespace szh {
+
+template <typename T> struct FTr;
+template <> struct FTr<float> {
+  using U = uint32_t;
+  static constexpr int MANT = 23, EXPB = 8, EMAX = 255;
+};
+template <> struct FTr<double> {
+  using U = uint64_t;
+  static constexpr int MANT = 52, EXPB = 11, EMAX = 2047;
+};
+
+constexpr int ipow(int b, int e) {
+  int r = 1;
+  for (int i = 0; i < e; i++) r *= b;
+  return r;
+}
+constexpr int binom(int n, int k) {
+  int r = 1;
+  for (int i = 1; i <= k; i++) r = r * (n - k + i) / i;
+  return r;
+}
+
+// Offsets k = (a, b, c) along (z, y, x) and coefficients
+// -prod_j (-1)^{k_j} C(n, k_j) of Eq. predmodel, in lexicographic order of k
+// with the slowest dimension most significant.
+template <int DIM, int NL>
+struct Terms {
+  static constexpr int N = ipow(NL + 1, DIM) - 1;
+  int a[N], b[N], c[N], coef[N];
+  constexpr Terms() : a(), b(), c(), coef() {
+    int t = 0;
+    for (int idx = 1; idx < ipow(NL + 1, DIM); idx++) {
+      int k[3] = {0, 0, 0};
+      int rem = idx;
+      for (int d = 2; d >= 3 - DIM; d--) {
+        k[d] = rem % (NL + 1);
+        rem /= (NL + 1);
+      }
+      int prod = 1;
+      for (int d = 3 - DIM; d < 3; d++) {
+        int bn = binom(NL, k[d]);
+        prod *= (k[d] & 1) ? -bn : bn;
+      }
+      a[t] = k[0];
+      b[t] = k[1];
+      c[t] = k[2];
+      coef[t] = -prod;
+      t++;
+    }
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ T bits_to(typename FTr<T>::U u) {
+  return __builtin_bit_cast(T, u);
+}
+template <typename T>
+__device__ __forceinline__ typename FTr<T>::U to_bits(T v) {
+  return __builtin_bit_cast(typename FTr<T>::U, v);
+}
+
+// Reduced binary representation of an unpredictable value: sign, exponent
+// and the top e(x) - e(eb) mantissa bits (zero when the value's exponent is
+// below the bound's; everything when the bound is zero or subnormal, or the
+// value is Inf/NaN).
+template <typename T>
+__device__ __forceinline__ T truncate_unpred(T x, typename FTr<T>::U ebT_bits) {
+  using U = typename FTr<T>::U;
+  constexpr int MANT = FTr<T>::MANT, EXPB = FTr<T>::EXPB, EMAX = FTr<T>::EMAX;
+  const U u = to_bits<T>(x);
+  const int e = (int)((u >> MANT) & (U)EMAX);
+  const int e_eb = (int)((ebT_bits >> MANT) & (U)EMAX);
+  if (e_eb == 0 || e == EMAX) return x;
+  if (e == 0 || e < e_eb) return bits_to<T>((u >> (MANT + EXPB)) << (MANT + EXPB));
+  int r = e - e_eb;
+  if (r >= MANT) return x;
+  const U mask = ~((((U)1) << (MANT - r)) - 1);
+  return bits_to<T>(u & mask);
+}
+
+struct SweepArgs {
+  Geom g;
+  const void* x;          // compress: input field
+  void* codes;            // compress: output codes; decompress: input codes
+  void* xo;               // compress: halo scratch; decompress: output field
+  const void* uvals;      // decompress: unpredictable values, raster order
+  const uint64_t* useg;   // decompress: first unpredictable index of each row segment
+  uint64_t n_unpred;
+  uint32_t* hist;         // compress: 2^m bins
+  uint32_t* progress;     // per tile: completed steps
+  uint32_t* ticket;
+  DevPlan* plan;
+  uint32_t pass2;         // adaptive-m second sweep: skip unless plan->rerun
+  uint32_t export_all;    // debug: store every decompressed value to xo
+};
+
+constexpr uint32_t kDone = 0xFFFFFFFFu;
+// About 2^21 polls of a progress flag (each one a device-scope load plus a
+// short sleep, roughly 1-2 us) before a wait is declared stalled.
+constexpr uint32_t kSpinLimit = 1u << 21;
+constexpr int32_t kStatusStalled = -7;
+constexpr int kHistWin = 1024;
+
+__device__ __forceinline__ void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+template <int NL>
+constexpr int ring_slots() {
+  return (3 * NL + 1 <= 4) ? 4 : ((3 * NL + 1 <= 8) ? 8 : 16);
+}
+
+template <typename T, typename CT, int DIM, int NL, bool COMP, int RZ, int RY>
+__global__ void __launch_bounds__(RZ * RY) sweep_kernel(SweepArgs A) {
+  using U = typename FTr<T>::U;
+  constexpr int NT = RZ * RY;
+  constexpr int R = ring_slots<NL>();
+  constexpr int HZ = (DIM == 3) ? NL : 0;
+  constexpr int HY = (DIM >= 2) ? NL : 0;
+  constexpr int XZ = RZ + HZ, XY = RY + HY;
+  constexpr Terms<DIM, NL> TT{};
+  constexpr int NTERM = Terms<DIM, NL>::N;
+  // halo rows: z-halo NL x (RY + NL), y-halo RZ x NL
+  constexpr int H = (DIM == 3) ? (NL * (RY + NL) + RZ * NL) : ((DIM == 2) ? NL : 0);
+  static_assert(H <= NT, "halo rows exceed threads");
+  // lanes per row for 16-byte chunk traffic
+  constexpr int XLPR = (kG * (int)sizeof(T)) / 16;   // x / x' chunks
+  constexpr int CLPR = (kG * (int)sizeof(CT)) / 16;  // code chunks
+  constexpr int XEPL = 16 / (int)sizeof(T);
+  constexpr int CEPL = 16 / (int)sizeof(CT);
+
+  __shared__ T xring[R][XZ][XY];
+  __shared__ __align__(16) T vring[NT][kRing];   // compress: input x; decompress: output x'
+  __shared__ __align__(16) CT cring[NT][kRing];  // codes (out for compress, in for decompress)
+  __shared__ uint32_t hl[COMP ? kHistWin : 1];
+  __shared__ int s_tile;
+
+  DevPlan* P = A.plan;
+  if (P->status != 0) return;
+  if (A.pass2 && !P->rerun) return;
+
+  const int tid = threadIdx.x;
+  const int rz = (DIM == 3) ? tid / RY : 0;
+  const int ry = (DIM == 3) ? tid % RY : tid;
+  const int s = (DIM == 1) ? 0 : rz + ry;
+  const Geom& g = A.g;
+
+  if (tid == 0) s_tile = (int)atomicAdd(A.ticket, 1u);
+  for (int i = tid; i < R * XZ * XY; i += NT) (&xring[0][0][0])[i] = T(0);
+  if (COMP)
+    for (int i = tid; i < kHistWin; i += NT) hl[i] = 0;
+  __syncthreads();
+  const int tile = s_tile;
+
+  // ---- tile geometry
+  int64_t zb0 = 0, zb1 = 1, yb0 = 0, yb1 = 1, xb0 = 0, xb1 = 0, z0 = 0, y0 = 0;
+  int pred_z = -1, pred_y = -1;
+  if (DIM >= 2) {
+    const int per_blk = g.tz_per_blk * g.ty_per_blk;
+    const int bi = tile / per_blk;
+    const int rem = tile % per_blk;
+    const int tzt = rem / g.ty_per_blk, tyt = rem % g.ty_per_blk;
+    const int b0 = bi / (g.nblk[1] * g.nblk[2]);
+    const int b1 = (bi / g.nblk[2]) % g.nblk[1];
+    const int b2 = bi % g.nblk[2];
+    zb0 = (int64_t)b0 * g.blk[0];
+    zb1 = min(zb0 + g.blk[0], g.dims[0]);
+    yb0 = (int64_t)b1 * g.blk[1];
+    yb1 = min(yb0 + g.blk[1], g.dims[1]);
+    xb0 = (int64_t)b2 * g.blk[2];
+    xb1 = min(xb0 + g.blk[2], g.dims[2]);
+    z0 = zb0 + (int64_t)tzt * RZ;
+    y0 = yb0 + (int64_t)tyt * RY;
+    if (DIM == 3 && tzt > 0) pred_z = tile - g.ty_per_blk;
+    if (tyt > 0) pred_y = tile - 1;
+    if (z0 >= zb1 || y0 >= yb1) {  // empty tile past a ragged block edge
+      if (tid == 0) __hip_atomic_store(&A.progress[tile], kDone, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+  }
+  const int64_t Xd = g.dims[2], Yd = g.dims[1];
+
+  // per-row geometry (for any row index r of the tile)
+  auto row_info = [&](int r, int64_t& base, int64_t& xlen, int& sk, bool& ok) {
+    if (DIM == 1) {
+      const int64_t id = (int64_t)tile * NT + r;
+      const int64_t nb = (g.n + g.blk[2] - 1) / g.blk[2];
+      ok = id < nb;
+      base = id * g.blk[2];
+      xlen = ok ? min(g.blk[2], g.n - base) : 0;
+      sk = 0;
+    } else {
+      const int rrz = (DIM == 3) ? r / RY : 0;
+      const int rry = (DIM == 3) ? r % RY : r;
+      const int64_t zr = (DIM == 3) ? z0 + rrz : 0;
+      const int64_t yr = y0 + rry;
+      ok = zr < zb1 && yr < yb1;
+      base = (zr * Yd + yr) * Xd + xb0;
+      xlen = xb1 - xb0;
+      sk = rrz + rry;
+    }
+  };
+
+  int64_t base, xlen;
+  int sk_unused;
+  bool row_ok;
+  row_info(tid, base, xlen, sk_unused, row_ok);
+  const int64_t xlen_tile = (DIM == 1) ? g.blk[2] : (xb1 - xb0);
+  const int span = (DIM == 1) ? 0 : (RZ - 1) + (RY - 1);
+  const int nsteps = (int)xlen_tile + span;
+  const int ngroups = (nsteps + kG - 1) / kG;
+
+  const uint32_t m = P->m;
+  const int32_t half = 1 << (m - 1);
+  const T ebT = bits_to<T>((U)P->ebT_bits);
+  const T twoeb = bits_to<T>((U)P->twoeb_bits);
+  const T inv2eb = bits_to<T>((U)P->inv2eb_bits);
+  const U ebT_bits = (U)P->ebT_bits;
+
+  const T* __restrict__ xin = (const T*)A.x;
+  CT* __restrict__ cglob = (CT*)A.codes;
+  T* __restrict__ xo = (T*)A.xo;
+  const int64_t ntot = g.n;
+
+  // ---- halo ownership
+  bool h_own = false;
+  int hrz = 0, hry = 0, hs = 0;
+  bool h_in = false;
+  int64_t h_base = 0;
+  if (DIM >= 2 && tid < H) {
+    h_own = true;
+    if (DIM == 3) {
+      if (tid < NL * (RY + NL)) {
+        hrz = -(1 + tid / (RY + NL));
+        hry = tid % (RY + NL) - NL;
+      } else {
+        const int q = tid - NL * (RY + NL);
+        hrz = q / NL;
+        hry = -(1 + q % NL);
+      }
+    } else {
+      hrz = 0;
+      hry = -(1 + tid);
+    }
+    hs = hrz + hry;
+    const int64_t zh = (DIM == 3) ? z0 + hrz : 0;
+    const int64_t yh = y0 + hry;
+    h_in = zh >= zb0 && zh < zb1 && yh >= yb0 && yh < yb1;
+    h_base = (zh * Yd + yh) * Xd + xb0;
+  }
+  const bool exporter = (DIM == 3) ? (rz >= RZ - NL || ry >= RY - NL) : ((DIM == 2) ? ry >= RY - NL : false);
+
+  T hv[kG], hn[kG];
+#pragma unroll
+  for (int i = 0; i < kG; i++) hv[i] = hn[i] = T(0);
+
+  auto wait_preds = [&](int grp) {
+    // halo values of group grp need z-pred step +RZ and y-pred step +RY
+    if (DIM == 1) return;
+    // Bounded wait: a tile only waits on tiles with smaller tickets, which
+    // are already resident, so the wait always ends; the spin limit turns a
+    // broken invariant into an error status instead of a hang (every tile
+    // then runs to completion and publishes, so all waiters drain).
+    if (tid == 0) {
+      const uint32_t last = (uint32_t)(grp * kG + kG);
+      const int preds[2] = {pred_z, pred_y};
+      const uint32_t needs[2] = {last + RZ, last + RY};
+      for (int q = 0; q < 2; q++) {
+        if (preds[q] < 0) continue;
+        uint32_t spins = 0;
+        while (__hip_atomic_load(&A.progress[preds[q]], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < needs[q]) {
+          if (__hip_atomic_load(&P->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+          if (++spins > kSpinLimit) {
+            atomicCAS(&P->status, 0, kStatusStalled);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+    }
+    __syncthreads();
+  };
+
+  auto load_halo = [&](int grp, T (&dst)[kG]) {
+    if (!h_own) return;
+#pragma unroll
+    for (int i = 0; i < kG; i++) {
+      const int64_t xl = (int64_t)grp * kG + i - hs;
+      dst[i] = (h_in && xl >= 0 && xl < xlen_tile) ? xo[h_base + xl] : T(0);
+    }
+  };
+
+  // ---- streamed chunks: register staging for the next group's input chunk
+  constexpr int LPR_IN = COMP ? XLPR : CLPR;
+  constexpr int EPL_IN = COMP ? XEPL : CEPL;
+  uint4 pre[LPR_IN];
+  bool pre_ok[LPR_IN];
+  int64_t pre_pos[LPR_IN];
+
+  // Issue loads of chunk q for the job's row (job j = i * NT + tid).
+  auto load_chunk_regs = [&](int grp) {
+#pragma unroll
+    for (int i = 0; i < LPR_IN; i++) {
+      const int j = i * NT + tid;
+      const int r = j / LPR_IN, part = j % LPR_IN;
+      int64_t rb, rl;
+      int rs;
+      bool rok;
+      row_info(r, rb, rl, rs, rok);
+      const int64_t hi = rb + (int64_t)grp * kG + (kG - 1) - rs;
+      const int64_t q = hi >> 4;  // kG == 16
+      const int64_t c0 = q * kG;
+      const bool overlap = rok && (c0 + kG > rb) && (c0 < rb + rl);
+      pre_ok[i] = overlap;
+      pre_pos[i] = c0 + part * EPL_IN;
+      pre[i] = make_uint4(0, 0, 0, 0);
+      if (overlap) {
+        const int64_t e0 = c0 + part * EPL_IN;
+        if (COMP) {
+          if (e0 + EPL_IN <= ntot) {
+            pre[i] = *(const uint4*)(xin + e0);
+          } else {
+            T tmp[XEPL];
+#pragma unroll
+            for (int e = 0; e < XEPL; e++) tmp[e] = (e0 + e < ntot) ? xin[e0 + e] : T(0);
+            pre[i] = *(uint4*)tmp;
+          }
+        } else {
+          pre[i] = *(const uint4*)(cglob + e0);  // code workspace is padded
+        }
+      }
+    }
+  };
+  auto store_chunk_ring = [&]() {
+#pragma unroll
+    for (int i = 0; i < LPR_IN; i++) {
+      if (!pre_ok[i]) continue;
+      const int j = i * NT + tid;
+      const int r = j / LPR_IN;
+      const int pos = (int)(pre_pos[i] & (kRing - 1));
+      if (COMP)
+        *(uint4*)&vring[r][pos] = pre[i];
+      else
+        *(uint4*)&cring[r][pos] = pre[i];
+    }
+  };
+
+  // Flush of completed output chunks (codes for compress, x' for decompress).
+  constexpr int LPR_OUT = COMP ? CLPR : XLPR;
+  constexpr int EPL_OUT = COMP ? CEPL : XEPL;
+  auto flush = [&](int grp, bool final_pass) {
+#pragma unroll
+    for (int i = 0; i < LPR_OUT; i++) {
+      const int j = i * NT + tid;
+      const int r = j / LPR_OUT, part = j % LPR_OUT;
+      int64_t rb, rl;
+      int rs;
+      bool rok;
+      row_info(r, rb, rl, rs, rok);
+      if (!rok) continue;
+      const int64_t hi = rb + (int64_t)grp * kG + (kG - 1) - rs;  // last raster index processed
+      int64_t q;
+      if (!final_pass) {
+        q = ((hi + 1) >> 4) - 1;
+      } else {
+        // the chunk holding the row's last element, unless already complete
+        const int64_t last = rb + rl - 1;
+        q = last >> 4;
+        const int64_t qdone = ((hi + 1) >> 4) - 1;
+        if (q <= qdone) continue;
+      }
+      const int64_t c0 = q * kG;
+      const int64_t lo_ok = rb, hi_ok = rb + rl;  // valid raster range of the row
+      if (c0 + kG <= lo_ok || c0 >= hi_ok) continue;
+      if (!final_pass && hi < rb) continue;
+      const int64_t e0 = c0 + part * EPL_OUT;
+      const int pos = (int)(e0 & (kRing - 1));
+      if (e0 >= lo_ok && e0 + EPL_OUT <= hi_ok) {
+        if (COMP)
+          *(uint4*)(cglob + e0) = *(const uint4*)&cring[r][pos];
+        else
+          *(uint4*)(xo + e0) = *(const uint4*)&vring[r][pos];
+      } else {
+        for (int e = 0; e < EPL_OUT; e++) {
+          const int64_t ix = e0 + e;
+          if (ix < lo_ok || ix >= hi_ok) continue;
+          if (COMP)
+            cglob[ix] = cring[r][(pos + e) & (kRing - 1)];
+          else
+            xo[ix] = vring[r][(pos + e) & (kRing - 1)];
+        }
+      }
+    }
+  };
+
+  // ---- decompress: queue of this row's unpredictable values
+  uint64_t uidx = 0;
+  T unext = T(0);
+  if (!COMP && row_ok) {
+    int64_t seg;
+    if (DIM == 1) {
+      seg = (int64_t)tile * NT + tid;
+    } else {
+      const int64_t zr = (DIM == 3) ? z0 + rz : 0;
+      const int64_t yr = y0 + ry;
+      seg = (zr * Yd + yr) * g.nblk[2] + xb0 / g.blk[2];
+    }
+    uidx = A.useg[seg];
+    unext = (uidx < A.n_unpred) ? ((const T*)A.uvals)[uidx] : T(0);
+  }
+
+  uint32_t cnt_center = 0, cnt_zero = 0;
+  const int32_t wbase = (COMP && (1 << m) > kHistWin) ? half - kHistWin / 2 : 0;
+
+  // ---- prologue: group 0 halo and the two chunks group 0 may touch
+  wait_preds(0);
+  load_halo(0, hv);
+  // Halo rows with negative skew start before step 0: their first -hs cells
+  // belong to steps that never run, so they are written here.
+  if (DIM >= 2 && h_own && hs < 0) {
+    for (int xl = 0; xl < -hs; xl++) {
+      const T v = (h_in && xl < xlen_tile) ? xo[h_base + xl] : T(0);
+      xring[xl & (R - 1)][hrz + HZ][hry + HY] = v;
+    }
+  }
+  load_chunk_regs(-1);
+  store_chunk_ring();
+  load_chunk_regs(0);
+  store_chunk_ring();
+  __syncthreads();
+
+  for (int grp = 0; grp < ngroups; grp++) {
+    const bool more = grp + 1 < ngroups;
+    if (more) {
+      wait_preds(grp + 1);
+      load_halo(grp + 1, hn);
+      load_chunk_regs(grp + 1);
+    }
+#pragma unroll
+    for (int i = 0; i < kG; i++) {
+      const int sigma = grp * kG + i;
+      const int xl = sigma - s;
+      const bool act = row_ok && xl >= 0 && xl < xlen;
+      if (DIM >= 2 && h_own) xring[(sigma - hs) & (R - 1)][hrz + HZ][hry + HY] = hv[i];
+      T p = T(0);
+#pragma unroll
+      for (int t = 0; t < NTERM; t++) {
+        const T v = xring[(xl - TT.c[t]) & (R - 1)][rz - TT.a[t] + HZ][ry - TT.b[t] + HY];
+        p = p + T(TT.coef[t]) * v;
+      }
+      T xq = T(0);
+      const int rpos = (int)((base + xl) & (kRing - 1));
+      if (act) {
+        if (COMP) {
+          const T x = vring[tid][rpos];
+          const T t = (x - p) * inv2eb;
+          uint32_t code = 0;
+          if (fabs(t) < T(half)) {
+            const int k = (int)rint(t);
+            if (k <= half - 1 && k >= -(half - 1)) {
+              const T xqq = p + T(k) * twoeb;
+              if (fabs(x - xqq) < ebT) {
+                code = (uint32_t)(k + half);
+                xq = xqq;
+              }
+            }
+          }
+          if (code == 0) {
+            xq = truncate_unpred<T>(x, ebT_bits);
+            cnt_zero++;
+          } else if ((int32_t)code == half) {
+            cnt_center++;
+          } else {
+            const int32_t w = (int32_t)code - wbase;
+            if (w >= 0 && w < kHistWin)
+              atomicAdd(&hl[w], 1u);
+            else
+              atomicAdd(&A.hist[code], 1u);
+          }
+          cring[tid][rpos] = (CT)code;
+        } else {
+          const int32_t code = (int32_t)cring[tid][rpos];
+          if (code != 0) {
+            xq = p + T(code - half) * twoeb;
+          } else {
+            xq = unext;
+            uidx++;
+            unext = (uidx < A.n_unpred) ? ((const T*)A.uvals)[uidx] : T(0);
+          }
+          vring[tid][rpos] = xq;
+        }
+        if (exporter || (COMP && A.export_all)) xo[base + xl] = xq;
+      }
+      xring[xl & (R - 1)][rz + HZ][ry + HY] = xq;
+      if (DIM >= 2) __syncthreads();
+    }
+    // Group end.  The exports of this group must be complete before the
+    // progress flag moves; the next input chunk replaces the ring half that
+    // this group finished reading; completed output chunks are flushed after
+    // the flag so their stores never delay a successor tile.  (1-D rows
+    // share no values, so only here do all waves meet before the rings are
+    // refilled by other lanes.)
+    if (DIM == 1) __syncthreads();
+    wait_vm();
+    if (more) store_chunk_ring();
+#pragma unroll
+    for (int i = 0; i < kG; i++) hv[i] = hn[i];
+    __syncthreads();
+    if (DIM >= 2 && tid == 0) {
+      const uint32_t done = more ? (uint32_t)((grp + 1) * kG) : kDone;
+      __hip_atomic_store(&A.progress[tile], done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    flush(grp, false);
+    if (!more) flush(grp, true);
+  }
+
+  if (COMP) {
+    if (cnt_zero) {
+      if (0 - wbase >= 0 && 0 - wbase < kHistWin)
+        atomicAdd(&hl[0 - wbase], cnt_zero);
+      else
+        atomicAdd(&A.hist[0], cnt_zero);
+    }
+    if (cnt_center) atomicAdd(&hl[half - wbase], cnt_center);
+    __syncthreads();
+    const int nb = min(kHistWin, 1 << m);
+    for (int i = tid; i < nb; i += NT)
+      if (hl[i]) atomicAdd(&A.hist[wbase + i], hl[i]);
+  }
+}
+
+}  // namespace szh

@@ -1,0 +1,59 @@
+// Host-side dispatch of the sweep kernel instantiations.  Each element type
+// and dimensionality lives in its own translation unit so the 96 kernel
+// variants compile in parallel.
+#pragma once
+
+#include "common.hpp"
+#include "sweep.hpp"
+
+namespace szh {
+
+// Tile shapes (rows per workgroup) per element type and dimensionality.
+template <typename T, int DIM> struct TileShape;
+template <> struct TileShape<float, 3> { static constexpr int RZ = 16, RY = 16; };
+template <> struct TileShape<double, 3> { static constexpr int RZ = 8, RY = 16; };
+template <> struct TileShape<float, 2> { static constexpr int RZ = 1, RY = 256; };
+template <> struct TileShape<double, 2> { static constexpr int RZ = 1, RY = 128; };
+template <> struct TileShape<float, 1> { static constexpr int RZ = 1, RY = 256; };
+template <> struct TileShape<double, 1> { static constexpr int RZ = 1, RY = 128; };
+
+template <typename T, int DIM, int NL, bool COMP>
+inline hipError_t launch_one(int cw, const SweepArgs& a, int grid, hipStream_t st) {
+  constexpr int RZ = TileShape<T, DIM>::RZ, RY = TileShape<T, DIM>::RY;
+  if (cw == 1)
+    hipLaunchKernelGGL((sweep_kernel<T, uint8_t, DIM, NL, COMP, RZ, RY>), dim3(grid), dim3(RZ * RY), 0, st, a);
+  else
+    hipLaunchKernelGGL((sweep_kernel<T, uint16_t, DIM, NL, COMP, RZ, RY>), dim3(grid), dim3(RZ * RY), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename T, int DIM>
+inline hipError_t launch_sweep_t(int nl, bool comp, int cw, const SweepArgs& a, int grid, hipStream_t st) {
+  switch (nl) {
+    case 1: return comp ? launch_one<T, DIM, 1, true>(cw, a, grid, st) : launch_one<T, DIM, 1, false>(cw, a, grid, st);
+    case 2: return comp ? launch_one<T, DIM, 2, true>(cw, a, grid, st) : launch_one<T, DIM, 2, false>(cw, a, grid, st);
+    case 3: return comp ? launch_one<T, DIM, 3, true>(cw, a, grid, st) : launch_one<T, DIM, 3, false>(cw, a, grid, st);
+    case 4: return comp ? launch_one<T, DIM, 4, true>(cw, a, grid, st) : launch_one<T, DIM, 4, false>(cw, a, grid, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Defined in sweep_<type>_d<dim>.hip
+hipError_t sweep_f32_d1(int nl, bool comp, int cw, const SweepArgs& a, int grid, hipStream_t st);
+hipError_t sweep_f32_d2(int nl, bool comp, int cw, const SweepArgs& a, int grid, hipStream_t st);
+hipError_t sweep_f32_d3(int nl, bool comp, int cw, const SweepArgs& a, int grid, hipStream_t st);
+hipError_t sweep_f64_d1(int nl, bool comp, int cw, const SweepArgs& a, int grid, hipStream_t st);
+hipError_t sweep_f64_d2(int nl, bool comp, int cw, const SweepArgs& a, int grid, hipStream_t st);
+hipError_t sweep_f64_d3(int nl, bool comp, int cw, const SweepArgs& a, int grid, hipStream_t st);
+
+inline void tile_shape(int dtype, int ndim, int& rz, int& ry) {
+  if (dtype == SZ_F32) {
+    rz = ndim == 3 ? TileShape<float, 3>::RZ : 1;
+    ry = ndim == 3 ? TileShape<float, 3>::RY : (ndim == 2 ? TileShape<float, 2>::RY : TileShape<float, 1>::RY);
+  } else {
+    rz = ndim == 3 ? TileShape<double, 3>::RZ : 1;
+    ry = ndim == 3 ? TileShape<double, 3>::RY : (ndim == 2 ? TileShape<double, 2>::RY : TileShape<double, 1>::RY);
+  }
+}
+
+}  // namespace szh
