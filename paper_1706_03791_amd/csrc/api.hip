@@ -83,6 +83,9 @@ struct Layout {
   Geom g;
   int grid;        // sweep workgroups
   uint64_t nseg;   // row segments (decompress queues)
+  uint32_t ne;     // exporter rows per tile
+  uint32_t nsp;    // steps stored per exporter row
+  uint64_t xchg_bytes;
   double theta;
   uint64_t out_dims[3], out_block[3];
 };
@@ -152,6 +155,17 @@ int resolve(const sz_params* p, Layout& L) {
     L.nseg = (uint64_t)L.dims3[0] * L.dims3[1] * g.nblk[2];
   }
   L.grid = g.ntiles;
+  // exchange buffer of boundary rows: [tile][exporter row][step]
+  const int span = (L.ndim == 1) ? 0 : (rz - 1) + (ry - 1);
+  const uint64_t ngroups = ceil_div((uint64_t)L.blk3[2] + span, kG);
+  L.ne = (L.ndim == 3) ? (uint32_t)(L.nl * ry + (rz - L.nl) * L.nl) : (L.ndim == 2 ? (uint32_t)L.nl : 0);
+  L.nsp = (uint32_t)ceil_div(kG * ngroups + rz + ry + kG, kG) * kG;
+  L.xchg_bytes = (uint64_t)g.ntiles * L.ne * L.nsp * L.ts;
+  // Buffer-resource offsets are 32-bit: the exchange buffer and the input
+  // span of one tile must stay below 2 GiB.
+  const uint64_t tile_span = (L.ndim == 3) ? (uint64_t)rz * L.dims3[1] * L.dims3[2]
+                                           : (L.ndim == 2 ? (uint64_t)ry * L.dims3[2] : (uint64_t)ry * L.blk3[2]);
+  if (L.xchg_bytes >= 0x7FFFFF00ull || (tile_span + 64) * L.ts >= 0x7FFFFF00ull) return SZ_EINVAL;
   return SZ_OK;
 }
 
@@ -170,7 +184,8 @@ struct Carve {
 
 struct CompWs {
   uint8_t* codes;
-  void* xs;
+  void* xs;        // every recorded value (sz_quantize only)
+  void* xchg;
   uint32_t* hist;
   uint32_t* progress;
   uint32_t* ticket;
@@ -184,12 +199,13 @@ struct CompWs {
   uint32_t *gpar, *ganc, *gdep;
 };
 
-size_t carve_comp(const Layout& L, uint8_t* base, CompWs* W) {
+size_t carve_comp(const Layout& L, uint8_t* base, CompWs* W, bool keep_values = false) {
   Carve c{base};
   const uint64_t nt = ceil_div(L.n_chunks, 4096) + 1;
   CompWs w;
   w.codes = c.take<uint8_t>((L.n + 64) * L.cw);
-  w.xs = c.take<uint8_t>(L.n * L.ts);
+  w.xs = keep_values ? c.take<uint8_t>(L.n * L.ts) : nullptr;
+  w.xchg = c.take<uint8_t>(L.xchg_bytes + 64);
   w.hist = c.take<uint32_t>(65536 * 4);
   w.progress = c.take<uint32_t>((L.g.ntiles + 1) * 4);
   w.ticket = w.progress + L.g.ntiles;
@@ -263,10 +279,10 @@ template <typename T>
 int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const void* d_in, void* d_out, size_t cap,
                        hipStream_t st, bool debug_codes_only) {
   CompWs W;
-  const size_t need = carve_comp(L, nullptr, nullptr);
+  const size_t need = carve_comp(L, nullptr, nullptr, debug_codes_only);
   int rc = ensure_arena(ctx, need);
   if (rc) return rc;
-  carve_comp(L, (uint8_t*)ctx->arena, &W);
+  carve_comp(L, (uint8_t*)ctx->arena, &W, debug_codes_only);
   DevPlan* P = ctx->plan;
   const bool adaptive = L.m_req == 0;
   PlanInit I;
@@ -291,9 +307,13 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
   a.x = d_in;
   a.codes = W.codes;
   a.xo = W.xs;
+  a.xchg = W.xchg;
+  a.ne = L.ne;
+  a.nsp = L.nsp;
   a.uvals = nullptr;
   a.useg = nullptr;
   a.n_unpred = 0;
+  a.codes_cap = (uint64_t)L.n + 64;
   a.hist = W.hist;
   a.progress = W.progress;
   a.ticket = W.ticket;
@@ -492,6 +512,7 @@ struct DecWs {
   uint64_t *roff, *tsum_r;
   uint32_t* progress;
   uint32_t* ticket;
+  void* xchg;
 };
 
 size_t carve_dec(const Layout& L, uint64_t U, uint8_t* base, DecWs* W) {
@@ -514,6 +535,7 @@ size_t carve_dec(const Layout& L, uint64_t U, uint8_t* base, DecWs* W) {
   w.tsum_r = c.take<uint64_t>((ceil_div(ngr, 4096) + 1) * 8);
   w.progress = c.take<uint32_t>((L.g.ntiles + 1) * 4);
   w.ticket = w.progress + L.g.ntiles;
+  w.xchg = c.take<uint8_t>(L.xchg_bytes + 64);
   if (W) *W = w;
   return c.off + 256;
 }
@@ -589,9 +611,13 @@ int enqueue_decompress_t(sz_ctx* ctx, const Layout& L, const Hdr& h, const void*
   a.x = nullptr;
   a.codes = W.codes;
   a.xo = d_out;
+  a.xchg = W.xchg;
+  a.ne = L.ne;
+  a.nsp = L.nsp;
   a.uvals = W.uvals;
   a.useg = W.useg;
   a.n_unpred = U;
+  a.codes_cap = (uint64_t)L.n + 64;
   a.hist = nullptr;
   a.progress = W.progress;
   a.ticket = W.ticket;
@@ -739,7 +765,7 @@ int sz_quantize(sz_ctx* ctx, const sz_params* p, const void* d_in, uint16_t* d_c
                          : enqueue_compress_t<double>(ctx, L, &q, d_in, nullptr, 0, st, true);
   if (rc) return rc;
   CompWs W;
-  carve_comp(L, (uint8_t*)ctx->arena, &W);
+  carve_comp(L, (uint8_t*)ctx->arena, &W, true);
   HIPCHK(hipMemcpyAsync(d_codes, W.codes, (size_t)L.n * 2, hipMemcpyDeviceToDevice, st));
   if (d_xprime) HIPCHK(hipMemcpyAsync(d_xprime, W.xs, (size_t)L.n * L.ts, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(ctx->h_plan, ctx->plan, sizeof(DevPlan), hipMemcpyDeviceToHost, st));

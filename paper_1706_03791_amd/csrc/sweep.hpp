@@ -104,35 +104,115 @@ __device__ __forceinline__ T truncate_unpred(T x, typename FTr<T>::U ebT_bits) {
   return bits_to<T>(u & mask);
 }
 
+// The same truncation without branches (selects only), for the sweep's
+// inner loop; returns the bit pattern.
+template <typename T>
+__device__ __forceinline__ typename FTr<T>::U truncate_bits(typename FTr<T>::U u, int e_eb) {
+  using U = typename FTr<T>::U;
+  constexpr int MANT = FTr<T>::MANT, EXPB = FTr<T>::EXPB, EMAX = FTr<T>::EMAX;
+  const int e = (int)((u >> MANT) & (U)EMAX);
+  const int r = e - e_eb;
+  const bool keep = (e_eb == 0) | (e == EMAX) | (r >= MANT);
+  const bool zero = (e == 0) | (r < 0);
+  const int rc = r < 0 ? 0 : (r > MANT - 1 ? MANT - 1 : r);
+  const U mask = ~((((U)1) << (MANT - rc)) - 1);
+  const U sign = (u >> (MANT + EXPB)) << (MANT + EXPB);
+  return keep ? u : (zero ? sign : (u & mask));
+}
+
 struct SweepArgs {
   Geom g;
   const void* x;          // compress: input field
   void* codes;            // compress: output codes; decompress: input codes
-  void* xo;               // compress: halo scratch; decompress: output field
+  void* xo;               // compress: optional copy of every recorded value; decompress: output field
+  void* xchg;             // boundary rows published to successor tiles: [tile][row][step]
+  uint32_t ne;            // exporter rows per tile
+  uint32_t nsp;           // steps stored per exporter row (multiple of kG)
   const void* uvals;      // decompress: unpredictable values, raster order
   const uint64_t* useg;   // decompress: first unpredictable index of each row segment
   uint64_t n_unpred;
+  uint64_t codes_cap;     // decompress: elements in the code workspace
   uint32_t* hist;         // compress: 2^m bins
   uint32_t* progress;     // per tile: completed steps
   uint32_t* ticket;
   DevPlan* plan;
   uint32_t pass2;         // adaptive-m second sweep: skip unless plan->rerun
-  uint32_t export_all;    // debug: store every decompressed value to xo
+  uint32_t export_all;    // compress debug: store every recorded value to xo
 };
 
 constexpr uint32_t kDone = 0xFFFFFFFFu;
-// About 2^21 polls of a progress flag (each one a device-scope load plus a
-// short sleep, roughly 1-2 us) before a wait is declared stalled.
+// About 2^21 polls of a progress flag (each a device-scope load plus a short
+// sleep) before a wait is declared stalled.
 constexpr uint32_t kSpinLimit = 1u << 21;
 constexpr int32_t kStatusStalled = -7;
 constexpr int kHistWin = 1024;
+// Cache policy of exchange traffic: sc0|sc1 = device-coherent (bypasses the
+// per-CU cache and is coherent across the L2s of all XCDs), so a relaxed
+// flag store after s_waitcnt publishes the data without L2 writeback or
+// invalidation.
+constexpr int kCoherent = 17;
 
-__device__ __forceinline__ void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima), issued as
+// the builtin so the compiler's own wait tracking knows the loads are done.
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint64_t bytes) {
+  const uint64_t cap = 0x7FFFFFF0ull;
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)(bytes < cap ? bytes : cap), 0x00020000);
+}
+
+// Element i of a register array of 16-byte pieces, and the reverse packing.
+template <typename T>
+__device__ __forceinline__ T piece_elem(const uint4* a, int i) {
+  if constexpr (sizeof(T) == 4) {
+    const uint4 v = a[i >> 2];
+    const uint32_t w = (i & 3) == 0 ? v.x : (i & 3) == 1 ? v.y : (i & 3) == 2 ? v.z : v.w;
+    return __builtin_bit_cast(T, w);
+  } else {
+    const uint4 v = a[i >> 1];
+    const uint64_t w = (i & 1) ? (((uint64_t)v.w << 32) | v.z) : (((uint64_t)v.y << 32) | v.x);
+    return __builtin_bit_cast(T, w);
+  }
+}
+template <typename T>
+__device__ __forceinline__ uint4 pack_piece(const T* e, int j) {
+  if constexpr (sizeof(T) == 4) {
+    return make_uint4(__builtin_bit_cast(uint32_t, e[4 * j]), __builtin_bit_cast(uint32_t, e[4 * j + 1]),
+                      __builtin_bit_cast(uint32_t, e[4 * j + 2]), __builtin_bit_cast(uint32_t, e[4 * j + 3]));
+  } else {
+    const uint64_t a = __builtin_bit_cast(uint64_t, e[2 * j]), b = __builtin_bit_cast(uint64_t, e[2 * j + 1]);
+    return make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
+  }
+}
+template <typename T>
+__device__ __forceinline__ T load_coherent(__amdgpu_buffer_rsrc_t r, int byte_off) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 17));
+  else
+    return __builtin_bit_cast(T, (uint64_t)__builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 17));
+}
 
 template <int NL>
 constexpr int ring_slots() {
   return (3 * NL + 1 <= 4) ? 4 : ((3 * NL + 1 <= 8) ? 8 : 16);
 }
+
+// Rows of a tile that successor tiles read (last NL rows along z and y).
+template <int DIM, int NL, int RZ, int RY>
+struct Exporters {
+  static constexpr int NE = (DIM == 3) ? NL * RY + (RZ - NL) * NL : ((DIM == 2) ? NL : 0);
+  static __device__ __forceinline__ int row(int rz, int ry) {
+    if (DIM == 3) {
+      if (rz >= RZ - NL) return (rz - (RZ - NL)) * RY + ry;
+      if (ry >= RY - NL) return NL * RY + rz * NL + (ry - (RY - NL));
+      return -1;
+    }
+    if (DIM == 2) return ry >= RY - NL ? ry - (RY - NL) : -1;
+    return -1;
+  }
+};
 
 template <typename T, typename CT, int DIM, int NL, bool COMP, int RZ, int RY>
 __global__ void __launch_bounds__(RZ * RY) sweep_kernel(SweepArgs A) {
@@ -144,12 +224,13 @@ __global__ void __launch_bounds__(RZ * RY) sweep_kernel(SweepArgs A) {
   constexpr int XZ = RZ + HZ, XY = RY + HY;
   constexpr Terms<DIM, NL> TT{};
   constexpr int NTERM = Terms<DIM, NL>::N;
+  using EX = Exporters<DIM, NL, RZ, RY>;
+  constexpr int NE = EX::NE;
   // halo rows: z-halo NL x (RY + NL), y-halo RZ x NL
   constexpr int H = (DIM == 3) ? (NL * (RY + NL) + RZ * NL) : ((DIM == 2) ? NL : 0);
   static_assert(H <= NT, "halo rows exceed threads");
-  // lanes per row for 16-byte chunk traffic
-  constexpr int XLPR = (kG * (int)sizeof(T)) / 16;   // x / x' chunks
-  constexpr int CLPR = (kG * (int)sizeof(CT)) / 16;  // code chunks
+  constexpr int XLPR = (kG * (int)sizeof(T)) / 16;   // 16-byte pieces per x / x' chunk
+  constexpr int CLPR = (kG * (int)sizeof(CT)) / 16;  // 16-byte pieces per code chunk
   constexpr int XEPL = 16 / (int)sizeof(T);
   constexpr int CEPL = 16 / (int)sizeof(CT);
 
@@ -178,7 +259,7 @@ __global__ void __launch_bounds__(RZ * RY) sweep_kernel(SweepArgs A) {
 
   // ---- tile geometry
   int64_t zb0 = 0, zb1 = 1, yb0 = 0, yb1 = 1, xb0 = 0, xb1 = 0, z0 = 0, y0 = 0;
-  int pred_z = -1, pred_y = -1;
+  int pred_z = -1, pred_y = -1, pred_zy = -1;
   if (DIM >= 2) {
     const int per_blk = g.tz_per_blk * g.ty_per_blk;
     const int bi = tile / per_blk;
@@ -197,8 +278,9 @@ __global__ void __launch_bounds__(RZ * RY) sweep_kernel(SweepArgs A) {
     y0 = yb0 + (int64_t)tyt * RY;
     if (DIM == 3 && tzt > 0) pred_z = tile - g.ty_per_blk;
     if (tyt > 0) pred_y = tile - 1;
+    if (DIM == 3 && tzt > 0 && tyt > 0) pred_zy = tile - g.ty_per_blk - 1;
     if (z0 >= zb1 || y0 >= yb1) {  // empty tile past a ragged block edge
-      if (tid == 0) __hip_atomic_store(&A.progress[tile], kDone, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (tid == 0) __hip_atomic_store(&A.progress[tile], kDone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
   }
@@ -246,40 +328,64 @@ __global__ void __launch_bounds__(RZ * RY) sweep_kernel(SweepArgs A) {
   T* __restrict__ xo = (T*)A.xo;
   const int64_t ntot = g.n;
 
-  // ---- halo ownership
-  bool h_own = false;
+  // ---- exchange buffer: one descriptor for all tiles (wave-uniform)
+  const __amdgpu_buffer_rsrc_t xr =
+      make_rsrc(A.xchg, (uint64_t)g.ntiles * (uint64_t)(NE > 0 ? NE : 1) * A.nsp * sizeof(T));
+  const int my_erow = EX::row(rz, ry);
+
+  // ---- halo ownership: virtual row (hrz, hry) of this tile, read from a
+  // predecessor's exporter row at a step offset d.
+  bool h_own = false, h_in = false;
   int hrz = 0, hry = 0, hs = 0;
-  bool h_in = false;
-  int64_t h_base = 0;
+  int64_t h_elem = 0;  // element offset of the predecessor row's step 0 in xchg
+  int hd = 0;
   if (DIM >= 2 && tid < H) {
     h_own = true;
+    int ptile, prz, pry;
     if (DIM == 3) {
       if (tid < NL * (RY + NL)) {
         hrz = -(1 + tid / (RY + NL));
         hry = tid % (RY + NL) - NL;
+        if (hry >= 0) {
+          ptile = pred_z;
+          prz = RZ + hrz;
+          pry = hry;
+          hd = RZ;
+        } else {
+          ptile = pred_zy;
+          prz = RZ + hrz;
+          pry = RY + hry;
+          hd = RZ + RY;
+        }
       } else {
         const int q = tid - NL * (RY + NL);
         hrz = q / NL;
         hry = -(1 + q % NL);
+        ptile = pred_y;
+        prz = hrz;
+        pry = RY + hry;
+        hd = RY;
       }
     } else {
       hrz = 0;
       hry = -(1 + tid);
+      ptile = pred_y;
+      prz = 0;
+      pry = RY + hry;
+      hd = RY;
     }
     hs = hrz + hry;
-    const int64_t zh = (DIM == 3) ? z0 + hrz : 0;
-    const int64_t yh = y0 + hry;
-    h_in = zh >= zb0 && zh < zb1 && yh >= yb0 && yh < yb1;
-    h_base = (zh * Yd + yh) * Xd + xb0;
+    h_in = ptile >= 0;
+    if (h_in) h_elem = ((int64_t)ptile * NE + EX::row(prz, pry)) * (int64_t)A.nsp;
   }
-  const bool exporter = (DIM == 3) ? (rz >= RZ - NL || ry >= RY - NL) : ((DIM == 2) ? ry >= RY - NL : false);
 
-  T hv[kG], hn[kG];
+  constexpr int HL = (kG * (int)sizeof(T)) / 16;  // 16-byte pieces per halo window
+  uint4 hraw[HL], hnext[HL];
 #pragma unroll
-  for (int i = 0; i < kG; i++) hv[i] = hn[i] = T(0);
+  for (int j = 0; j < HL; j++) hraw[j] = hnext[j] = make_uint4(0, 0, 0, 0);
 
   auto wait_preds = [&](int grp) {
-    // halo values of group grp need z-pred step +RZ and y-pred step +RY
+    // halo values of group grp need z-pred steps + RZ and y-pred steps + RY
     if (DIM == 1) return;
     // Bounded wait: a tile only waits on tiles with smaller tickets, which
     // are already resident, so the wait always ends; the spin limit turns a
@@ -292,7 +398,7 @@ __global__ void __launch_bounds__(RZ * RY) sweep_kernel(SweepArgs A) {
       for (int q = 0; q < 2; q++) {
         if (preds[q] < 0) continue;
         uint32_t spins = 0;
-        while (__hip_atomic_load(&A.progress[preds[q]], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < needs[q]) {
+        while (__hip_atomic_load(&A.progress[preds[q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < needs[q]) {
           if (__hip_atomic_load(&P->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
           if (++spins > kSpinLimit) {
             atomicCAS(&P->status, 0, kStatusStalled);
@@ -305,12 +411,14 @@ __global__ void __launch_bounds__(RZ * RY) sweep_kernel(SweepArgs A) {
     __syncthreads();
   };
 
-  auto load_halo = [&](int grp, T (&dst)[kG]) {
+  // Halo window of group grp: predecessor steps [grp*kG + hd, +kG).
+  auto load_halo = [&](int grp, uint4 (&dst)[HL]) {
     if (!h_own) return;
+    const int64_t e0 = h_in ? h_elem + (int64_t)grp * kG + hd : 0;
 #pragma unroll
-    for (int i = 0; i < kG; i++) {
-      const int64_t xl = (int64_t)grp * kG + i - hs;
-      dst[i] = (h_in && xl >= 0 && xl < xlen_tile) ? xo[h_base + xl] : T(0);
+    for (int j = 0; j < HL; j++) {
+      const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(xr, (int)(e0 * sizeof(T)) + 16 * j, 0, kCoherent);
+      dst[j] = __builtin_bit_cast(uint4, v);
     }
   };
 
@@ -320,8 +428,19 @@ __global__ void __launch_bounds__(RZ * RY) sweep_kernel(SweepArgs A) {
   uint4 pre[LPR_IN];
   bool pre_ok[LPR_IN];
   int64_t pre_pos[LPR_IN];
+  int64_t row0_base, tmp_l;
+  int tmp_s;
+  bool tmp_ok;
+  row_info(0, row0_base, tmp_l, tmp_s, tmp_ok);
+  const int64_t xdesc_base = row0_base & ~(int64_t)(kG - 1);
+  const __amdgpu_buffer_rsrc_t xrs =
+      make_rsrc(COMP ? (const void*)(xin + xdesc_base) : nullptr,
+                COMP ? (uint64_t)(ntot - xdesc_base) * sizeof(T) : 0);
 
-  // Issue loads of chunk q for the job's row (job j = i * NT + tid).
+  // Issue loads of the chunk holding the last element a job's row touches in
+  // group grp (job j = i * NT + tid); loads are unconditional (out-of-range
+  // input reads return zero, code reads are clamped into the padded
+  // workspace) so no wait is placed before the group's steps.
   auto load_chunk_regs = [&](int grp) {
 #pragma unroll
     for (int i = 0; i < LPR_IN; i++) {
@@ -332,26 +451,16 @@ __global__ void __launch_bounds__(RZ * RY) sweep_kernel(SweepArgs A) {
       bool rok;
       row_info(r, rb, rl, rs, rok);
       const int64_t hi = rb + (int64_t)grp * kG + (kG - 1) - rs;
-      const int64_t q = hi >> 4;  // kG == 16
-      const int64_t c0 = q * kG;
-      const bool overlap = rok && (c0 + kG > rb) && (c0 < rb + rl);
-      pre_ok[i] = overlap;
+      const int64_t c0 = (hi >> 4) * kG;  // kG == 16
+      pre_ok[i] = rok && (c0 + kG > rb) && (c0 < rb + rl);
       pre_pos[i] = c0 + part * EPL_IN;
-      pre[i] = make_uint4(0, 0, 0, 0);
-      if (overlap) {
-        const int64_t e0 = c0 + part * EPL_IN;
-        if (COMP) {
-          if (e0 + EPL_IN <= ntot) {
-            pre[i] = *(const uint4*)(xin + e0);
-          } else {
-            T tmp[XEPL];
-#pragma unroll
-            for (int e = 0; e < XEPL; e++) tmp[e] = (e0 + e < ntot) ? xin[e0 + e] : T(0);
-            pre[i] = *(uint4*)tmp;
-          }
-        } else {
-          pre[i] = *(const uint4*)(cglob + e0);  // code workspace is padded
-        }
+      if (COMP) {
+        const int off = (int)((c0 + part * EPL_IN - xdesc_base) * (int64_t)sizeof(T));
+        pre[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(xrs, off, 0, 0));
+      } else {
+        int64_t e0 = c0 + part * EPL_IN;
+        e0 = e0 < 0 ? 0 : (e0 > (int64_t)A.codes_cap - CEPL ? (int64_t)A.codes_cap - CEPL : e0);
+        pre[i] = *(const uint4*)(cglob + e0);
       }
     }
   };
@@ -396,7 +505,6 @@ __global__ void __launch_bounds__(RZ * RY) sweep_kernel(SweepArgs A) {
       const int64_t c0 = q * kG;
       const int64_t lo_ok = rb, hi_ok = rb + rl;  // valid raster range of the row
       if (c0 + kG <= lo_ok || c0 >= hi_ok) continue;
-      if (!final_pass && hi < rb) continue;
       const int64_t e0 = c0 + part * EPL_OUT;
       const int pos = (int)(e0 & (kRing - 1));
       if (e0 >= lo_ok && e0 + EPL_OUT <= hi_ok) {
@@ -434,105 +542,122 @@ __global__ void __launch_bounds__(RZ * RY) sweep_kernel(SweepArgs A) {
   }
 
   uint32_t cnt_center = 0, cnt_zero = 0;
+  const int xlen_row = row_ok ? (int)xlen : 0;
+  const int base_lo = (int)(base & (kRing - 1));
+  const int e_eb = (int)((ebT_bits >> FTr<T>::MANT) & (U)FTr<T>::EMAX);
   const int32_t wbase = (COMP && (1 << m) > kHistWin) ? half - kHistWin / 2 : 0;
+  T ev[kG];  // this row's values of the current group, published if it is an exporter
 
   // ---- prologue: group 0 halo and the two chunks group 0 may touch
   wait_preds(0);
-  load_halo(0, hv);
+  load_halo(0, hraw);
   // Halo rows with negative skew start before step 0: their first -hs cells
   // belong to steps that never run, so they are written here.
   if (DIM >= 2 && h_own && hs < 0) {
     for (int xl = 0; xl < -hs; xl++) {
-      const T v = (h_in && xl < xlen_tile) ? xo[h_base + xl] : T(0);
-      xring[xl & (R - 1)][hrz + HZ][hry + HY] = v;
+      const int64_t e = h_in ? h_elem + (xl + hs) + hd : 0;
+      const T v = load_coherent<T>(xr, (int)(e * sizeof(T)));
+      xring[xl & (R - 1)][hrz + HZ][hry + HY] = (h_in && xl < xlen_tile) ? v : T(0);
     }
   }
   load_chunk_regs(-1);
   store_chunk_ring();
   load_chunk_regs(0);
   store_chunk_ring();
+  // Nothing may still be in flight when the loop starts, or the compiler's
+  // wait tracking (merging this path with the loop's back edge) would stall
+  // every group's prefetch on it.
+  wait_vm();
   __syncthreads();
 
   for (int grp = 0; grp < ngroups; grp++) {
     const bool more = grp + 1 < ngroups;
     if (more) {
       wait_preds(grp + 1);
-      load_halo(grp + 1, hn);
+      load_halo(grp + 1, hnext);
       load_chunk_regs(grp + 1);
     }
 #pragma unroll
     for (int i = 0; i < kG; i++) {
       const int sigma = grp * kG + i;
       const int xl = sigma - s;
-      const bool act = row_ok && xl >= 0 && xl < xlen;
-      if (DIM >= 2 && h_own) xring[(sigma - hs) & (R - 1)][hrz + HZ][hry + HY] = hv[i];
+      const bool act = (unsigned)xl < (unsigned)xlen_row;
+      if (DIM >= 2 && h_own) {
+        const int hx = sigma - hs;
+        const bool hv_ok = h_in && (unsigned)hx < (unsigned)xlen_tile;
+        xring[hx & (R - 1)][hrz + HZ][hry + HY] = hv_ok ? piece_elem<T>(hraw, i) : T(0);
+      }
       T p = T(0);
 #pragma unroll
       for (int t = 0; t < NTERM; t++) {
         const T v = xring[(xl - TT.c[t]) & (R - 1)][rz - TT.a[t] + HZ][ry - TT.b[t] + HY];
         p = p + T(TT.coef[t]) * v;
       }
-      T xq = T(0);
-      const int rpos = (int)((base + xl) & (kRing - 1));
-      if (act) {
-        if (COMP) {
-          const T x = vring[tid][rpos];
-          const T t = (x - p) * inv2eb;
-          uint32_t code = 0;
-          if (fabs(t) < T(half)) {
-            const int k = (int)rint(t);
-            if (k <= half - 1 && k >= -(half - 1)) {
-              const T xqq = p + T(k) * twoeb;
-              if (fabs(x - xqq) < ebT) {
-                code = (uint32_t)(k + half);
-                xq = xqq;
-              }
-            }
-          }
-          if (code == 0) {
-            xq = truncate_unpred<T>(x, ebT_bits);
-            cnt_zero++;
-          } else if ((int32_t)code == half) {
-            cnt_center++;
-          } else {
-            const int32_t w = (int32_t)code - wbase;
-            if (w >= 0 && w < kHistWin)
-              atomicAdd(&hl[w], 1u);
-            else
-              atomicAdd(&A.hist[code], 1u);
-          }
-          cring[tid][rpos] = (CT)code;
-        } else {
-          const int32_t code = (int32_t)cring[tid][rpos];
-          if (code != 0) {
-            xq = p + T(code - half) * twoeb;
-          } else {
-            xq = unext;
-            uidx++;
-            unext = (uidx < A.n_unpred) ? ((const T*)A.uvals)[uidx] : T(0);
-          }
-          vring[tid][rpos] = xq;
+      const int rpos = (base_lo + xl) & (kRing - 1);
+      T xq;
+      if (COMP) {
+        // Quantization of one point (same IEEE operations as the format
+        // defines: t = (x - p) * (1/2eb), k = rint(t), x_q = p + k * 2eb,
+        // predictable iff |t| < 2^(m-1), |k| <= 2^(m-1) - 1, |x - x_q| < eb).
+        const T x = vring[tid][rpos];
+        const T t = (x - p) * inv2eb;
+        const bool inr = fabs(t) < T(half);
+        const int k = inr ? (int)rint(t) : 0;
+        const bool kin = (k <= half - 1) & (k >= -(half - 1));
+        const T xqq = p + T(k) * twoeb;
+        const bool ok = inr & kin & (fabs(x - xqq) < ebT);
+        const T xt = bits_to<T>(truncate_bits<T>(to_bits<T>(x), e_eb));
+        xq = act ? (ok ? xqq : xt) : T(0);
+        const uint32_t code = ok ? (uint32_t)(k + half) : 0u;
+        cnt_center += (act & ok & (k == 0)) ? 1u : 0u;
+        cnt_zero += (act & !ok) ? 1u : 0u;
+        if (act & ok & (k != 0)) {
+          const uint32_t w = code - (uint32_t)wbase;
+          if (w < (uint32_t)kHistWin)
+            atomicAdd(&hl[w], 1u);
+          else
+            atomicAdd(&A.hist[code], 1u);
         }
-        if (exporter || (COMP && A.export_all)) xo[base + xl] = xq;
+        if (act) cring[tid][rpos] = (CT)code;
+        if (A.export_all && act) xo[base + xl] = xq;
+      } else {
+        const int32_t code = (int32_t)cring[tid][rpos];
+        const T v1 = p + T(code - half) * twoeb;
+        const bool zc = act & (code == 0);
+        xq = act ? (code != 0 ? v1 : unext) : T(0);
+        if (zc) {
+          uidx++;
+          unext = (uidx < A.n_unpred) ? ((const T*)A.uvals)[uidx] : T(0);
+        }
+        if (act) vring[tid][rpos] = xq;
       }
+      ev[i] = xq;
       xring[xl & (R - 1)][rz + HZ][ry + HY] = xq;
       if (DIM >= 2) __syncthreads();
     }
-    // Group end.  The exports of this group must be complete before the
-    // progress flag moves; the next input chunk replaces the ring half that
-    // this group finished reading; completed output chunks are flushed after
-    // the flag so their stores never delay a successor tile.  (1-D rows
-    // share no values, so only here do all waves meet before the rings are
-    // refilled by other lanes.)
+    // Group end.  Exporter rows publish their 16 values with coherent vector
+    // stores; once every wave's stores are complete the progress flag moves.
+    // The next input chunk replaces the ring half that this group finished
+    // reading; completed output chunks are flushed after the flag so their
+    // stores never delay a successor tile.
+    if (DIM >= 2 && my_erow >= 0) {
+      const int64_t e0 = ((int64_t)tile * NE + my_erow) * (int64_t)A.nsp + (int64_t)grp * kG;
+#pragma unroll
+      for (int j = 0; j < HL; j++) {
+        const uint4 v = pack_piece<T>(ev, j);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), xr, (int)(e0 * sizeof(T)) + 16 * j, 0,
+                                               kCoherent);
+      }
+    }
     if (DIM == 1) __syncthreads();
     wait_vm();
     if (more) store_chunk_ring();
 #pragma unroll
-    for (int i = 0; i < kG; i++) hv[i] = hn[i];
+    for (int j = 0; j < HL; j++) hraw[j] = hnext[j];
     __syncthreads();
     if (DIM >= 2 && tid == 0) {
       const uint32_t done = more ? (uint32_t)((grp + 1) * kG) : kDone;
-      __hip_atomic_store(&A.progress[tile], done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&A.progress[tile], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     flush(grp, false);
     if (!more) flush(grp, true);
