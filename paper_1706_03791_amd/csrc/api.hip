@@ -346,7 +346,7 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
   hipLaunchKernelGGL(codebook_kernel, dim3(1), dim3(kCbNT), 0, st, cb);
   stage_end(ctx, ST_CODEBOOK, st);
   stage_begin(ctx, ST_ENCODE, st);
-  const unsigned nch = (unsigned)L.n_chunks;
+  const unsigned nch = (unsigned)std::min<uint64_t>(ceil_div(L.n_chunks, 4), 8192);
   if (L.cw == 1)
     hipLaunchKernelGGL((chunk_stats_kernel<T, uint8_t>), dim3(nch), dim3(256), 0, st, (const uint8_t*)W.codes,
                        (const T*)d_in, (const uint8_t*)W.len, (uint64_t)L.n, L.chunk, W.cbits, W.cu, W.ctb,

@@ -494,33 +494,86 @@ __device__ __forceinline__ int kept_bits(T x, typename FTr<T>::U ebT_bits) {
 }
 
 // ------------------------------------------------- K5a: per-chunk totals
+// One wave per chunk of C symbols (C a multiple of 256): lane l takes the
+// C/64 consecutive symbols starting at l*C/64, loaded as 16-byte vectors.
+template <typename V>
+__device__ __forceinline__ V wave_sum(V v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+template <typename V>
+__device__ __forceinline__ V wave_exscan(V v, V* total) {
+  const int lane = threadIdx.x & 63;
+  V x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const V y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (total) *total = __shfl(x, 63, 64);
+  return x - v;
+}
+
+// Four consecutive codes starting at i (a multiple of 4), as one 4- or
+// 8-byte load; codes at or past n read as 0.
+template <typename CT>
+__device__ __forceinline__ void load4(const CT* __restrict__ codes, uint64_t i, uint64_t n, uint32_t (&o)[4]) {
+  if (i + 4 <= n) {
+    if constexpr (sizeof(CT) == 1) {
+      const uint32_t w = *(const uint32_t*)(codes + i);
+      o[0] = w & 0xFF;
+      o[1] = (w >> 8) & 0xFF;
+      o[2] = (w >> 16) & 0xFF;
+      o[3] = w >> 24;
+    } else {
+      const uint2 w = *(const uint2*)(codes + i);
+      o[0] = w.x & 0xFFFF;
+      o[1] = w.x >> 16;
+      o[2] = w.y & 0xFFFF;
+      o[3] = w.y >> 16;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; k++) o[k] = (i + k < n) ? (uint32_t)codes[i + k] : 0u;
+  }
+}
+
 template <typename T, typename CT>
 __global__ void __launch_bounds__(256) chunk_stats_kernel(const CT* __restrict__ codes, const T* __restrict__ x,
                                                           const uint8_t* __restrict__ len, uint64_t n,
                                                           uint32_t C, uint32_t* cbits, uint32_t* cu,
                                                           uint32_t* ctb, const DevPlan* P) {
   using U = typename FTr<T>::U;
-  __shared__ uint32_t red[8];
   if (P->status) return;
-  const uint64_t c = blockIdx.x;
-  const uint64_t i0 = c * C, i1 = min(n, i0 + C);
+  const uint64_t n_chunks = (n + C - 1) / C;
+  const int lane = threadIdx.x & 63;
+  const int per = (int)(C / 64);
   const U ebb = (U)P->ebT_bits;
-  uint32_t b = 0, z = 0, tb = 0;
-  for (uint64_t i = i0 + threadIdx.x; i < i1; i += 256) {
-    const uint32_t code = codes[i];
-    b += len[code];
-    if (code == 0) {
-      z++;
-      tb += (uint32_t)kept_bits<T>(x[i], ebb);
+  for (uint64_t c = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < n_chunks; c += (uint64_t)gridDim.x * 4) {
+    const uint64_t i0 = c * C + (uint64_t)lane * per;
+    uint32_t b = 0, z = 0, tb = 0;
+    for (int j = 0; j < per; j += 4) {
+      uint32_t sym[4];
+      load4<CT>(codes, i0 + j, n, sym);
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        if (i0 + j + k >= n) break;
+        b += len[sym[k]];
+        if (sym[k] == 0) {
+          z++;
+          tb += (uint32_t)kept_bits<T>(x[i0 + j + k], ebb);
+        }
+      }
     }
-  }
-  b = block_sum<256, uint32_t>(b, red);
-  z = block_sum<256, uint32_t>(z, red);
-  tb = block_sum<256, uint32_t>(tb, red);
-  if (threadIdx.x == 0) {
-    cbits[c] = b;
-    cu[c] = z;
-    ctb[c] = tb;
+    b = wave_sum(b);
+    z = wave_sum(z);
+    tb = wave_sum(tb);
+    if (lane == 0) {
+      cbits[c] = b;
+      cu[c] = z;
+      ctb[c] = tb;
+    }
   }
 }
 
@@ -599,8 +652,12 @@ __global__ void layout_kernel(LayoutArgs A) {
 }
 
 // ------------------------------------------------------- K5c: encoding
+// One wave per chunk: lane offsets by a wave scan of code lengths, bits ORed
+// into the wave's LDS words, then written out (words shared with the
+// neighbouring chunks with an atomic OR, the rest with plain stores).
 constexpr int kEncNT = 256;
 constexpr int kMaxChunk = 4096;
+constexpr int kEncWords = kMaxChunk * kLmax / 32 + 2;
 
 template <typename T, typename CT>
 __global__ void __launch_bounds__(kEncNT) encode_kernel(const CT* __restrict__ codes, const T* __restrict__ x,
@@ -612,75 +669,80 @@ __global__ void __launch_bounds__(kEncNT) encode_kernel(const CT* __restrict__ c
   using U = typename FTr<T>::U;
   constexpr int MANT = FTr<T>::MANT;
   constexpr int HB = 1 + FTr<T>::EXPB;
-  __shared__ uint32_t words[kMaxChunk * kLmax / 32 + 2];
-  __shared__ uint64_t red[8];
+  __shared__ uint32_t words_all[4][kEncWords];
   if (P->status || P->raw) return;
-  const uint64_t c = blockIdx.x;
-  const uint64_t i0 = c * C, i1 = min(n, i0 + C);
-  const uint32_t nb = cbits[c];
-  const uint64_t b0 = boff[c];
-  const uint32_t nw = (uint32_t)((((b0 & 31) + nb) + 31) / 32);
-  for (uint32_t w = threadIdx.x; w < nw; w += kEncNT) words[w] = 0;
+  const uint64_t n_chunks = (n + C - 1) / C;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t* words = words_all[wv];
+  const int per = (int)(C / 64);
   uint32_t* bs = (uint32_t*)(out + P->off_bs);
   uint32_t* hd = (uint32_t*)(out + P->off_hd);
   uint32_t* tl = (uint32_t*)(out + P->off_tl);
+  uint32_t* ch = (uint32_t*)(out + P->off_ch);
   const U ebb = (U)P->ebT_bits;
-  // each thread takes a contiguous run of symbols (raster order preserved)
-  const uint32_t per = (C + kEncNT - 1) / kEncNT;
-  const uint64_t lo = min(i1, i0 + (uint64_t)threadIdx.x * per), hi = min(i1, lo + per);
-  uint64_t mybits = 0, myz = 0, mytb = 0;
-  for (uint64_t i = lo; i < hi; i++) {
-    const uint32_t code = codes[i];
-    mybits += len[code];
-    if (code == 0) {
-      myz++;
-      mytb += kept_bits<T>(x[i], ebb);
+  for (uint64_t c = (uint64_t)blockIdx.x * 4 + wv; c < n_chunks; c += (uint64_t)gridDim.x * 4) {
+    const uint32_t nb = cbits[c];
+    const uint64_t b0 = boff[c];
+    const uint32_t nw = (uint32_t)((((b0 & 31) + nb) + 31) / 32);
+    for (uint32_t w = lane; w < nw; w += 64) words[w] = 0;
+    const uint64_t i0 = c * C + (uint64_t)lane * per;
+    uint32_t mybits = 0, myz = 0, mytb = 0;
+    for (int j = 0; j < per; j += 4) {
+      uint32_t sym[4];
+      load4<CT>(codes, i0 + j, n, sym);
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        if (i0 + j + k >= n) break;
+        mybits += len[sym[k]];
+        if (sym[k] == 0) {
+          myz++;
+          mytb += (uint32_t)kept_bits<T>(x[i0 + j + k], ebb);
+        }
+      }
     }
-  }
-  uint64_t bpos = block_exscan<kEncNT, uint64_t>(mybits, red, nullptr);
-  uint64_t zpos = block_exscan<kEncNT, uint64_t>(myz, red, nullptr);
-  uint64_t tpos = block_exscan<kEncNT, uint64_t>(mytb, red, nullptr);
-  bpos += (b0 & 31);
-  zpos += uoff[c];
-  tpos += toff[c];
-  for (uint64_t i = lo; i < hi; i++) {
-    const uint32_t code = codes[i];
-    const int l = len[code];
-    const uint32_t v = cw[code];
-    // at most two LDS words per code (l <= 27)
-    const uint32_t w = (uint32_t)(bpos >> 5);
-    const int off = (int)(bpos & 31);
-    if (off + l <= 32) {
-      atomicOr(&words[w], v << (32 - off - l));
-    } else {
-      const int first = 32 - off;
-      atomicOr(&words[w], v >> (l - first));
-      atomicOr(&words[w + 1], v << (32 - (l - first)));
+    uint64_t bpos = (b0 & 31) + wave_exscan<uint32_t>(mybits, nullptr);
+    uint64_t zpos = uoff[c] + wave_exscan<uint32_t>(myz, nullptr);
+    uint64_t tpos = toff[c] + wave_exscan<uint32_t>(mytb, nullptr);
+    __builtin_amdgcn_wave_barrier();
+    for (int e = 0; e < per; e++) {
+      if (i0 + e >= n) break;
+      const uint32_t code = codes[i0 + e];
+      const int l = len[code];
+      const uint32_t v = cw[code];
+      const uint32_t w = (uint32_t)(bpos >> 5);
+      const int off = (int)(bpos & 31);
+      if (off + l <= 32) {
+        atomicOr(&words[w], v << (32 - off - l));
+      } else {
+        const int first = 32 - off;
+        atomicOr(&words[w], v >> (l - first));
+        atomicOr(&words[w + 1], v << (32 - (l - first)));
+      }
+      bpos += l;
+      if (code == 0) {
+        const T xi = x[i0 + e];
+        const U ub = to_bits<T>(truncate_unpred<T>(xi, ebb));
+        const int r = kept_bits<T>(xi, ebb);
+        or_bits(hd, zpos * HB, (uint64_t)(ub >> MANT), HB);
+        if (r > 0) or_bits(tl, tpos, (uint64_t)((ub & ((((U)1) << MANT) - 1)) >> (MANT - r)), r);
+        zpos++;
+        tpos += r;
+      }
     }
-    bpos += l;
-    if (code == 0) {
-      const T xt = truncate_unpred<T>(x[i], ebb);
-      const U ub = to_bits<T>(xt);
-      const int r = kept_bits<T>(x[i], ebb);
-      or_bits(hd, zpos * HB, (uint64_t)(ub >> MANT), HB);
-      if (r > 0) or_bits(tl, tpos, (uint64_t)((ub & ((((U)1) << MANT) - 1)) >> (MANT - r)), r);
-      zpos++;
-      tpos += r;
+    __builtin_amdgcn_wave_barrier();
+    const uint64_t gw0 = b0 >> 5;
+    const uint64_t bend = b0 + nb;
+    for (uint32_t w = lane; w < nw; w += 64) {
+      const uint64_t gw = gw0 + w;
+      const bool full = (gw * 32 >= b0) && (gw * 32 + 32 <= bend);
+      if (full)
+        bs[gw] = words[w];
+      else if (words[w])
+        atomicOr(&bs[gw], words[w]);
     }
+    if (lane == 0) ch[c] = nb;
+    __builtin_amdgcn_wave_barrier();
   }
-  __syncthreads();
-  const uint64_t gw0 = b0 >> 5;
-  const uint64_t bend = b0 + nb;
-  for (uint32_t w = threadIdx.x; w < nw; w += kEncNT) {
-    const uint64_t gw = gw0 + w;
-    const bool full = (gw * 32 >= b0) && (gw * 32 + 32 <= bend);
-    if (full)
-      bs[gw] = words[w];
-    else if (words[w])
-      atomicOr(&bs[gw], words[w]);
-  }
-  // chunk table entry
-  if (threadIdx.x == 0) ((uint32_t*)(out + P->off_ch))[c] = nb;
 }
 
 // -------------------------------------------------- K7: header + codebook
@@ -858,7 +920,22 @@ __global__ void __launch_bounds__(1024) dectab_kernel(const uint8_t* comp, uint6
 
 // K8: one lane per chunk decodes its symbols sequentially from the chunk's
 // bit offset; the canonical code is resolved by a 12-bit table in LDS with a
-// first-code-per-length fallback for longer codes.
+// first-code-per-length fallback for longer codes.  The bitstream is read in
+// 16-byte groups one group ahead of use, and the decoded codes leave in
+// 16-byte stores.
+__device__ __forceinline__ uint4 load_words4(const uint32_t* words, uint64_t nwords, uint64_t w) {
+  if (w + 4 <= nwords) return *(const uint4*)(words + w);
+  uint4 r;
+  r.x = (w + 0 < nwords) ? words[w + 0] : 0u;
+  r.y = (w + 1 < nwords) ? words[w + 1] : 0u;
+  r.z = (w + 2 < nwords) ? words[w + 2] : 0u;
+  r.w = (w + 3 < nwords) ? words[w + 3] : 0u;
+  return r;
+}
+__device__ __forceinline__ uint32_t pick4(const uint4& v, int i) {
+  return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+
 template <typename CT>
 __global__ void __launch_bounds__(256) decode_kernel(const uint8_t* __restrict__ comp, uint64_t off_bs,
                                                      uint64_t nwords, uint64_t n, uint32_t C, uint64_t n_chunks,
@@ -878,34 +955,41 @@ __global__ void __launch_bounds__(256) decode_kernel(const uint8_t* __restrict__
   if (P->status) return;
   const uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   if (c >= n_chunks) return;
-  const uint32_t* words = (const uint32_t*)(comp + off_bs);
+  // 16-byte aligned groups of 4 words: start, 2-deep window, word cursor
+  const uint32_t* words = (const uint32_t*)(comp + off_bs);  // 64-byte aligned section
   uint64_t pos = boff[c];
   const uint64_t end = pos + cbits[c];
   const uint64_t i0 = c * C, i1 = min(n, i0 + C);
-  // bit buffer: `buf` holds `nb` valid bits MSB-aligned
-  uint64_t wi = pos >> 5;
+  uint64_t wg = (pos >> 5) & ~3ull;
+  uint4 cur = load_words4(words, nwords, wg);
+  uint4 nxt = load_words4(words, nwords, wg + 4);
+  int wi = (int)((pos >> 5) - wg);  // index of the next word to take from cur
   uint64_t buf = 0;
   int nb = 0;
   {
-    const uint32_t w0 = (wi < nwords) ? words[wi] : 0u;
-    buf = (uint64_t)w0 << 32;
-    buf <<= (pos & 31);
+    const uint32_t w0 = pick4(cur, wi);
+    buf = ((uint64_t)w0 << 32) << (pos & 31);
     nb = 32 - (int)(pos & 31);
     wi++;
   }
-  uint32_t pack = 0;
-  int npack = 0;
-  constexpr int PER = 4 / sizeof(CT);
+  constexpr int SB = 8 * sizeof(CT);  // bits per code
+  constexpr int PER = 128 / SB;       // codes per 16-byte store
+  uint64_t acc_lo = 0, acc_hi = 0;
+  int nacc = 0;
   bool bad = false;
   for (uint64_t i = i0; i < i1; i++) {
     if (nb < 32) {
-      const uint32_t w = (wi < nwords) ? words[wi] : 0u;
-      buf |= (uint64_t)w << (32 - nb);
+      if (wi == 4) {
+        cur = nxt;
+        wg += 4;
+        nxt = load_words4(words, nwords, wg + 4);
+        wi = 0;
+      }
+      buf |= (uint64_t)pick4(cur, wi) << (32 - nb);
       nb += 32;
       wi++;
     }
-    const uint32_t top = (uint32_t)(buf >> (64 - kLutBits));
-    uint32_t e = lut[top];
+    const uint32_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
     uint32_t sym, l;
     if (e) {
       sym = e & 0xFFFF;
@@ -930,11 +1014,13 @@ __global__ void __launch_bounds__(256) decode_kernel(const uint8_t* __restrict__
     buf <<= l;
     nb -= (int)l;
     pos += l;
-    pack |= sym << (8 * sizeof(CT) * npack);
-    if (++npack == PER) {
-      ((uint32_t*)codes)[(i - (PER - 1)) / PER] = pack;
-      pack = 0;
-      npack = 0;
+    // shift the code into a 128-bit accumulator (first code lowest)
+    acc_lo = (acc_lo >> SB) | (acc_hi << (64 - SB));
+    acc_hi = (acc_hi >> SB) | ((uint64_t)sym << (64 - SB));
+    if (++nacc == PER) {
+      *(uint4*)(codes + (i + 1 - PER)) =
+          make_uint4((uint32_t)acc_lo, (uint32_t)(acc_lo >> 32), (uint32_t)acc_hi, (uint32_t)(acc_hi >> 32));
+      nacc = 0;
     }
     if (sym == 0) {
       uint64_t seg;
@@ -947,9 +1033,14 @@ __global__ void __launch_bounds__(256) decode_kernel(const uint8_t* __restrict__
       atomicAdd(&segcnt[seg], 1u);
     }
   }
-  if (!bad && npack) {
-    // ragged tail of the array: write the remaining codes one by one
-    for (int q = 0; q < npack; q++) codes[i1 - npack + q] = (CT)((pack >> (8 * sizeof(CT) * q)) & ((1u << (8 * sizeof(CT))) - 1));
+  if (!bad && nacc) {
+    // ragged end of the array: the last nacc codes sit in the top of the accumulator
+    for (int q = 0; q < nacc; q++) {
+      const int slot = PER - nacc + q;  // position inside the 128-bit value
+      const uint64_t word = slot * SB < 64 ? acc_lo : acc_hi;
+      const int sh = (slot * SB) % 64;
+      codes[i1 - nacc + q] = (CT)((word >> sh) & ((1ull << SB) - 1));
+    }
   }
   if (bad || pos != end) set_status(P, SZ_ECORRUPT);
 }
