@@ -347,12 +347,13 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
   stage_end(ctx, ST_CODEBOOK, st);
   stage_begin(ctx, ST_ENCODE, st);
   const unsigned nch = (unsigned)std::min<uint64_t>(ceil_div(L.n_chunks, 4), 8192);
+  const unsigned cs_lds = 4u * L.chunk * (unsigned)L.cw;
   if (L.cw == 1)
-    hipLaunchKernelGGL((chunk_stats_kernel<T, uint8_t>), dim3(nch), dim3(256), 0, st, (const uint8_t*)W.codes,
+    hipLaunchKernelGGL((chunk_stats_kernel<T, uint8_t>), dim3(nch), dim3(256), cs_lds, st, (const uint8_t*)W.codes,
                        (const T*)d_in, (const uint8_t*)W.len, (uint64_t)L.n, L.chunk, W.cbits, W.cu, W.ctb,
                        (const DevPlan*)P);
   else
-    hipLaunchKernelGGL((chunk_stats_kernel<T, uint16_t>), dim3(nch), dim3(256), 0, st, (const uint16_t*)W.codes,
+    hipLaunchKernelGGL((chunk_stats_kernel<T, uint16_t>), dim3(nch), dim3(256), cs_lds, st, (const uint16_t*)W.codes,
                        (const T*)d_in, (const uint8_t*)W.len, (uint64_t)L.n, L.chunk, W.cbits, W.cu, W.ctb,
                        (const DevPlan*)P);
   scan_u32(W.cbits, L.n_chunks, W.boff, W.tsum_b, W.tot + 0, st);
@@ -372,16 +373,22 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
     hipLaunchKernelGGL(zero_container_kernel, dim3((unsigned)g), dim3(256), 0, st, (uint32_t*)d_out,
                        (const DevPlan*)P);
   }
-  if (L.cw == 1)
-    hipLaunchKernelGGL((encode_kernel<T, uint8_t>), dim3(nch), dim3(kEncNT), 0, st, (const uint8_t*)W.codes,
+  const unsigned enc_lds = enc_lds_bytes(L.chunk, (uint32_t)L.cw);
+  if (L.cw == 1) {
+    hipFuncSetAttribute((const void*)encode_kernel<T, uint8_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)enc_lds);
+    hipLaunchKernelGGL((encode_kernel<T, uint8_t>), dim3(nch), dim3(kEncNT), enc_lds, st, (const uint8_t*)W.codes,
                        (const T*)d_in, (const uint8_t*)W.len, (const uint32_t*)W.cw, (uint64_t)L.n, L.chunk,
                        (const uint32_t*)W.cbits, (const uint64_t*)W.boff, (const uint64_t*)W.uoff,
                        (const uint64_t*)W.toff, (uint8_t*)d_out, (const DevPlan*)P);
-  else
-    hipLaunchKernelGGL((encode_kernel<T, uint16_t>), dim3(nch), dim3(kEncNT), 0, st, (const uint16_t*)W.codes,
+  } else {
+    hipFuncSetAttribute((const void*)encode_kernel<T, uint16_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)enc_lds);
+    hipLaunchKernelGGL((encode_kernel<T, uint16_t>), dim3(nch), dim3(kEncNT), enc_lds, st, (const uint16_t*)W.codes,
                        (const T*)d_in, (const uint8_t*)W.len, (const uint32_t*)W.cw, (uint64_t)L.n, L.chunk,
                        (const uint32_t*)W.cbits, (const uint64_t*)W.boff, (const uint64_t*)W.uoff,
                        (const uint64_t*)W.toff, (uint8_t*)d_out, (const DevPlan*)P);
+  }
   HeaderArgs h;
   h.out = (uint8_t*)d_out;
   h.len = W.len;
@@ -583,12 +590,12 @@ int enqueue_decompress_t(sz_ctx* ctx, const Layout& L, const Hdr& h, const void*
     hipLaunchKernelGGL(decode_kernel<uint8_t>, dim3(gdec), dim3(256), 0, st, comp, h.off_bs, nwords,
                        (uint64_t)L.n, L.chunk, L.n_chunks, (const uint32_t*)(comp + h.off_ch),
                        (const uint64_t*)W.boff, (const DecTables*)W.tabs, (const uint32_t*)W.sorted,
-                       (uint8_t*)W.codes, W.segcnt, X, Bx, nbx, L.ndim, P);
+                       (uint8_t*)W.codes, W.segcnt, X, Bx, nbx, P);
   else
     hipLaunchKernelGGL(decode_kernel<uint16_t>, dim3(gdec), dim3(256), 0, st, comp, h.off_bs, nwords,
                        (uint64_t)L.n, L.chunk, L.n_chunks, (const uint32_t*)(comp + h.off_ch),
                        (const uint64_t*)W.boff, (const DecTables*)W.tabs, (const uint32_t*)W.sorted,
-                       (uint16_t*)W.codes, W.segcnt, X, Bx, nbx, L.ndim, P);
+                       (uint16_t*)W.codes, W.segcnt, X, Bx, nbx, P);
   scan_u32(W.segcnt, L.nseg, W.useg, W.tsum_s, W.tot + 1, st);
   hipLaunchKernelGGL(check_total_kernel, dim3(1), dim3(64), 0, st, (const uint64_t*)(W.tot + 1), U, P);
   stage_end(ctx, ST_DECODE, st);

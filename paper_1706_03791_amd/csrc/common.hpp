@@ -31,6 +31,7 @@ constexpr uint32_t kVersion = 1;
 constexpr uint32_t kHdr = 192;
 constexpr uint32_t kAlign = 64;
 constexpr uint32_t kDefaultChunk = 1024;
+constexpr uint32_t kMaxChunk = 4096;
 constexpr uint32_t kDefaultBlock1D = 2048;
 constexpr int kLmax = 27;
 

@@ -539,33 +539,87 @@ __device__ __forceinline__ void load4(const CT* __restrict__ codes, uint64_t i, 
   }
 }
 
-template <typename T, typename CT>
-__global__ void __launch_bounds__(256) chunk_stats_kernel(const CT* __restrict__ codes, const T* __restrict__ x,
-                                                          const uint8_t* __restrict__ len, uint64_t n,
-                                                          uint32_t C, uint32_t* cbits, uint32_t* cu,
-                                                          uint32_t* ctb, const DevPlan* P) {
-  using U = typename FTr<T>::U;
-  if (P->status) return;
+// Code lengths (and codewords) live in LDS when the alphabet is small.
+constexpr uint32_t kTabLds = 4096;
+
+// Stage chunk c's codes into the wave's LDS buffer with 16-byte coalesced
+// loads (codes past n read as 0); returns the number of real codes.
+template <typename CT>
+__device__ __forceinline__ uint32_t stage_codes(const CT* __restrict__ codes, uint64_t n, uint64_t c, uint32_t C,
+                                                CT* sc, int lane) {
+  const uint64_t i0 = c * C;
+  const uint32_t cnt = (uint32_t)min((uint64_t)C, n - i0);
+  constexpr uint32_t E = 16 / sizeof(CT);
+  if (cnt == C) {
+    // C is a multiple of 256 and codes are 16-byte aligned, so the chunk is
+    // whole 16-byte vectors
+    const uint4* src = (const uint4*)(codes + i0);
+    uint4* dst = (uint4*)sc;
+    const uint32_t nv = C / E;
+#pragma unroll 4
+    for (uint32_t v = lane; v < nv; v += 64) dst[v] = src[v];
+  } else {
+    for (uint32_t k = lane; k < C; k += 64) sc[k] = (k < cnt) ? codes[i0 + k] : (CT)0;
+  }
+  __builtin_amdgcn_wave_barrier();
+  return cnt;
+}
+
+// Four codes from LDS starting at k (a multiple of 4).
+template <typename CT>
+__device__ __forceinline__ void lds_code4(const CT* sc, uint32_t k, uint32_t (&o)[4]) {
+  if constexpr (sizeof(CT) == 1) {
+    const uint32_t w = *(const uint32_t*)(sc + k);
+    o[0] = w & 0xFF;
+    o[1] = (w >> 8) & 0xFF;
+    o[2] = (w >> 16) & 0xFF;
+    o[3] = w >> 24;
+  } else {
+    const uint2 w = *(const uint2*)(sc + k);
+    o[0] = w.x & 0xFFFF;
+    o[1] = w.x >> 16;
+    o[2] = w.y & 0xFFFF;
+    o[3] = w.y >> 16;
+  }
+}
+
+// Code length of symbol s: from the LDS table (len << 27 | code) when LT,
+// else from the global length array.
+template <bool LT>
+__device__ __forceinline__ uint32_t code_entry(uint32_t s, const uint32_t* s_tab, const uint8_t* len,
+                                               const uint32_t* cw) {
+  if constexpr (LT)
+    return s_tab[s];
+  else
+    return ((uint32_t)len[s] << 27) | (cw ? cw[s] : 0u);
+}
+
+template <typename T, typename CT, bool LT>
+__device__ __forceinline__ void chunk_stats_body(const CT* __restrict__ codes, const T* __restrict__ x,
+                                                 const uint8_t* __restrict__ len, const uint32_t* s_tab,
+                                                 CT* sc, uint64_t n, uint32_t C, uint32_t* cbits, uint32_t* cu,
+                                                 uint32_t* ctb, typename FTr<T>::U ebb) {
   const uint64_t n_chunks = (n + C - 1) / C;
   const int lane = threadIdx.x & 63;
-  const int per = (int)(C / 64);
-  const U ebb = (U)P->ebT_bits;
+  const uint32_t per = C / 64;
   for (uint64_t c = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < n_chunks; c += (uint64_t)gridDim.x * 4) {
-    const uint64_t i0 = c * C + (uint64_t)lane * per;
+    const uint32_t cnt = stage_codes<CT>(codes, n, c, C, sc, lane);
+    const uint32_t k0 = (uint32_t)lane * per;
     uint32_t b = 0, z = 0, tb = 0;
-    for (int j = 0; j < per; j += 4) {
+    for (uint32_t j = 0; j < per; j += 4) {
       uint32_t sym[4];
-      load4<CT>(codes, i0 + j, n, sym);
+      lds_code4<CT>(sc, k0 + j, sym);
 #pragma unroll
       for (int k = 0; k < 4; k++) {
-        if (i0 + j + k >= n) break;
-        b += len[sym[k]];
-        if (sym[k] == 0) {
+        const bool real = k0 + j + k < cnt;
+        b += real ? (code_entry<LT>(sym[k], s_tab, len, nullptr) >> 27) : 0u;
+        if (real && sym[k] == 0) {
           z++;
-          tb += (uint32_t)kept_bits<T>(x[i0 + j + k], ebb);
+          tb += (uint32_t)kept_bits<T>(x[c * C + k0 + j + k], ebb);
         }
       }
     }
+    __builtin_amdgcn_wave_barrier();
     b = wave_sum(b);
     z = wave_sum(z);
     tb = wave_sum(tb);
@@ -575,6 +629,27 @@ __global__ void __launch_bounds__(256) chunk_stats_kernel(const CT* __restrict__
       ctb[c] = tb;
     }
   }
+}
+
+template <typename T, typename CT>
+__global__ void __launch_bounds__(256) chunk_stats_kernel(const CT* __restrict__ codes, const T* __restrict__ x,
+                                                          const uint8_t* __restrict__ len, uint64_t n,
+                                                          uint32_t C, uint32_t* cbits, uint32_t* cu,
+                                                          uint32_t* ctb, const DevPlan* P) {
+  extern __shared__ uint4 s_dyn[];  // [4][C] codes, one slice per wave
+  __shared__ uint32_t s_tab[kTabLds];
+  if (P->status) return;
+  const uint32_t nsym = 1u << P->m;
+  const bool lt = nsym <= kTabLds;
+  if (lt)
+    for (uint32_t i = threadIdx.x; i < nsym; i += 256) s_tab[i] = (uint32_t)len[i] << 27;
+  __syncthreads();
+  CT* sc = (CT*)s_dyn + (size_t)(threadIdx.x >> 6) * C;
+  const auto ebb = (typename FTr<T>::U)P->ebT_bits;
+  if (sizeof(CT) == 1 || lt)
+    chunk_stats_body<T, CT, true>(codes, x, len, s_tab, sc, n, C, cbits, cu, ctb, ebb);
+  else
+    chunk_stats_body<T, CT, false>(codes, x, len, s_tab, sc, n, C, cbits, cu, ctb, ebb);
 }
 
 // ------------------------------------------ device-wide exclusive scans
@@ -652,49 +727,53 @@ __global__ void layout_kernel(LayoutArgs A) {
 }
 
 // ------------------------------------------------------- K5c: encoding
-// One wave per chunk: lane offsets by a wave scan of code lengths, bits ORed
-// into the wave's LDS words, then written out (words shared with the
-// neighbouring chunks with an atomic OR, the rest with plain stores).
+// One wave per chunk: the chunk's codes are staged in LDS, lane offsets come
+// from a wave scan of code lengths, bits are ORed into the wave's LDS words
+// and then written out (words shared with the neighbouring chunks with an
+// atomic OR, the rest with plain stores).  The (length, codeword) table sits
+// in LDS as (len << 27) | code when 2^m <= 4096.
 constexpr int kEncNT = 256;
-constexpr int kMaxChunk = 4096;
-constexpr int kEncWords = kMaxChunk * kLmax / 32 + 2;
+__host__ __device__ constexpr uint32_t enc_words_per_wave(uint32_t C) { return C * kLmax / 32 + 2; }
+// dynamic LDS of the encoder: per wave, the bit words then C codes of CT
+__host__ __device__ constexpr uint32_t enc_lds_bytes(uint32_t C, uint32_t code_bytes) {
+  return 4u * (enc_words_per_wave(C) * 4u + C * code_bytes);
+}
 
-template <typename T, typename CT>
-__global__ void __launch_bounds__(kEncNT) encode_kernel(const CT* __restrict__ codes, const T* __restrict__ x,
-                                                        const uint8_t* __restrict__ len,
-                                                        const uint32_t* __restrict__ cw, uint64_t n, uint32_t C,
-                                                        const uint32_t* cbits, const uint64_t* boff,
-                                                        const uint64_t* uoff, const uint64_t* toff,
-                                                        uint8_t* out, const DevPlan* P) {
+template <typename T, typename CT, bool LT>
+__device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const T* __restrict__ x,
+                                            const uint8_t* __restrict__ len, const uint32_t* __restrict__ cw,
+                                            const uint32_t* s_tab, uint32_t* words, CT* sc, uint64_t n,
+                                            uint32_t C, const uint32_t* cbits, const uint64_t* boff,
+                                            const uint64_t* uoff, const uint64_t* toff, uint8_t* out,
+                                            const DevPlan* P) {
   using U = typename FTr<T>::U;
   constexpr int MANT = FTr<T>::MANT;
   constexpr int HB = 1 + FTr<T>::EXPB;
-  __shared__ uint32_t words_all[4][kEncWords];
-  if (P->status || P->raw) return;
   const uint64_t n_chunks = (n + C - 1) / C;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  uint32_t* words = words_all[wv];
-  const int per = (int)(C / 64);
+  const int lane = threadIdx.x & 63;
+  const uint32_t per = C / 64;
   uint32_t* bs = (uint32_t*)(out + P->off_bs);
   uint32_t* hd = (uint32_t*)(out + P->off_hd);
   uint32_t* tl = (uint32_t*)(out + P->off_tl);
   uint32_t* ch = (uint32_t*)(out + P->off_ch);
   const U ebb = (U)P->ebT_bits;
-  for (uint64_t c = (uint64_t)blockIdx.x * 4 + wv; c < n_chunks; c += (uint64_t)gridDim.x * 4) {
+  for (uint64_t c = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < n_chunks; c += (uint64_t)gridDim.x * 4) {
     const uint32_t nb = cbits[c];
     const uint64_t b0 = boff[c];
     const uint32_t nw = (uint32_t)((((b0 & 31) + nb) + 31) / 32);
     for (uint32_t w = lane; w < nw; w += 64) words[w] = 0;
-    const uint64_t i0 = c * C + (uint64_t)lane * per;
+    const uint32_t cnt = stage_codes<CT>(codes, n, c, C, sc, lane);
+    const uint32_t k0 = (uint32_t)lane * per;
+    const uint64_t i0 = c * C + k0;
     uint32_t mybits = 0, myz = 0, mytb = 0;
-    for (int j = 0; j < per; j += 4) {
+    for (uint32_t j = 0; j < per; j += 4) {
       uint32_t sym[4];
-      load4<CT>(codes, i0 + j, n, sym);
+      lds_code4<CT>(sc, k0 + j, sym);
 #pragma unroll
       for (int k = 0; k < 4; k++) {
-        if (i0 + j + k >= n) break;
-        mybits += len[sym[k]];
-        if (sym[k] == 0) {
+        const bool real = k0 + j + k < cnt;
+        mybits += real ? (code_entry<LT>(sym[k], s_tab, len, cw) >> 27) : 0u;
+        if (real && sym[k] == 0) {
           myz++;
           mytb += (uint32_t)kept_bits<T>(x[i0 + j + k], ebb);
         }
@@ -704,29 +783,35 @@ __global__ void __launch_bounds__(kEncNT) encode_kernel(const CT* __restrict__ c
     uint64_t zpos = uoff[c] + wave_exscan<uint32_t>(myz, nullptr);
     uint64_t tpos = toff[c] + wave_exscan<uint32_t>(mytb, nullptr);
     __builtin_amdgcn_wave_barrier();
-    for (int e = 0; e < per; e++) {
-      if (i0 + e >= n) break;
-      const uint32_t code = codes[i0 + e];
-      const int l = len[code];
-      const uint32_t v = cw[code];
-      const uint32_t w = (uint32_t)(bpos >> 5);
-      const int off = (int)(bpos & 31);
-      if (off + l <= 32) {
-        atomicOr(&words[w], v << (32 - off - l));
-      } else {
-        const int first = 32 - off;
-        atomicOr(&words[w], v >> (l - first));
-        atomicOr(&words[w + 1], v << (32 - (l - first)));
-      }
-      bpos += l;
-      if (code == 0) {
-        const T xi = x[i0 + e];
-        const U ub = to_bits<T>(truncate_unpred<T>(xi, ebb));
-        const int r = kept_bits<T>(xi, ebb);
-        or_bits(hd, zpos * HB, (uint64_t)(ub >> MANT), HB);
-        if (r > 0) or_bits(tl, tpos, (uint64_t)((ub & ((((U)1) << MANT) - 1)) >> (MANT - r)), r);
-        zpos++;
-        tpos += r;
+    for (uint32_t j = 0; j < per; j += 4) {
+      uint32_t sym[4];
+      lds_code4<CT>(sc, k0 + j, sym);
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        if (k0 + j + k >= cnt) break;
+        const uint32_t code = sym[k];
+        const uint32_t e = code_entry<LT>(code, s_tab, len, cw);
+        const int l = (int)(e >> 27);
+        const uint32_t v = e & 0x07FFFFFFu;
+        const uint32_t w = (uint32_t)(bpos >> 5);
+        const int off = (int)(bpos & 31);
+        if (off + l <= 32) {
+          atomicOr(&words[w], v << (32 - off - l));
+        } else {
+          const int first = 32 - off;
+          atomicOr(&words[w], v >> (l - first));
+          atomicOr(&words[w + 1], v << (32 - (l - first)));
+        }
+        bpos += l;
+        if (code == 0) {
+          const T xi = x[i0 + j + k];
+          const U ub = to_bits<T>(truncate_unpred<T>(xi, ebb));
+          const int r = kept_bits<T>(xi, ebb);
+          or_bits(hd, zpos * HB, (uint64_t)(ub >> MANT), HB);
+          if (r > 0) or_bits(tl, tpos, (uint64_t)((ub & ((((U)1) << MANT) - 1)) >> (MANT - r)), r);
+          zpos++;
+          tpos += r;
+        }
       }
     }
     __builtin_amdgcn_wave_barrier();
@@ -743,6 +828,30 @@ __global__ void __launch_bounds__(kEncNT) encode_kernel(const CT* __restrict__ c
     if (lane == 0) ch[c] = nb;
     __builtin_amdgcn_wave_barrier();
   }
+}
+
+template <typename T, typename CT>
+__global__ void __launch_bounds__(kEncNT) encode_kernel(const CT* __restrict__ codes, const T* __restrict__ x,
+                                                        const uint8_t* __restrict__ len,
+                                                        const uint32_t* __restrict__ cw, uint64_t n, uint32_t C,
+                                                        const uint32_t* cbits, const uint64_t* boff,
+                                                        const uint64_t* uoff, const uint64_t* toff,
+                                                        uint8_t* out, const DevPlan* P) {
+  extern __shared__ uint4 s_dyn[];  // [4][words] then [4][C] codes
+  __shared__ uint32_t s_tab[kTabLds];
+  if (P->status || P->raw) return;
+  const uint32_t nsym = 1u << P->m;
+  const bool lt = nsym <= kTabLds;
+  if (lt)
+    for (uint32_t i = threadIdx.x; i < nsym; i += kEncNT) s_tab[i] = ((uint32_t)len[i] << 27) | cw[i];
+  __syncthreads();
+  const int wv = threadIdx.x >> 6;
+  uint32_t* words = (uint32_t*)s_dyn + (size_t)wv * enc_words_per_wave(C);
+  CT* sc = (CT*)((uint32_t*)s_dyn + 4 * (size_t)enc_words_per_wave(C)) + (size_t)wv * C;
+  if (sizeof(CT) == 1 || lt)
+    encode_body<T, CT, true>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P);
+  else
+    encode_body<T, CT, false>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P);
 }
 
 // -------------------------------------------------- K7: header + codebook
@@ -841,6 +950,9 @@ __global__ void finish_kernel(const DevPlan* P, uint64_t* d_size, int32_t* d_sta
 struct DecTables {
   uint32_t lut[4096];       // (len << 16) | sym for codes of length <= 12, 0 if longer
   uint32_t first[32], count[32], start[32];
+  // lim[l]: (first[l] + count[l]) << (27 - l), the first 27-bit left-aligned
+  // value past the codes of length <= l (non-decreasing in l)
+  uint32_t lim[32];
   uint32_t nsorted;
 };
 constexpr int kLutBits = 12;
@@ -894,9 +1006,12 @@ __global__ void __launch_bounds__(1024) dectab_kernel(const uint8_t* comp, uint6
       start += s_cnt[l];
     }
     for (int l = 0; l < 32; l++) {
-      D->first[l] = (l >= 1 && l <= kLmax) ? s_first[l] : 0;
+      const bool in = l >= 1 && l <= kLmax;
+      D->first[l] = in ? s_first[l] : 0;
       D->count[l] = s_cnt[l];
-      D->start[l] = (l >= 1 && l <= kLmax) ? s_start[l] : 0;
+      D->start[l] = in ? s_start[l] : 0;
+      // Kraft-valid lengths keep first + count <= 2^l, so lim <= 2^27
+      D->lim[l] = in ? (uint32_t)(((uint64_t)s_first[l] + s_cnt[l]) << (kLmax - l)) : (l ? (1u << kLmax) : 0u);
     }
     D->nsorted = n_used;
   }
@@ -919,10 +1034,15 @@ __global__ void __launch_bounds__(1024) dectab_kernel(const uint8_t* comp, uint6
 }
 
 // K8: one lane per chunk decodes its symbols sequentially from the chunk's
-// bit offset; the canonical code is resolved by a 12-bit table in LDS with a
-// first-code-per-length fallback for longer codes.  The bitstream is read in
-// 16-byte groups one group ahead of use, and the decoded codes leave in
-// 16-byte stores.
+// bit offset.  A 12-bit table in LDS resolves short codes; a longer code's
+// length is the count of per-length limits its 27-bit window reaches (the
+// canonical code orders codes by length), and its symbol comes from the
+// length-sorted symbol list (in LDS when it has at most 4096 entries).  The
+// bitstream is read in 16-byte groups one group ahead of use, the decoded
+// codes leave in 16-byte stores, and unpredictable codes are counted per
+// row segment (block row) with the segment tracked incrementally.
+constexpr uint32_t kSymLds = 4096;
+
 __device__ __forceinline__ uint4 load_words4(const uint32_t* words, uint64_t nwords, uint64_t w) {
   if (w + 4 <= nwords) return *(const uint4*)(words + w);
   uint4 r;
@@ -942,36 +1062,52 @@ __global__ void __launch_bounds__(256) decode_kernel(const uint8_t* __restrict__
                                                      const uint32_t* cbits, const uint64_t* boff,
                                                      const DecTables* D, const uint32_t* sorted_syms,
                                                      CT* codes, uint32_t* segcnt, int64_t X, int64_t Bx,
-                                                     int32_t nbx, int ndim, DevPlan* P) {
+                                                     int32_t nbx, DevPlan* P) {
   __shared__ uint32_t lut[4096];
-  __shared__ uint32_t s_first[32], s_count[32], s_start[32];
+  __shared__ uint32_t s_first[32], s_start[32], s_lim[32];
+  __shared__ uint16_t s_syms[kSymLds];
+  __shared__ uint32_t s_win[4][256];  // each lane's current 16-byte group, word-major
+  const uint32_t nsorted = D->nsorted;
+  const bool syms_lds = nsorted <= kSymLds;
   for (int i = threadIdx.x; i < 4096; i += 256) lut[i] = D->lut[i];
+  if (syms_lds)
+    for (uint32_t i = threadIdx.x; i < nsorted; i += 256) s_syms[i] = (uint16_t)sorted_syms[i];
   if (threadIdx.x < 32) {
     s_first[threadIdx.x] = D->first[threadIdx.x];
-    s_count[threadIdx.x] = D->count[threadIdx.x];
     s_start[threadIdx.x] = D->start[threadIdx.x];
+    s_lim[threadIdx.x] = D->lim[threadIdx.x];
   }
   __syncthreads();
   if (P->status) return;
   const uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   if (c >= n_chunks) return;
-  // 16-byte aligned groups of 4 words: start, 2-deep window, word cursor
+  const int t = threadIdx.x;
+  // The bitstream is read in 16-byte aligned groups of 4 words: the group in
+  // use sits in this lane's LDS slot, the next one is in flight in registers
+  // (never copied, so its load is waited for only when it is needed).
   const uint32_t* words = (const uint32_t*)(comp + off_bs);  // 64-byte aligned section
   uint64_t pos = boff[c];
   const uint64_t end = pos + cbits[c];
   const uint64_t i0 = c * C, i1 = min(n, i0 + C);
   uint64_t wg = (pos >> 5) & ~3ull;
-  uint4 cur = load_words4(words, nwords, wg);
-  uint4 nxt = load_words4(words, nwords, wg + 4);
-  int wi = (int)((pos >> 5) - wg);  // index of the next word to take from cur
-  uint64_t buf = 0;
-  int nb = 0;
   {
-    const uint32_t w0 = pick4(cur, wi);
-    buf = ((uint64_t)w0 << 32) << (pos & 31);
-    nb = 32 - (int)(pos & 31);
-    wi++;
+    const uint4 g0 = load_words4(words, nwords, wg);
+    s_win[0][t] = g0.x;
+    s_win[1][t] = g0.y;
+    s_win[2][t] = g0.z;
+    s_win[3][t] = g0.w;
   }
+  uint4 pend = load_words4(words, nwords, wg + 4);
+  int wi = (int)((pos >> 5) - wg);  // index of the next word to take from the slot
+  uint64_t buf = ((uint64_t)s_win[wi][t] << 32) << (pos & 31);
+  int nb = 32 - (int)(pos & 31);
+  wi++;
+  // row segment of i0: seg = row * nbx + col / Bx, rem = elements left in it
+  const uint64_t row0 = i0 / (uint64_t)X, col0 = i0 - row0 * (uint64_t)X;
+  int64_t bx = (int64_t)(col0 / (uint64_t)Bx);
+  uint64_t seg = row0 * (uint64_t)nbx + (uint64_t)bx;
+  int64_t rem = min(X, (bx + 1) * Bx) - (int64_t)col0;
+  uint32_t zc = 0;
   constexpr int SB = 8 * sizeof(CT);  // bits per code
   constexpr int PER = 128 / SB;       // codes per 16-byte store
   uint64_t acc_lo = 0, acc_hi = 0;
@@ -980,12 +1116,18 @@ __global__ void __launch_bounds__(256) decode_kernel(const uint8_t* __restrict__
   for (uint64_t i = i0; i < i1; i++) {
     if (nb < 32) {
       if (wi == 4) {
-        cur = nxt;
+        s_win[0][t] = pend.x;
+        s_win[1][t] = pend.y;
+        s_win[2][t] = pend.z;
+        s_win[3][t] = pend.w;
+        // re-read the slot from LDS rather than forward pend's registers,
+        // which the next load is about to reuse
+        __asm__ volatile("" ::: "memory");
         wg += 4;
-        nxt = load_words4(words, nwords, wg + 4);
+        pend = load_words4(words, nwords, wg + 4);
         wi = 0;
       }
-      buf |= (uint64_t)pick4(cur, wi) << (32 - nb);
+      buf |= (uint64_t)s_win[wi][t] << (32 - nb);
       nb += 32;
       wi++;
     }
@@ -996,19 +1138,20 @@ __global__ void __launch_bounds__(256) decode_kernel(const uint8_t* __restrict__
       l = e >> 16;
     } else {
       const uint32_t v27 = (uint32_t)(buf >> (64 - kLmax));
-      l = 0;
-      sym = 0;
-      for (int q = kLutBits + 1; q <= kLmax; q++) {
-        const uint32_t code = v27 >> (kLmax - q);
-        if (s_count[q] && code >= s_first[q] && code - s_first[q] < s_count[q]) {
-          l = q;
-          sym = sorted_syms[s_start[q] + (code - s_first[q])];
-          break;
-        }
-      }
-      if (!l) {
+      l = kLutBits + 1;
+#pragma unroll
+      for (int q = kLutBits + 1; q < kLmax; q++) l += (v27 >= s_lim[q]) ? 1u : 0u;
+      if (v27 >= s_lim[kLmax]) {
         bad = true;
         break;
+      }
+      const uint32_t idx = s_start[l] + ((v27 >> (kLmax - l)) - s_first[l]);
+      if (syms_lds) {
+        sym = s_syms[idx];
+      } else {
+        sym = sorted_syms[idx];
+        // keep the load's register out of the other paths' wait analysis
+        __builtin_amdgcn_s_waitcnt(0x0F70);
       }
     }
     buf <<= l;
@@ -1022,17 +1165,16 @@ __global__ void __launch_bounds__(256) decode_kernel(const uint8_t* __restrict__
           make_uint4((uint32_t)acc_lo, (uint32_t)(acc_lo >> 32), (uint32_t)acc_hi, (uint32_t)(acc_hi >> 32));
       nacc = 0;
     }
-    if (sym == 0) {
-      uint64_t seg;
-      if (ndim == 1) {
-        seg = i / (uint64_t)Bx;
-      } else {
-        const uint64_t row = i / (uint64_t)X;
-        seg = row * nbx + (i % (uint64_t)X) / (uint64_t)Bx;
-      }
-      atomicAdd(&segcnt[seg], 1u);
+    zc += (sym == 0) ? 1u : 0u;
+    if (--rem == 0) {
+      if (zc) atomicAdd(&segcnt[seg], zc);
+      zc = 0;
+      seg++;
+      if (++bx == nbx) bx = 0;
+      rem = min(X, (bx + 1) * Bx) - bx * Bx;
     }
   }
+  if (zc && !bad) atomicAdd(&segcnt[seg], zc);
   if (!bad && nacc) {
     // ragged end of the array: the last nacc codes sit in the top of the accumulator
     for (int q = 0; q < nacc; q++) {
