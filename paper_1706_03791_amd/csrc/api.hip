@@ -375,14 +375,14 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
   }
   const unsigned enc_lds = enc_lds_bytes(L.chunk, (uint32_t)L.cw);
   if (L.cw == 1) {
-    hipFuncSetAttribute((const void*)encode_kernel<T, uint8_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)encode_kernel<T, uint8_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)enc_lds);
     hipLaunchKernelGGL((encode_kernel<T, uint8_t>), dim3(nch), dim3(kEncNT), enc_lds, st, (const uint8_t*)W.codes,
                        (const T*)d_in, (const uint8_t*)W.len, (const uint32_t*)W.cw, (uint64_t)L.n, L.chunk,
                        (const uint32_t*)W.cbits, (const uint64_t*)W.boff, (const uint64_t*)W.uoff,
                        (const uint64_t*)W.toff, (uint8_t*)d_out, (const DevPlan*)P);
   } else {
-    hipFuncSetAttribute((const void*)encode_kernel<T, uint16_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)encode_kernel<T, uint16_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)enc_lds);
     hipLaunchKernelGGL((encode_kernel<T, uint16_t>), dim3(nch), dim3(kEncNT), enc_lds, st, (const uint16_t*)W.codes,
                        (const T*)d_in, (const uint8_t*)W.len, (const uint32_t*)W.cw, (uint64_t)L.n, L.chunk,

@@ -107,60 +107,74 @@ __device__ __forceinline__ double unord64(uint64_t o) {
 }
 
 // ----------------------------------------------------- K1: value range
+// Min and max in T (only finite data uses the range: REL and BOTH modes
+// reject non-finite input, flagged here), four 16-byte loads in flight per
+// thread, combined across the grid as order-preserving integer keys.
+template <typename T>
+__device__ __forceinline__ void mm_update(T f, T& mn, T& mx, uint32_t& nf) {
+  nf |= !isfinite(f);
+  mn = f < mn ? f : mn;
+  mx = f > mx ? f : mx;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) minmax_kernel(const T* __restrict__ x, uint64_t n, DevPlan* P) {
   __shared__ uint64_t lmin[4], lmax[4];
   __shared__ uint32_t lnf;
   if (threadIdx.x == 0) lnf = 0;
-  uint64_t mn = ~0ull, mx = 0;
+  T mn = (T)__builtin_huge_val(), mx = -(T)__builtin_huge_val();
   uint32_t nf = 0;
   constexpr int V = 16 / sizeof(T);
   const uint64_t nv = n / V;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
-    uint4 raw = ((const uint4*)x)[i];
-    const T* v = (const T*)&raw;
+  const uint4* xv = (const uint4*)x;
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < nv; i += 4 * stride) {
+    uint4 raw[4];
 #pragma unroll
-    for (int e = 0; e < V; e++) {
-      const T f = v[e];
-      nf |= !isfinite(f);
-      const uint64_t o = (sizeof(T) == 4) ? (uint64_t)ord32((float)f) : ord64((double)f);
-      mn = o < mn ? o : mn;
-      mx = o > mx ? o : mx;
+    for (int u = 0; u < 4; u++) raw[u] = xv[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const T* v = (const T*)&raw[u];
+#pragma unroll
+      for (int e = 0; e < V; e++) mm_update<T>(v[e], mn, mx, nf);
     }
   }
-  for (uint64_t i = nv * V + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const T f = x[i];
-    nf |= !isfinite(f);
-    const uint64_t o = (sizeof(T) == 4) ? (uint64_t)ord32((float)f) : ord64((double)f);
-    mn = o < mn ? o : mn;
-    mx = o > mx ? o : mx;
+  for (; i < nv; i += stride) {
+    const uint4 raw = xv[i];
+    const T* v = (const T*)&raw;
+#pragma unroll
+    for (int e = 0; e < V; e++) mm_update<T>(v[e], mn, mx, nf);
   }
+  for (uint64_t k = nv * V + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
+    mm_update<T>(x[k], mn, mx, nf);
+  uint64_t omn = (sizeof(T) == 4) ? (uint64_t)ord32((float)mn) : ord64((double)mn);
+  uint64_t omx = (sizeof(T) == 4) ? (uint64_t)ord32((float)mx) : ord64((double)mx);
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
-    const uint64_t a = __shfl_xor(mn, o, 64), b = __shfl_xor(mx, o, 64);
-    mn = a < mn ? a : mn;
-    mx = b > mx ? b : mx;
+    const uint64_t a = __shfl_xor(omn, o, 64), b = __shfl_xor(omx, o, 64);
+    omn = a < omn ? a : omn;
+    omx = b > omx ? b : omx;
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
   if (nf) atomicOr(&lnf, 1u);
   if (lane == 0) {
-    lmin[wid] = mn;
-    lmax[wid] = mx;
+    lmin[wid] = omn;
+    lmax[wid] = omx;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < 4; w++) {
-      mn = lmin[w] < mn ? lmin[w] : mn;
-      mx = lmax[w] > mx ? lmax[w] : mx;
+      omn = lmin[w] < omn ? lmin[w] : omn;
+      omx = lmax[w] > omx ? lmax[w] : omx;
     }
     if (sizeof(T) == 4) {
-      atomicMin(&P->minmax_bits[0], (uint32_t)mn);
-      atomicMax(&P->minmax_bits[1], (uint32_t)mx);
+      atomicMin(&P->minmax_bits[0], (uint32_t)omn);
+      atomicMax(&P->minmax_bits[1], (uint32_t)omx);
     } else {
-      atomicMin((unsigned long long*)&P->minmax64[0], (unsigned long long)mn);
-      atomicMax((unsigned long long*)&P->minmax64[1], (unsigned long long)mx);
+      atomicMin((unsigned long long*)&P->minmax64[0], (unsigned long long)omn);
+      atomicMax((unsigned long long*)&P->minmax64[1], (unsigned long long)omx);
     }
     if (lnf) atomicOr(&P->nonfinite, 1u);
   }
@@ -496,24 +510,27 @@ __device__ __forceinline__ int kept_bits(T x, typename FTr<T>::U ebT_bits) {
 // ------------------------------------------------- K5a: per-chunk totals
 // One wave per chunk of C symbols (C a multiple of 256): lane l takes the
 // C/64 consecutive symbols starting at l*C/64, loaded as 16-byte vectors.
-template <typename V>
-__device__ __forceinline__ V wave_sum(V v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+// Wave-wide sums and scans of u32 by DPP lane moves: row shifts by 1, 2, 4
+// and 8 give the inclusive scan of each 16-lane row (lanes shifted in from
+// outside the row read 0), then row broadcasts of lanes 15 and 31 carry the
+// row totals into the later rows.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_move(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+__device__ __forceinline__ uint32_t wave_inscan(uint32_t v) {
+  v += dpp_move<0x111, 0xF>(v);  // row_shr:1
+  v += dpp_move<0x112, 0xF>(v);  // row_shr:2
+  v += dpp_move<0x114, 0xF>(v);  // row_shr:4
+  v += dpp_move<0x118, 0xF>(v);  // row_shr:8
+  v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
   return v;
 }
-template <typename V>
-__device__ __forceinline__ V wave_exscan(V v, V* total) {
-  const int lane = threadIdx.x & 63;
-  V x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const V y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (total) *total = __shfl(x, 63, 64);
-  return x - v;
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)wave_inscan(v), 63);
 }
+__device__ __forceinline__ uint32_t wave_exscan(uint32_t v) { return wave_inscan(v) - v; }
 
 // Four consecutive codes starting at i (a multiple of 4), as one 4- or
 // 8-byte load; codes at or past n read as 0.
@@ -779,9 +796,9 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
         }
       }
     }
-    uint64_t bpos = (b0 & 31) + wave_exscan<uint32_t>(mybits, nullptr);
-    uint64_t zpos = uoff[c] + wave_exscan<uint32_t>(myz, nullptr);
-    uint64_t tpos = toff[c] + wave_exscan<uint32_t>(mytb, nullptr);
+    uint64_t bpos = (b0 & 31) + wave_exscan(mybits);
+    uint64_t zpos = uoff[c] + wave_exscan(myz);
+    uint64_t tpos = toff[c] + wave_exscan(mytb);
     __builtin_amdgcn_wave_barrier();
     for (uint32_t j = 0; j < per; j += 4) {
       uint32_t sym[4];
