@@ -7,7 +7,7 @@
  * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
  * may load it.  Build: gcc -O2 -ffp-contract=off -fno-fast-math.
  *
- * Readings taken where the paper is silent (each listed in the design doc):
+ * Readings taken where the paper is silent:
  *  - memory is row-major, last index contiguous (the paper's lowest dimension);
  *  - neighbours outside the independent block read as zero;
  *  - eb in the element type is the double bound rounded toward zero;
