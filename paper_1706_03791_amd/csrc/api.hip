@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 
@@ -86,6 +87,9 @@ struct Layout {
   uint32_t ne;     // exporter rows per tile
   uint32_t nsp;    // steps stored per exporter row
   uint64_t xchg_bytes;
+  bool wave;        // wave-tiled sweep (3D, one layer)
+  int az;           // its z sub-rows per lane
+  uint64_t xy_bytes;  // y-exchange part of the exchange buffer (wave sweep)
   double theta;
   uint64_t out_dims[3], out_block[3];
 };
@@ -166,6 +170,35 @@ int resolve(const sz_params* p, Layout& L) {
   const uint64_t tile_span = (L.ndim == 3) ? (uint64_t)rz * L.dims3[1] * L.dims3[2]
                                            : (L.ndim == 2 ? (uint64_t)ry * L.dims3[2] : (uint64_t)ry * L.blk3[2]);
   if (L.xchg_bytes >= 0x7FFFFF00ull || (tile_span + 64) * L.ts >= 0x7FFFFF00ull) return SZ_EINVAL;
+  // 3D fields with the 1-layer predictor use the wave-tiled sweep: tiles of
+  // nw * az z-rows by 64 y-rows, one workgroup of nw waves each.
+  static const bool legacy = [] {
+    const char* e = std::getenv("SZHIP_LEGACY_SWEEP");
+    return e && e[0] == '1';
+  }();
+  L.wave = L.ndim == 3 && L.nl == 1 && !legacy;
+  L.az = 0;
+  L.xy_bytes = 0;
+  if (L.wave) {
+    const int az = wave_az(L.dtype), nw = wave_nw(L.dtype), tz = nw * az;
+    g.tz_per_blk = (int32_t)ceil_div(L.blk3[0], tz);
+    g.ty_per_blk = (int32_t)ceil_div(L.blk3[1], kWLanes);
+    const uint64_t nt = (uint64_t)g.nblk[0] * g.nblk[1] * g.nblk[2] * g.tz_per_blk * g.ty_per_blk;
+    if (nt >= (1ull << 31)) return SZ_EINVAL;
+    g.ntiles = (int32_t)nt;
+    L.grid = g.ntiles;
+    L.az = az;
+    const uint64_t nsteps = (uint64_t)L.blk3[2] + (tz - 1) + (kWLanes - 1);
+    L.nsp = (uint32_t)(ceil_div(nsteps + kWLanes + tz + 4 * kWG, 16) * 16);
+    L.ne = 0;
+    L.xy_bytes = (uint64_t)g.ntiles * nw * L.nsp * 16;
+    const uint64_t xz_bytes = (uint64_t)g.ntiles * 2 * 64 * L.nsp * L.ts;
+    L.xchg_bytes = L.xy_bytes + xz_bytes;
+    const uint64_t span = ((uint64_t)tz + 1) * L.dims3[1] * L.dims3[2] + 4 * (tz + kWLanes + kWG);
+    if (L.xy_bytes >= 0x7FFFFF00ull || xz_bytes >= 0x7FFFFF00ull || span * L.ts >= 0x7FFFFF00ull ||
+        span * L.cw >= 0x7FFFFF00ull)
+      return SZ_EINVAL;
+  }
   return SZ_OK;
 }
 
@@ -205,7 +238,7 @@ size_t carve_comp(const Layout& L, uint8_t* base, CompWs* W, bool keep_values = 
   CompWs w;
   w.codes = c.take<uint8_t>((L.n + 64) * L.cw);
   w.xs = keep_values ? c.take<uint8_t>(L.n * L.ts) : nullptr;
-  w.xchg = c.take<uint8_t>(L.xchg_bytes + 64);
+  w.xchg = c.take<uint8_t>(L.xchg_bytes + 512);
   w.hist = c.take<uint32_t>(65536 * 4);
   w.progress = c.take<uint32_t>((L.g.ntiles + 1) * 4);
   w.ticket = w.progress + L.g.ntiles;
@@ -260,6 +293,52 @@ int launch_sweep(const Layout& L, bool comp, const SweepArgs& a, hipStream_t st)
                                    : sweep_f64_d3(L.nl, comp, cw, a, L.grid, st));
   }
   return e == hipSuccess ? SZ_OK : SZ_EHIP;
+}
+
+WArgs make_wargs(const Layout& L, const void* x, void* codes, void* xo, void* xchg, uint32_t* progress,
+                 uint32_t* ticket, DevPlan* P) {
+  WArgs a;
+  for (int d = 0; d < 3; d++) {
+    a.dims[d] = L.dims3[d];
+    a.blk[d] = L.blk3[d];
+    a.nblk[d] = L.g.nblk[d];
+  }
+  a.tz_per_blk = L.g.tz_per_blk;
+  a.ty_per_blk = L.g.ty_per_blk;
+  a.ntiles = L.g.ntiles;
+  a.nsp = L.nsp;
+  a.x = x;
+  a.codes = codes;
+  a.xo = xo;
+  a.xy = xchg;
+  a.xz = (uint8_t*)xchg + ((L.xy_bytes + 255) & ~255ull);
+  a.uvals = nullptr;
+  a.useg = nullptr;
+  a.n_unpred = 0;
+  a.codes_cap = (uint64_t)L.n + 64;
+  a.n = (uint64_t)L.n;
+  a.progress = progress;
+  a.ticket = ticket;
+  a.plan = P;
+  a.pass2 = 0;
+  a.export_all = 0;
+  return a;
+}
+
+int launch_wsweep(const Layout& L, bool comp, const WArgs& a, hipStream_t st) {
+  const hipError_t e = L.dtype == SZ_F32 ? wsweep_f32(comp, L.cw, a, L.grid, st) : wsweep_f64(comp, L.cw, a, L.grid, st);
+  return e == hipSuccess ? SZ_OK : SZ_EHIP;
+}
+
+void launch_hist(const Layout& L, const void* codes, uint32_t* hist, const DevPlan* P, uint32_t pass2,
+                 hipStream_t st) {
+  const uint64_t g = std::min<uint64_t>(ceil_div((uint64_t)L.n, 1024 * 16), 1024);
+  if (L.cw == 1)
+    hipLaunchKernelGGL(hist_kernel<uint8_t>, dim3((unsigned)g), dim3(1024), 0, st, (const uint8_t*)codes,
+                       (uint64_t)L.n, hist, P, pass2);
+  else
+    hipLaunchKernelGGL(hist_kernel<uint16_t>, dim3((unsigned)g), dim3(1024), 0, st, (const uint16_t*)codes,
+                       (uint64_t)L.n, hist, P, pass2);
 }
 
 void fill(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st) {
@@ -321,12 +400,26 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
   a.pass2 = 0;
   a.export_all = debug_codes_only ? 1 : 0;
   stage_begin(ctx, ST_SWEEP_C, st);
-  if ((rc = launch_sweep(L, true, a, st))) return rc;
-  if (adaptive) {
-    hipLaunchKernelGGL(pick_m_kernel, dim3(1), dim3(1024), 0, st, W.hist, P, (uint64_t)L.n, L.theta);
-    fill(W.progress, 0, L.g.ntiles + 1, st);
-    a.pass2 = 1;
+  if (L.wave) {
+    WArgs wa = make_wargs(L, d_in, W.codes, W.xs, W.xchg, W.progress, W.ticket, P);
+    wa.export_all = a.export_all;
+    if ((rc = launch_wsweep(L, true, wa, st))) return rc;
+    launch_hist(L, W.codes, W.hist, P, 0, st);
+    if (adaptive) {
+      hipLaunchKernelGGL(pick_m_kernel, dim3(1), dim3(1024), 0, st, W.hist, P, (uint64_t)L.n, L.theta);
+      fill(W.progress, 0, L.g.ntiles + 1, st);
+      wa.pass2 = 1;
+      if ((rc = launch_wsweep(L, true, wa, st))) return rc;
+      launch_hist(L, W.codes, W.hist, P, 1, st);
+    }
+  } else {
     if ((rc = launch_sweep(L, true, a, st))) return rc;
+    if (adaptive) {
+      hipLaunchKernelGGL(pick_m_kernel, dim3(1), dim3(1024), 0, st, W.hist, P, (uint64_t)L.n, L.theta);
+      fill(W.progress, 0, L.g.ntiles + 1, st);
+      a.pass2 = 1;
+      if ((rc = launch_sweep(L, true, a, st))) return rc;
+    }
   }
   stage_end(ctx, ST_SWEEP_C, st);
   if (debug_codes_only) return SZ_OK;
@@ -542,7 +635,7 @@ size_t carve_dec(const Layout& L, uint64_t U, uint8_t* base, DecWs* W) {
   w.tsum_r = c.take<uint64_t>((ceil_div(ngr, 4096) + 1) * 8);
   w.progress = c.take<uint32_t>((L.g.ntiles + 1) * 4);
   w.ticket = w.progress + L.g.ntiles;
-  w.xchg = c.take<uint8_t>(L.xchg_bytes + 64);
+  w.xchg = c.take<uint8_t>(L.xchg_bytes + 512);
   if (W) *W = w;
   return c.off + 256;
 }
@@ -631,7 +724,15 @@ int enqueue_decompress_t(sz_ctx* ctx, const Layout& L, const Hdr& h, const void*
   a.plan = P;
   a.pass2 = 0;
   a.export_all = 0;
-  rc = launch_sweep(L, false, a, st);
+  if (L.wave) {
+    WArgs wa = make_wargs(L, nullptr, W.codes, d_out, W.xchg, W.progress, W.ticket, P);
+    wa.uvals = W.uvals;
+    wa.useg = W.useg;
+    wa.n_unpred = U;
+    rc = launch_wsweep(L, false, wa, st);
+  } else {
+    rc = launch_sweep(L, false, a, st);
+  }
   stage_end(ctx, ST_SWEEP_D, st);
   return rc;
 }

@@ -532,6 +532,64 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 }
 __device__ __forceinline__ uint32_t wave_exscan(uint32_t v) { return wave_inscan(v) - v; }
 
+// ------------------------------------------------ K3: code histogram
+// Histogram of the codes of a sweep (the wave-tiled sweep writes codes
+// only).  A window of up to 16384 bins around the centre code lives in LDS;
+// the centre and zero codes, the most frequent ones, are counted in
+// registers; codes outside the window go straight to global atomics.
+constexpr uint32_t kHistLds = 16384;
+
+template <typename CT>
+__global__ void __launch_bounds__(1024) hist_kernel(const CT* __restrict__ codes, uint64_t n, uint32_t* hist,
+                                                    const DevPlan* P, uint32_t pass2) {
+  __shared__ uint32_t h[kHistLds];
+  if (P->status) return;
+  if (pass2 && !P->rerun) return;
+  const uint32_t m = P->m;
+  const uint32_t nb = 1u << m, half = 1u << (m - 1);
+  const uint32_t W = nb < kHistLds ? nb : kHistLds;
+  const uint32_t wbase = nb > W ? half - W / 2 : 0;
+  for (uint32_t i = threadIdx.x; i < W; i += 1024) h[i] = 0;
+  __syncthreads();
+  uint32_t c_center = 0, c_zero = 0;
+  auto count = [&](uint32_t code) {
+    if (code == half) {
+      c_center++;
+    } else if (code == 0) {
+      c_zero++;
+    } else {
+      const uint32_t w = code - wbase;
+      if (w < W)
+        atomicAdd(&h[w], 1u);
+      else
+        atomicAdd(&hist[code], 1u);
+    }
+  };
+  constexpr int E = 16 / sizeof(CT);
+  const uint64_t nv = n / E;
+  const uint64_t stride = (uint64_t)gridDim.x * 1024;
+  for (uint64_t v = (uint64_t)blockIdx.x * 1024 + threadIdx.x; v < nv; v += stride) {
+    const uint4 raw = ((const uint4*)codes)[v];
+    const uint32_t wd[4] = {raw.x, raw.y, raw.z, raw.w};
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      const uint32_t word = wd[e / (E / 4)];
+      const int sh = (e % (E / 4)) * 8 * (int)sizeof(CT);
+      count((word >> sh) & ((sizeof(CT) == 1) ? 0xFFu : 0xFFFFu));
+    }
+  }
+  for (uint64_t i = nv * E + (uint64_t)blockIdx.x * 1024 + threadIdx.x; i < n; i += stride) count(codes[i]);
+  c_center = wave_sum(c_center);
+  c_zero = wave_sum(c_zero);
+  if ((threadIdx.x & 63) == 0) {
+    if (c_center) atomicAdd(&h[half - wbase], c_center);
+    if (c_zero) atomicAdd(&hist[0], c_zero);
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < W; i += 1024)
+    if (h[i]) atomicAdd(&hist[wbase + i], h[i]);
+}
+
 // Four consecutive codes starting at i (a multiple of 4), as one 4- or
 // 8-byte load; codes at or past n read as 0.
 template <typename CT>

@@ -5,6 +5,7 @@
 
 #include "common.hpp"
 #include "sweep.hpp"
+#include "wsweep.hpp"
 
 namespace szh {
 
@@ -45,6 +46,41 @@ hipError_t sweep_f32_d3(int nl, bool comp, int cw, const SweepArgs& a, int grid,
 hipError_t sweep_f64_d1(int nl, bool comp, int cw, const SweepArgs& a, int grid, hipStream_t st);
 hipError_t sweep_f64_d2(int nl, bool comp, int cw, const SweepArgs& a, int grid, hipStream_t st);
 hipError_t sweep_f64_d3(int nl, bool comp, int cw, const SweepArgs& a, int grid, hipStream_t st);
+
+// Wave-tiled sweep (3D, one layer): waves per workgroup and z sub-rows per
+// lane for each element type (two waves per SIMD; one 16-byte exchange
+// record per step).
+template <typename T> struct WaveShape;
+template <> struct WaveShape<float> { static constexpr int NW = 8, AZ = 2; };
+template <> struct WaveShape<double> { static constexpr int NW = 8, AZ = 1; };
+inline int wave_az(int dtype) { return dtype == SZ_F32 ? WaveShape<float>::AZ : WaveShape<double>::AZ; }
+inline int wave_nw(int dtype) { return dtype == SZ_F32 ? WaveShape<float>::NW : WaveShape<double>::NW; }
+
+template <typename T>
+inline hipError_t launch_wsweep_t(bool comp, int cw, const WArgs& a, int grid, hipStream_t st) {
+  constexpr int AZ = WaveShape<T>::AZ, NW = WaveShape<T>::NW;
+  const dim3 b(NW * 64);
+  if (comp && a.export_all) {
+    if (cw == 1)
+      hipLaunchKernelGGL((wsweep_kernel<T, uint8_t, true, NW, AZ, true>), dim3(grid), b, 0, st, a);
+    else
+      hipLaunchKernelGGL((wsweep_kernel<T, uint16_t, true, NW, AZ, true>), dim3(grid), b, 0, st, a);
+  } else if (comp) {
+    if (cw == 1)
+      hipLaunchKernelGGL((wsweep_kernel<T, uint8_t, true, NW, AZ, false>), dim3(grid), b, 0, st, a);
+    else
+      hipLaunchKernelGGL((wsweep_kernel<T, uint16_t, true, NW, AZ, false>), dim3(grid), b, 0, st, a);
+  } else {
+    if (cw == 1)
+      hipLaunchKernelGGL((wsweep_kernel<T, uint8_t, false, NW, AZ, false>), dim3(grid), b, 0, st, a);
+    else
+      hipLaunchKernelGGL((wsweep_kernel<T, uint16_t, false, NW, AZ, false>), dim3(grid), b, 0, st, a);
+  }
+  return hipGetLastError();
+}
+// Defined in wsweep_<type>.hip
+hipError_t wsweep_f32(bool comp, int cw, const WArgs& a, int grid, hipStream_t st);
+hipError_t wsweep_f64(bool comp, int cw, const WArgs& a, int grid, hipStream_t st);
 
 inline void tile_shape(int dtype, int ndim, int& rz, int& ry) {
   if (dtype == SZ_F32) {

@@ -1,0 +1,647 @@
+// Wave-tiled wavefront sweep for 3D fields with the 1-layer predictor
+// (arXiv 1706.03791, Sec. III-A Eq. predmodel with n = 1, the 3D Lorenzo
+// stencil; quantization of Sec. IV-A; the per-point loop of Algorithm 1).
+//
+// A workgroup of NW waves owns a tile of (NW * AZ) z-rows by 64 y-rows
+// (a row runs along the contiguous X axis).  Lane ly of wave w owns the 64
+// rows y0 + ly of the AZ z-rows z0 + AZ * w + a, and processes point x of
+// sub-row a at step x + AZ * w + a + ly.  With this skew every neighbour of
+// a point was produced one, two or three steps earlier:
+//   * along x by the same lane (registers),
+//   * along y by lane ly - 1 (a wave_shr:1 DPP move of that lane's output;
+//     lane 0 takes the value published by the tile before it along y),
+//   * along z by the same lane's sub-row a - 1 (registers), by the last
+//     sub-row of wave w - 1 (passed through LDS once per step), or, for
+//     wave 0, by the tile before it along z (published per group).
+// The dependence chain inside a workgroup therefore costs one step per row
+// and needs no LDS traffic along y.  Tiles are claimed through an atomic
+// ticket in dependence order and publish their boundary rows every kWG
+// steps with device-coherent stores followed by a relaxed progress flag.
+//
+// Input values (compress) and decompressed values (decompress) stream
+// through per-row LDS rings of two aligned chunks; codes stream through
+// registers.  The arithmetic of one point is the fixed sequence of IEEE
+// operations of the format (the library is built with -ffp-contract=off).
+#pragma once
+
+#include <type_traits>
+
+#include "sweep.hpp"
+
+namespace szh {
+
+constexpr int kWG = 8;       // steps per group (also the chunk length in elements)
+constexpr int kWRing = 16;   // ring slots per row: two chunks
+constexpr int kWLanes = 64;  // y-rows per tile
+
+struct WArgs {
+  int64_t dims[3];   // Z, Y, X
+  int64_t blk[3];
+  int32_t nblk[3];
+  int32_t tz_per_blk, ty_per_blk, ntiles;
+  uint32_t nsp;      // steps stored per exchange row (multiple of kWG)
+  const void* x;     // compress: input field
+  void* codes;       // compress: output codes; decompress: input codes
+  void* xo;          // compress (debug): every recorded value; decompress: output field
+  void* xy;          // exchange towards the next tile along y: [tile][wave][step][AZ]
+  void* xz;          // exchange towards the next tile along z: [tile][out | y-moved][lane][step + 1]
+  const void* uvals; // decompress: unpredictable values in raster order
+  const uint64_t* useg;
+  uint64_t n_unpred;
+  uint64_t codes_cap;  // elements in the code workspace
+  uint64_t n;
+  uint32_t* progress;
+  uint32_t* ticket;
+  DevPlan* plan;
+  uint32_t pass2;
+  uint32_t export_all;
+};
+
+// Lane l takes lane l-1's value; lane 0 takes `old` (wave_shr:1).
+template <typename T>
+__device__ __forceinline__ T wave_shr1(T src, T old) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                             __builtin_bit_cast(int, src), 0x138, 0xF, 0xF, false));
+  } else {
+    const uint64_t s = __builtin_bit_cast(uint64_t, src), o = __builtin_bit_cast(uint64_t, old);
+    const uint32_t lo =
+        (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)s, 0x138, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(s >> 32),
+                                                              0x138, 0xF, 0xF, false);
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+  }
+}
+template <typename T>
+__device__ __forceinline__ T read_lane(T v, int lane) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+  } else {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+  }
+}
+// acc with lane `lane` replaced by the wave-uniform value v.
+template <typename T>
+__device__ __forceinline__ T write_lane(T acc, T v, int lane, int my_lane) {
+  return my_lane == lane ? v : acc;
+}
+
+// One chunk of kWG codes as an integer (u8: 64 bits, u16: 128 bits), code i
+// in bits [i * SB, (i + 1) * SB).
+template <typename CT>
+using CWord = typename std::conditional<sizeof(CT) == 1, uint64_t, unsigned __int128>::type;
+
+template <typename CT>
+__device__ __forceinline__ CWord<CT> load_code_chunk(__amdgpu_buffer_rsrc_t r, int64_t q) {
+  // q may be negative or past the end: the offset then falls outside the
+  // descriptor and the load returns zero
+  const int64_t bo = q * (int64_t)(kWG * sizeof(CT));
+  const int off = (bo < 0 || bo > 0x7FFFFF00ll) ? 0x7FFFFF00 : (int)bo;
+  if constexpr (sizeof(CT) == 1) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    return ((uint64_t)v[1] << 32) | v[0];
+  } else {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    return ((unsigned __int128)(((uint64_t)v[3] << 32) | v[2]) << 64) | (((uint64_t)v[1] << 32) | v[0]);
+  }
+}
+
+// Codes of the window that starts o codes into chunk c0 (o in [0, kWG)).
+template <typename CT>
+__device__ __forceinline__ CWord<CT> code_window(CWord<CT> c0, CWord<CT> c1, int o) {
+  constexpr int SB = 8 * sizeof(CT);
+  constexpr int BITS = kWG * SB;
+  if (o == 0) return c0;
+  return (c0 >> (SB * o)) | (c1 << (BITS - SB * o));
+}
+
+// The AZ values of one step as a 16-byte exchange record.
+template <typename T, int AZ>
+__device__ __forceinline__ u32x4 pack_rec(const T (&v)[AZ]) {
+  if constexpr (sizeof(T) == 4) {
+    return u32x4{__builtin_bit_cast(uint32_t, v[0]), __builtin_bit_cast(uint32_t, v[1 % AZ]),
+                 __builtin_bit_cast(uint32_t, v[2 % AZ]), __builtin_bit_cast(uint32_t, v[3 % AZ])};
+  } else {
+    const uint64_t a0 = __builtin_bit_cast(uint64_t, v[0]), a1 = __builtin_bit_cast(uint64_t, v[1 % AZ]);
+    return u32x4{(uint32_t)a0, (uint32_t)(a0 >> 32), (uint32_t)a1, (uint32_t)(a1 >> 32)};
+  }
+}
+
+// Reduced binary representation of an unpredictable value (same result as
+// truncate_unpred) computed with bit masks only, so the step stays one
+// basic block: keep the value when the bound is not normal or the value is
+// Inf/NaN or no mantissa bit can go; a signed zero when its exponent is 0 or
+// below the bound's; else clear the low MANT - (e - e_eb) mantissa bits.
+template <typename T>
+__device__ __forceinline__ typename FTr<T>::U trunc_masked(typename FTr<T>::U u, int e_eb) {
+  using U = typename FTr<T>::U;
+  constexpr int MANT = FTr<T>::MANT, EXPB = FTr<T>::EXPB, EMAX = FTr<T>::EMAX;
+  const int e = (int)((u >> MANT) & (U)EMAX);
+  const int r = e - e_eb;
+  const U keep = (U)0 - (U)((e_eb == 0) | (e == EMAX) | (r >= MANT));
+  const U zero = (U)0 - (U)((e == 0) | (r < 0));
+  const int rc = r < 0 ? 0 : (r > MANT - 1 ? MANT - 1 : r);
+  const U mant = ~((((U)1) << (MANT - rc)) - 1);
+  const U sign = ((U)1) << (MANT + EXPB);
+  const U m = keep | (~keep & ((zero & sign) | (~zero & mant)));
+  return u & m;
+}
+
+// Element a of a 16-byte exchange record.
+template <typename T>
+__device__ __forceinline__ T rec_elem(u32x4 v, int a) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, (uint32_t)v[a]);
+  else
+    return __builtin_bit_cast(T, ((uint64_t)v[2 * a + 1] << 32) | v[2 * a]);
+}
+
+template <typename T, typename CT, bool COMP, int NW, int AZ, bool DBG>
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
+wsweep_kernel(WArgs A) {
+  using U = typename FTr<T>::U;
+  using CW = CWord<CT>;
+  constexpr int G = kWG;
+  constexpr int TZ = NW * AZ;
+  constexpr int SB = 8 * sizeof(CT);
+  constexpr int XPC = (G * (int)sizeof(T)) / 16;  // 16-byte pieces per chunk of values
+  constexpr int EPP = 16 / (int)sizeof(T);        // values per piece
+  static_assert(AZ * sizeof(T) <= 16, "one 16-byte exchange record per step");
+
+  __shared__ T s_ring[NW][AZ][kWRing][64];  // compress: input; decompress: output
+  __shared__ T s_xw[2][NW][2][64];          // last sub-row of each wave: [step parity][wave][out | moved][lane]
+  __shared__ u32x4 s_yin[NW][kWG];          // y-halo records of the group, one per step
+  __shared__ u32x4 s_yout[NW][kWG];         // lane 63's values of the group, one record per step
+  __shared__ int s_tile;
+
+  DevPlan* P = A.plan;
+  if (P->status != 0) return;
+  if (A.pass2 && !P->rerun) return;
+
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, ly = tid & 63;
+  const int wprev = w > 0 ? w - 1 : 0;
+  if (tid == 0) s_tile = (int)atomicAdd(A.ticket, 1u);
+  for (int i = tid; i < 2 * NW * 2 * 64; i += NW * 64) (&s_xw[0][0][0][0])[i] = T(0);
+  __syncthreads();
+  const int tile = s_tile;
+
+  // ---- tile geometry
+  const int per_blk = A.tz_per_blk * A.ty_per_blk;
+  const int bi = tile / per_blk, brem = tile % per_blk;
+  const int tzt = brem / A.ty_per_blk, tyt = brem % A.ty_per_blk;
+  const int bz = bi / (A.nblk[1] * A.nblk[2]), by = (bi / A.nblk[2]) % A.nblk[1], bx = bi % A.nblk[2];
+  const int64_t Yd = A.dims[1], Xd = A.dims[2];
+  const int64_t zb0 = (int64_t)bz * A.blk[0], zb1 = min(zb0 + A.blk[0], A.dims[0]);
+  const int64_t yb0 = (int64_t)by * A.blk[1], yb1 = min(yb0 + A.blk[1], Yd);
+  const int64_t xb0 = (int64_t)bx * A.blk[2], xb1 = min(xb0 + A.blk[2], Xd);
+  const int64_t z0 = zb0 + (int64_t)tzt * TZ, y0 = yb0 + (int64_t)tyt * kWLanes;
+  const int pred_z = tzt > 0 ? tile - A.ty_per_blk : -1;
+  const int pred_y = tyt > 0 ? tile - 1 : -1;
+  const bool succ_z = tzt + 1 < A.tz_per_blk && z0 + TZ < zb1;
+  const bool succ_y = tyt + 1 < A.ty_per_blk && y0 + kWLanes < yb1;
+  const int BX = (int)(xb1 - xb0);
+  const int nsteps = BX + (TZ - 1) + (kWLanes - 1);
+  const int ngroups = (nsteps + G - 1) / G;
+  const int64_t yr = y0 + ly;
+
+  int64_t rb[AZ];   // raster index of the row's first element
+  int64_t wlo[AZ];  // raster index of the first element of group 0's window
+  bool rv[AZ];
+  int sk[AZ];
+  int xlen[AZ];  // BX for a valid row, 0 for rows past the block edge
+#pragma unroll
+  for (int a = 0; a < AZ; a++) {
+    const int64_t zr = z0 + AZ * w + a;
+    rv[a] = zr < zb1 && yr < yb1;
+    rb[a] = (zr * Yd + yr) * Xd + xb0;
+    sk[a] = AZ * w + a + ly;
+    wlo[a] = rb[a] - sk[a];
+    xlen[a] = rv[a] ? (int)(xb1 - xb0) : 0;
+  }
+
+  const uint32_t m = P->m;
+  const int32_t half = 1 << (m - 1);
+  const T halfT = T(half), halfm1T = T(half - 1);
+  const T ebT = bits_to<T>((U)P->ebT_bits);
+  const T twoeb = bits_to<T>((U)P->twoeb_bits);
+  const T inv2eb = bits_to<T>((U)P->inv2eb_bits);
+  const int e_eb = (int)(((U)P->ebT_bits >> FTr<T>::MANT) & (U)FTr<T>::EMAX);
+
+  // ---- exchange descriptors (one each for all tiles; offsets < 2 GiB)
+  const uint64_t nsp = A.nsp;
+  const __amdgpu_buffer_rsrc_t ry =
+      make_rsrc(A.xy, (uint64_t)A.ntiles * NW * nsp * 16);
+  const __amdgpu_buffer_rsrc_t rz = make_rsrc(A.xz, (uint64_t)A.ntiles * 2 * 64 * nsp * sizeof(T));
+  auto y_off = [&](int t, int step) -> int {  // record of (tile t, wave w, step)
+    return (int)((((int64_t)t * NW + w) * (int64_t)nsp + step) * 16);
+  };
+  auto z_off = [&](int t, int kind, int idx) -> int {  // element (tile t, kind, lane, idx)
+    return (int)(((((int64_t)t * 2 + kind) * 64 + ly) * (int64_t)nsp + idx) * (int64_t)sizeof(T));
+  };
+  constexpr int kOut = 0x7FFFFF00;  // offset past every descriptor: loads read zero
+
+  // ---- input descriptor (values for compress, codes for decompress), based
+  // at the tile's first chunk so offsets stay small
+  const int64_t tile_lo = ((z0 * Yd + y0) * Xd + xb0) - (TZ + kWLanes + G);
+  // chunk index of the descriptor base, never before the buffer: chunks
+  // below it (negative indices near the array start) fall outside and read 0
+  const int64_t cbase = max((int64_t)0, tile_lo >> 3);
+  const int64_t ebase = cbase * G;     // element index of the descriptor base
+  const __amdgpu_buffer_rsrc_t rin =
+      COMP ? make_rsrc((const T*)A.x + ebase, (uint64_t)max((int64_t)0, (int64_t)A.n - ebase) * sizeof(T))
+           : make_rsrc((const CT*)A.codes + ebase, (uint64_t)max((int64_t)0, (int64_t)A.codes_cap - ebase) *
+                                                       sizeof(CT));
+
+  // ---- waits on predecessor tiles: the records a group needs
+  auto wait_preds = [&](int gr) {
+    if (tid == 0) {
+      // y records of steps [gr*G + 64, +G) are written by the predecessor's
+      // group (gr*G + 64 + G - 1) / G; z records of indices [gr*G + TZ, +G)
+      // (index k holds step k - 1) by its group (gr*G + TZ + G - 1) / G.
+      const uint32_t need_y = (uint32_t)(((gr * G + kWLanes + G - 1) / G + 1) * G);
+      const uint32_t need_z = (uint32_t)(((gr * G + TZ + G - 1) / G + 1) * G);
+      const int preds[2] = {pred_z, pred_y};
+      const uint32_t needs[2] = {need_z, need_y};
+      for (int q = 0; q < 2; q++) {
+        if (preds[q] < 0) continue;
+        uint32_t spins = 0;
+        while (__hip_atomic_load(&A.progress[preds[q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < needs[q]) {
+          if (__hip_atomic_load(&P->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+          if (++spins > kSpinLimit) {
+            atomicCAS(&P->status, 0, kStatusStalled);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+    }
+    __syncthreads();
+  };
+
+  // ---- halo records of group gr
+  // y: lanes 0..G-1 hold the AZ values lane 0 needs at step gr*G + lane
+  auto load_yh = [&](int gr) -> u32x4 {
+    const int off = pred_y >= 0 ? y_off(pred_y, gr * G + kWLanes + (ly & (G - 1))) : kOut;
+    return __builtin_amdgcn_raw_buffer_load_b128(ry, off, 0, kCoherent);
+  };
+  // z (wave 0): the moved and unmoved values of the row below at steps gr*G - 1 + i
+  auto load_zh = [&](int gr, uint4 (&zo)[XPC], uint4 (&zy)[XPC]) {
+#pragma unroll
+    for (int j = 0; j < XPC; j++) {
+      const int o0 = pred_z >= 0 ? z_off(pred_z, 0, gr * G + TZ) + 16 * j : kOut;
+      const int o1 = pred_z >= 0 ? z_off(pred_z, 1, gr * G + TZ) + 16 * j : kOut;
+      zo[j] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rz, o0, 0, kCoherent));
+      zy[j] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rz, o1, 0, kCoherent));
+    }
+  };
+
+  // ---- input chunks: chunk q of sub-row a (raster elements [8q, 8q + 8))
+  auto chunk_off = [&](int64_t q) -> int {
+    const int64_t bo = (q - cbase) * (int64_t)(G * (COMP ? sizeof(T) : sizeof(CT)));
+    return (bo < 0 || bo > 0x7FFFFF00ll) ? kOut : (int)bo;
+  };
+  auto load_x_chunk = [&](int64_t q, uint4 (&dst)[XPC]) {
+    const int off = chunk_off(q);
+#pragma unroll
+    for (int j = 0; j < XPC; j++)
+      dst[j] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rin, off == kOut ? kOut : off + 16 * j,
+                                                                               0, 0));
+  };
+  auto ring_put = [&](int a, int64_t q, const uint4 (&src)[XPC]) {
+#pragma unroll
+    for (int e = 0; e < G; e++) s_ring[w][a][(int)((q * G + e) & (kWRing - 1))][ly] = piece_elem<T>(src, e);
+  };
+
+  // Output chunk q of sub-row a: only the elements of this row are written.
+  auto store_codes = [&](int a, int64_t q, CW word) {
+    if (!rv[a]) return;
+    const int64_t e0 = q * G, lo = rb[a], hi = rb[a] + BX;
+    if (e0 + G <= lo || e0 >= hi) return;
+    CT* cg = (CT*)A.codes;
+    if (e0 >= lo && e0 + G <= hi) {
+      if constexpr (sizeof(CT) == 1) {
+        *(uint64_t*)(cg + e0) = (uint64_t)word;
+      } else {
+        const uint64_t w0 = (uint64_t)word, w1 = (uint64_t)(word >> 64);
+        *(uint4*)(cg + e0) = make_uint4((uint32_t)w0, (uint32_t)(w0 >> 32), (uint32_t)w1, (uint32_t)(w1 >> 32));
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < G; j++) {
+        const int64_t e = e0 + j;
+        if (e >= lo && e < hi) cg[e] = (CT)(word >> (SB * j));
+      }
+    }
+  };
+  auto flush_values = [&](int a, int64_t q) {
+    if (!rv[a]) return;
+    const int64_t e0 = q * G, lo = rb[a], hi = rb[a] + BX;
+    if (e0 + G <= lo || e0 >= hi) return;
+    T* xg = (T*)A.xo;
+    T v[G];
+#pragma unroll
+    for (int j = 0; j < G; j++) v[j] = s_ring[w][a][(int)((e0 + j) & (kWRing - 1))][ly];
+    if (e0 >= lo && e0 + G <= hi) {
+#pragma unroll
+      for (int j = 0; j < XPC; j++) *(uint4*)(xg + e0 + EPP * j) = pack_piece<T>(v, j);
+    } else {
+#pragma unroll
+      for (int j = 0; j < G; j++) {
+        const int64_t e = e0 + j;
+        if (e >= lo && e < hi) xg[e] = v[j];
+      }
+    }
+  };
+
+  // ---- state
+  T O1[AZ], O2[AZ], Y1[AZ], Y2[AZ], Y3[AZ];
+#pragma unroll
+  for (int a = 0; a < AZ; a++) O1[a] = O2[a] = Y1[a] = Y2[a] = Y3[a] = T(0);
+  T VO1 = T(0), VO2 = T(0), VY1 = T(0), VY2 = T(0), VY3 = T(0);  // row below sub-row 0
+
+  u32x4 yh_cur = {0, 0, 0, 0}, yh_nxt = {0, 0, 0, 0};
+  uint4 zo_cur[XPC], zy_cur[XPC], zo_nxt[XPC], zy_nxt[XPC];
+#pragma unroll
+  for (int j = 0; j < XPC; j++) zo_cur[j] = zy_cur[j] = zo_nxt[j] = zy_nxt[j] = make_uint4(0, 0, 0, 0);
+  T ezo[G], ezy[G];  // wave 3: records of indices g*G + i (index k = value of step k - 1)
+#pragma unroll
+  for (int i = 0; i < G; i++) ezo[i] = ezy[i] = T(0);
+  T co = T(0), cy = T(0);  // value of the group's last step: record 0 of the next group
+
+  uint4 xpre[AZ][COMP ? XPC : 1];  // compress: prefetched input chunk
+  CW c0[AZ], c1[AZ], cpre[AZ];     // decompress: code chunks
+  CW cacc[AZ], cprv[AZ];           // compress: codes of this and the previous group's window
+  uint64_t uidx[AZ];
+  T unext[AZ];
+#pragma unroll
+  for (int a = 0; a < AZ; a++) {
+    c0[a] = c1[a] = cpre[a] = cacc[a] = cprv[a] = (CW)0;
+    uidx[a] = 0;
+    unext[a] = T(0);
+  }
+
+  // ---- prologue: group 0's halo and input
+  wait_preds(0);
+  yh_cur = load_yh(0);
+  if (w == 0) {
+    load_zh(0, zo_cur, zy_cur);
+    // Rows before lane 0 run ahead of it: the y-halo row (skew -1) already
+    // produced x = 0 at step -1, and the corner row (z-1, y-1; skew -2) at
+    // step -2.  Their values enter the histories before step 0.
+    if (pred_y >= 0) {
+      const u32x4 r = __builtin_amdgcn_raw_buffer_load_b128(ry, y_off(pred_y, kWLanes - 1), 0, kCoherent);
+      const T v = rec_elem<T>(r, 0);
+      Y1[0] = ly == 0 ? v : T(0);
+    }
+    if (pred_z >= 0) VY1 = load_coherent<T>(rz, z_off(pred_z, 1, TZ - 1));
+  }
+  // Step -1 of each wave's last sub-row, read by the next wave at step 0
+  // (nonzero only for the seeded y-halo value above when AZ == 1).
+  s_xw[1][w][0][ly] = O1[AZ - 1];
+  s_xw[1][w][1][ly] = Y1[AZ - 1];
+#pragma unroll
+  for (int a = 0; a < AZ; a++) {
+    const int64_t q0 = wlo[a] >> 3;
+    if constexpr (COMP) {
+      uint4 t0[XPC], t1[XPC];
+      load_x_chunk(q0, t0);
+      load_x_chunk(q0 + 1, t1);
+      wait_vm();
+      ring_put(a, q0, t0);
+      ring_put(a, q0 + 1, t1);
+    } else {
+      __amdgpu_buffer_rsrc_t r = rin;
+      c0[a] = load_code_chunk<CT>(r, q0 - cbase);
+      c1[a] = load_code_chunk<CT>(r, q0 + 1 - cbase);
+      if (rv[a]) {
+        const int64_t seg = ((z0 + AZ * w + a) * Yd + yr) * A.nblk[2] + bx;
+        uidx[a] = A.useg[seg];
+        unext[a] = (uidx[a] < A.n_unpred) ? ((const T*)A.uvals)[uidx[a]] : T(0);
+      }
+    }
+  }
+  wait_vm();
+  __syncthreads();
+
+  for (int g = 0; g < ngroups; g++) {
+    const bool more = g + 1 < ngroups;
+    if (ly < G) s_yin[w][ly] = yh_cur;
+    if (more) {
+      wait_preds(g + 1);
+      yh_nxt = load_yh(g + 1);
+      if (w == 0) load_zh(g + 1, zo_nxt, zy_nxt);
+#pragma unroll
+      for (int a = 0; a < AZ; a++) {
+        const int64_t q = (wlo[a] + (int64_t)(g + 1) * G) >> 3;  // first chunk of the next window
+        if constexpr (COMP)
+          load_x_chunk(q + 1, xpre[a]);
+        else
+          cpre[a] = load_code_chunk<CT>(rin, q + 1 - cbase);
+      }
+    }
+    // per-group window of each sub-row and its inputs
+    int bslot[AZ];
+    CW cwin[AZ];
+#pragma unroll
+    for (int a = 0; a < AZ; a++) {
+      const int64_t lo = wlo[a] + (int64_t)g * G;
+      bslot[a] = (int)(lo & (kWRing - 1));
+      if constexpr (!COMP) cwin[a] = code_window<CT>(c0[a], c1[a], (int)(lo & (G - 1)));
+    }
+    T xin[AZ][COMP ? G : 1];
+    T yk[G][AZ];  // this group's values; lane 63's are the y-successor's halo
+    if constexpr (COMP) {
+#pragma unroll
+      for (int a = 0; a < AZ; a++)
+#pragma unroll
+        for (int i = 0; i < G; i++) xin[a][i] = s_ring[w][a][(bslot[a] + i) & (kWRing - 1)][ly];
+    }
+
+#pragma unroll
+    for (int i = 0; i < G; i++) {
+      const int sig = g * G + i;
+      // the row below sub-row 0 at step sig - 1
+      const T lo_o = s_xw[(sig - 1) & 1][wprev][0][ly];
+      const T lo_y = s_xw[(sig - 1) & 1][wprev][1][ly];
+      const T vn_o = w > 0 ? lo_o : piece_elem<T>(zo_cur, i);
+      const T vn_y = w > 0 ? lo_y : piece_elem<T>(zy_cur, i);
+      const u32x4 yrec = s_yin[w][i];  // the y-halo values lane 0 takes at this step
+      VO2 = VO1;
+      VO1 = vn_o;
+      VY3 = VY2;
+      VY2 = VY1;
+      VY1 = vn_y;
+      // The AZ sub-rows are independent within a step (each reads only
+      // values of earlier steps); every statement below runs across all of
+      // them so their dependence chains interleave.
+      T l1[AZ], l2[AZ], ly2[AZ], ly3[AZ], p[AZ], xq[AZ];
+      bool act[AZ];
+#pragma unroll
+      for (int a = 0; a < AZ; a++) {
+        l1[a] = a > 0 ? O1[a > 0 ? a - 1 : 0] : VO1;
+        l2[a] = a > 0 ? O2[a > 0 ? a - 1 : 0] : VO2;
+        ly2[a] = a > 0 ? Y2[a > 0 ? a - 1 : 0] : VY2;
+        ly3[a] = a > 0 ? Y3[a > 0 ? a - 1 : 0] : VY3;
+        act[a] = (unsigned)(sig - sk[a]) < (unsigned)xlen[a];
+      }
+      // Eq. predmodel, n = 1, terms in lexicographic order of (kz, ky, kx)
+#pragma unroll
+      for (int a = 0; a < AZ; a++) p[a] = T(0) + O1[a];  // (0,0,1) +1
+#pragma unroll
+      for (int a = 0; a < AZ; a++) p[a] = p[a] + Y1[a];  // (0,1,0) +1
+#pragma unroll
+      for (int a = 0; a < AZ; a++) p[a] = p[a] - Y2[a];  // (0,1,1) -1
+#pragma unroll
+      for (int a = 0; a < AZ; a++) p[a] = p[a] + l1[a];  // (1,0,0) +1
+#pragma unroll
+      for (int a = 0; a < AZ; a++) p[a] = p[a] - l2[a];  // (1,0,1) -1
+#pragma unroll
+      for (int a = 0; a < AZ; a++) p[a] = p[a] - ly2[a];  // (1,1,0) -1
+#pragma unroll
+      for (int a = 0; a < AZ; a++) p[a] = p[a] + ly3[a];  // (1,1,1) +1
+      if constexpr (COMP) {
+        T t[AZ], rk[AZ], xqq[AZ];
+        bool ok[AZ];
+#pragma unroll
+        for (int a = 0; a < AZ; a++) t[a] = (xin[a][i] - p[a]) * inv2eb;
+#pragma unroll
+        for (int a = 0; a < AZ; a++) rk[a] = rint(t[a]);
+#pragma unroll
+        for (int a = 0; a < AZ; a++) xqq[a] = p[a] + rk[a] * twoeb;
+#pragma unroll
+        for (int a = 0; a < AZ; a++)
+          ok[a] = (fabs(t[a]) < halfT) & (fabs(rk[a]) <= halfm1T) & (fabs(xin[a][i] - xqq[a]) < ebT);
+#pragma unroll
+        for (int a = 0; a < AZ; a++) {
+          // select by masks (keeps the step one basic block)
+          const U xt = trunc_masked<T>(to_bits<T>(xin[a][i]), e_eb);
+          const U okm = (U)0 - (U)ok[a], am = (U)0 - (U)act[a];
+          xq[a] = bits_to<T>(((to_bits<T>(xqq[a]) & okm) | (xt & ~okm)) & am);
+          const uint32_t code = ok[a] ? (uint32_t)((int)rk[a] + half) : 0u;
+          cacc[a] |= (CW)code << (SB * i);
+          if constexpr (DBG)
+            if (act[a]) ((T*)A.xo)[rb[a] + (sig - sk[a])] = xq[a];
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < AZ; a++) {
+          const uint32_t code = (uint32_t)(cwin[a] >> (SB * i)) & ((1u << SB) - 1);
+          const T v1 = p[a] + T((int32_t)code - half) * twoeb;
+          xq[a] = act[a] ? (code != 0 ? v1 : unext[a]) : T(0);
+          if (act[a] && code == 0) {
+            uidx[a]++;
+            unext[a] = (uidx[a] < A.n_unpred) ? ((const T*)A.uvals)[uidx[a]] : T(0);
+          }
+          s_ring[w][a][(bslot[a] + i) & (kWRing - 1)][ly] = xq[a];
+        }
+      }
+      // y-moved values: lane 0 takes the last row of the tile before along y
+      T ynew[AZ];
+#pragma unroll
+      for (int a = 0; a < AZ; a++) ynew[a] = wave_shr1<T>(xq[a], rec_elem<T>(yrec, a));
+#pragma unroll
+      for (int a = 0; a < AZ; a++) {
+        O2[a] = O1[a];
+        O1[a] = xq[a];
+        Y3[a] = Y2[a];
+        Y2[a] = Y1[a];
+        Y1[a] = ynew[a];
+        yk[i][a] = xq[a];
+      }
+      s_xw[sig & 1][w][0][ly] = xq[AZ - 1];
+      s_xw[sig & 1][w][1][ly] = ynew[AZ - 1];
+      if (i + 1 < G) {
+        ezo[i + 1] = xq[AZ - 1];
+        ezy[i + 1] = ynew[AZ - 1];
+      } else {
+        co = xq[AZ - 1];
+        cy = ynew[AZ - 1];
+      }
+      __syncthreads();
+    }
+
+    // ---- group end: publish boundary records, then the progress flag
+    if (succ_y) {
+      if (ly == kWLanes - 1) {
+#pragma unroll
+        for (int i = 0; i < G; i++) s_yout[w][i] = pack_rec<T, AZ>(yk[i]);
+      }
+      if (ly < G) __builtin_amdgcn_raw_buffer_store_b128(s_yout[w][ly], ry, y_off(tile, g * G + ly), 0, kCoherent);
+    }
+    if (succ_z && w == NW - 1) {
+#pragma unroll
+      for (int j = 0; j < XPC; j++) {
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, pack_piece<T>(ezo, j)), rz,
+                                               z_off(tile, 0, g * G) + 16 * j, 0, kCoherent);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, pack_piece<T>(ezy, j)), rz,
+                                               z_off(tile, 1, g * G) + 16 * j, 0, kCoherent);
+      }
+    }
+    if (succ_z && w == NW - 1 && !more) {
+      // the last step's value lives in record (g + 1) * G, past this group
+      if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, co), rz, z_off(tile, 0, (g + 1) * G), 0,
+                                              kCoherent);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, cy), rz, z_off(tile, 1, (g + 1) * G), 0,
+                                              kCoherent);
+      } else {
+        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+        const uint64_t uo = __builtin_bit_cast(uint64_t, co), uy = __builtin_bit_cast(uint64_t, cy);
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2{(uint32_t)uo, (uint32_t)(uo >> 32)}, rz,
+                                              z_off(tile, 0, (g + 1) * G), 0, kCoherent);
+        __builtin_amdgcn_raw_buffer_store_b64(u32x2{(uint32_t)uy, (uint32_t)(uy >> 32)}, rz,
+                                              z_off(tile, 1, (g + 1) * G), 0, kCoherent);
+      }
+    }
+    ezo[0] = co;
+    ezy[0] = cy;
+    wait_vm();
+    __syncthreads();
+    if (tid == 0) {
+      const uint32_t done = more ? (uint32_t)((g + 1) * G) : kDone;
+      __hip_atomic_store(&A.progress[tile], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // ---- completed chunk of each row, input refill, register rotation
+#pragma unroll
+    for (int a = 0; a < AZ; a++) {
+      const int64_t lo = wlo[a] + (int64_t)g * G;
+      const int64_t q = lo >> 3;
+      const int o = (int)(lo & (G - 1));
+      if constexpr (COMP) {
+        const CW word = o ? ((cprv[a] >> (SB * (G - o))) | (cacc[a] << (SB * o))) : cacc[a];
+        store_codes(a, q, word);
+        cprv[a] = cacc[a];
+        cacc[a] = (CW)0;
+        if (more) ring_put(a, q + 2, xpre[a]);
+      } else {
+        flush_values(a, q);
+        c0[a] = c1[a];
+        c1[a] = cpre[a];
+      }
+    }
+    yh_cur = yh_nxt;
+#pragma unroll
+    for (int j = 0; j < XPC; j++) {
+      zo_cur[j] = zo_nxt[j];
+      zy_cur[j] = zy_nxt[j];
+    }
+  }
+  // ---- the chunk after the last window (its head was produced in the last group)
+#pragma unroll
+  for (int a = 0; a < AZ; a++) {
+    const int64_t lo = wlo[a] + (int64_t)(ngroups - 1) * G;
+    const int64_t q = (lo >> 3) + 1;
+    const int o = (int)(lo & (G - 1));
+    if (o == 0) continue;
+    if constexpr (COMP)
+      store_codes(a, q, cprv[a] >> (SB * (G - o)));
+    else
+      flush_values(a, q);
+  }
+}
+
+}  // namespace szh
