@@ -47,6 +47,7 @@ extern "C" {
 #define SZ_ENOMEM (-5)
 #define SZ_EHIP (-6)
 #define SZ_ESTALL (-7) /* internal dataflow wait exceeded its bound (a bug) */
+#define SZ_ETIMEDOUT (-8) /* sz_server_wait: the request did not finish in time */
 
 typedef enum { SZ_F32 = 0, SZ_F64 = 1 } sz_dtype;
 
@@ -130,6 +131,96 @@ const char* sz_strerror(int code);
  * reconstruction sweep.  Returns the number of stages. */
 int sz_ctx_profile(sz_ctx* ctx, int enable);
 int sz_ctx_profile_read(sz_ctx* ctx, double* ms, uint64_t* calls, int n);
+
+/* ------------------------------------------------------------ batched form
+ * Many fields of uneven shape compressed together (not a method of the
+ * paper: a throughput form of the same per-field computation).  Every stage
+ * runs as one launch for the whole batch and the prediction sweep is one
+ * persistent launch over the tiles of all fields; the sequence can be
+ * captured into a HIP graph and replayed.  The container of field i is
+ * byte-identical to what sz_compress produces for params[i] and input i.
+ *
+ * sz_batch_create plans a batch of n (1..65535) fields of one dtype for the
+ * context's device.  `schedule` selects a tile schedule (0..3, see
+ * sz_batch_info) or -1 to time all schedules on the first sz_batch_compress
+ * and keep the fastest (cached per batch signature for the process).  The
+ * batch owns its workspace and per-field plans; the context is only used
+ * for its device and must outlive the batch.
+ *
+ * sz_batch_compress enqueues the compression of d_in[i] (dims of params[i])
+ * into d_out[i] (capacity caps[i], >= sz_compress_bound(params[i]) to avoid
+ * SZ_ECAPACITY) without host synchronisation (autotuning, when pending,
+ * synchronises).  Container sizes go to device uint64 d_sizes[i] and status
+ * words (SZ_OK or a negative code) to device int32 d_status[i].  With
+ * use_graph != 0 the sequence is captured once per set of buffers into a HIP
+ * graph (on a stream of the batch, ordered after and before `stream`) and
+ * replayed.  Calls on one batch must not overlap in time on different
+ * streams. */
+typedef struct sz_batch sz_batch;
+int sz_batch_create(sz_ctx* ctx, uint32_t n, const sz_params* params, int schedule, sz_batch** batch);
+int sz_batch_compress(sz_batch* batch, const void* const* d_in, void* const* d_out, const size_t* caps,
+                      uint64_t* d_sizes, int32_t* d_status, int use_graph, void* stream);
+/* Schedule in use (-1 before tuning), sweep tiles of the batch, threads per
+ * sweep workgroup, and the tuned time (ms) of each candidate (0 if not
+ * measured).  Returns the number of candidate schedules. */
+int sz_batch_info(const sz_batch* batch, int* schedule, uint32_t* tiles, int* threads, double* tune_ms, int n_ms);
+void sz_batch_destroy(sz_batch* batch);
+
+/* ------------------------------------------------------------- served form
+ * A request server with continuous batching (not a method of the paper: a
+ * serving form of the same per-request work).  A native scheduler thread
+ * admits submitted requests, in arrival order, as execution slots (one HIP
+ * stream each) and HBM free up, so requests arriving while others run
+ * overlap with them on the device.  Every request's workspace is carved from
+ * one device pool of `hbm_budget` bytes allocated by sz_server_create:
+ * admission is by workspace footprint and nothing is allocated while
+ * serving.  A request that does not fit in the free pool lets later requests
+ * pass for at most 50 ms, then admission waits for it; a request larger than
+ * the whole pool fails with SZ_ENOMEM.  Results equal those of sz_compress /
+ * sz_decompress on the same input.  Input and output buffers belong to the
+ * client and must stay valid until sz_server_wait returns for the request. */
+#define SZ_REQ_COMPRESS 0
+#define SZ_REQ_DECOMPRESS 1
+
+typedef struct {
+  uint32_t op;          /* SZ_REQ_COMPRESS or SZ_REQ_DECOMPRESS */
+  uint32_t reserved;
+  sz_params params;     /* compress: the field; decompress: ignored */
+  const void* d_in;     /* compress: field (device); decompress: container (device) */
+  size_t in_bytes;      /* decompress: container size in bytes */
+  const void* h_header; /* decompress: optional host copy of the container's first
+                           192 bytes (NULL: the server reads it from d_in) */
+  void* d_out;          /* compress: container buffer; decompress: field buffer (device) */
+  size_t out_cap;       /* capacity of d_out in bytes */
+} sz_request;
+
+typedef struct {
+  int32_t status;       /* SZ_OK or a negative code */
+  uint32_t slot;        /* execution slot that ran the request */
+  uint64_t out_size;    /* container bytes (compress) or field bytes (decompress) */
+  uint64_t workspace_bytes;
+  double t_submit, t_admit, t_done; /* seconds on the server's steady clock */
+} sz_result;
+
+typedef struct {
+  uint64_t submitted, admitted, completed;
+  uint32_t in_flight, max_in_flight;
+  uint64_t pool_bytes, pool_peak_bytes;
+  double clock_s;       /* the server clock now */
+} sz_server_stats_t;
+
+typedef struct sz_server sz_server;
+/* Start a server on `device` with a workspace pool of hbm_budget bytes
+ * (>= 1 MiB) and `slots` (1..64) concurrent requests. */
+int sz_server_create(int device, size_t hbm_budget, uint32_t slots, sz_server** server);
+/* Queue a request (thread-safe, never blocks on the GPU); *id names it. */
+int sz_server_submit(sz_server* server, const sz_request* req, uint64_t* id);
+/* Wait for request `id` (timeout_ms < 0: no limit) and release its record:
+ * SZ_OK with *res filled, SZ_ETIMEDOUT, or SZ_EINVAL for an unknown id. */
+int sz_server_wait(sz_server* server, uint64_t id, sz_result* res, int timeout_ms);
+int sz_server_stats(sz_server* server, sz_server_stats_t* stats);
+/* Finish every queued request, then stop the scheduler and free the pool. */
+void sz_server_destroy(sz_server* server);
 
 #ifdef __cplusplus
 }

@@ -16,13 +16,17 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libszhip.so")
 
 SZ_OK, SZ_EINVAL, SZ_ECAPACITY, SZ_ECORRUPT, SZ_ENONFINITE, SZ_ENOMEM, SZ_EHIP, SZ_ESTALL = 0, -1, -2, -3, -4, -5, -6, -7
+SZ_ETIMEDOUT = -8
+SZ_REQ_COMPRESS, SZ_REQ_DECOMPRESS = 0, 1
 SZ_F32, SZ_F64 = 0, 1
 SZ_EB_ABS, SZ_EB_REL, SZ_EB_ABS_AND_REL = 0, 1, 2
 HEADER_BYTES = 192
 
 EXPORTS = ("sz_ctx_create", "sz_ctx_destroy", "sz_compress_bound", "sz_compress", "sz_compress_async",
            "sz_inspect", "sz_decompress", "sz_quantize", "sz_strerror", "sz_ctx_profile",
-           "sz_ctx_profile_read")
+           "sz_ctx_profile_read", "sz_batch_create", "sz_batch_compress", "sz_batch_info",
+           "sz_batch_destroy", "sz_server_create", "sz_server_submit", "sz_server_wait", "sz_server_stats",
+           "sz_server_destroy")
 STAGES = ("range", "sweep_compress", "codebook", "encode", "dectab", "decode", "unpred", "sweep_decompress")
 
 
@@ -39,6 +43,29 @@ class SzStats(C.Structure):
                 ("eb_used", C.c_double), ("hit_rate", C.c_double), ("value_min", C.c_double),
                 ("value_max", C.c_double), ("m_used", C.c_uint32), ("m_suggested", C.c_uint32),
                 ("raw_fallback", C.c_uint32), ("n_used_syms", C.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SzRequest(C.Structure):
+    _fields_ = [("op", C.c_uint32), ("reserved", C.c_uint32), ("params", SzParams), ("d_in", C.c_void_p),
+                ("in_bytes", C.c_size_t), ("h_header", C.c_void_p), ("d_out", C.c_void_p), ("out_cap", C.c_size_t)]
+
+
+class SzResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("slot", C.c_uint32), ("out_size", C.c_uint64),
+                ("workspace_bytes", C.c_uint64), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SzServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("admitted", C.c_uint64), ("completed", C.c_uint64),
+                ("in_flight", C.c_uint32), ("max_in_flight", C.c_uint32), ("pool_bytes", C.c_uint64),
+                ("pool_peak_bytes", C.c_uint64), ("clock_s", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -77,6 +104,17 @@ def lib():
             L.sz_strerror.restype = C.c_char_p
             L.sz_ctx_profile.argtypes = [vp, C.c_int]
             L.sz_ctx_profile_read.argtypes = [vp, vp, vp, C.c_int]
+            L.sz_batch_create.argtypes = [vp, C.c_uint32, P(SzParams), C.c_int, P(vp)]
+            L.sz_batch_compress.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int, vp]
+            L.sz_batch_info.argtypes = [vp, P(C.c_int), P(C.c_uint32), P(C.c_int), vp, C.c_int]
+            L.sz_batch_destroy.argtypes = [vp]
+            L.sz_batch_destroy.restype = None
+            L.sz_server_create.argtypes = [C.c_int, C.c_size_t, C.c_uint32, P(vp)]
+            L.sz_server_submit.argtypes = [vp, P(SzRequest), P(C.c_uint64)]
+            L.sz_server_wait.argtypes = [vp, C.c_uint64, P(SzResult), C.c_int]
+            L.sz_server_stats.argtypes = [vp, P(SzServerStats)]
+            L.sz_server_destroy.argtypes = [vp]
+            L.sz_server_destroy.restype = None
             _lib = L
         return _lib
 
@@ -154,6 +192,72 @@ def sz_ctx_profile_read(ctx):
     calls = (C.c_uint64 * 16)()
     n = lib().sz_ctx_profile_read(C.c_void_p(ctx), ms, calls, 16)
     return {STAGES[i]: (ms[i], calls[i]) for i in range(min(n, len(STAGES)))}
+
+
+def sz_batch_create(ctx, params, schedule: int = -1) -> int:
+    """Plan a batch over a list of SzParams; returns the batch handle."""
+    arr = (SzParams * len(params))(*params)
+    h = C.c_void_p()
+    rc = lib().sz_batch_create(C.c_void_p(ctx), len(params), arr, int(schedule), C.byref(h))
+    if rc:
+        raise SzError(rc, "sz_batch_create")
+    return h.value
+
+
+def sz_batch_compress(batch, d_in, d_out, caps, d_sizes: int, d_status: int, use_graph: bool = True,
+                      stream: int = 0) -> int:
+    n = len(d_in)
+    ins = (C.c_void_p * n)(*d_in)
+    outs = (C.c_void_p * n)(*d_out)
+    cp = (C.c_size_t * n)(*caps)
+    return lib().sz_batch_compress(C.c_void_p(batch), ins, outs, cp, C.c_void_p(d_sizes), C.c_void_p(d_status),
+                                   int(bool(use_graph)), C.c_void_p(stream))
+
+
+def sz_batch_info(batch):
+    """(schedule, sweep tiles, threads per sweep workgroup, tuned ms per candidate)."""
+    sched, tiles, thr = C.c_int(0), C.c_uint32(0), C.c_int(0)
+    ms = (C.c_double * 8)()
+    n = lib().sz_batch_info(C.c_void_p(batch), C.byref(sched), C.byref(tiles), C.byref(thr), ms, 8)
+    return sched.value, tiles.value, thr.value, [ms[i] for i in range(n)]
+
+
+def sz_batch_destroy(batch) -> None:
+    lib().sz_batch_destroy(C.c_void_p(batch))
+
+
+def sz_server_create(device: int, hbm_budget: int, slots: int) -> int:
+    h = C.c_void_p()
+    rc = lib().sz_server_create(int(device), int(hbm_budget), int(slots), C.byref(h))
+    if rc:
+        raise SzError(rc, "sz_server_create")
+    return h.value
+
+
+def sz_server_submit(server, req: SzRequest):
+    """Returns (rc, request id)."""
+    i = C.c_uint64(0)
+    rc = lib().sz_server_submit(C.c_void_p(server), C.byref(req), C.byref(i))
+    return rc, i.value
+
+
+def sz_server_wait(server, rid: int, timeout_ms: int = -1):
+    """Returns (rc, SzResult)."""
+    r = SzResult()
+    rc = lib().sz_server_wait(C.c_void_p(server), C.c_uint64(rid), C.byref(r), int(timeout_ms))
+    return rc, r
+
+
+def sz_server_stats(server) -> dict:
+    s = SzServerStats()
+    rc = lib().sz_server_stats(C.c_void_p(server), C.byref(s))
+    if rc:
+        raise SzError(rc, "sz_server_stats")
+    return s.as_dict()
+
+
+def sz_server_destroy(server) -> None:
+    lib().sz_server_destroy(C.c_void_p(server))
 
 
 # ------------------------------------------------------- torch conveniences
@@ -248,3 +352,120 @@ def quantize(x, m=8, stream=None, want_xprime=False, **kw):
         raise SzError(rc, "sz_quantize")
     c = codes[: x.numel()].view(x.shape).to(torch.int32) & 0xFFFF
     return (c, xp, st.as_dict()) if want_xprime else (c, st.as_dict())
+
+
+class Batch:
+    """Batched compression of a fixed list of field shapes (torch tensors).
+
+    ``kws`` is one keyword dict per field (those of ``make_params``); fields
+    must share one dtype.  ``compress(xs)`` returns the containers as uint8
+    tensor views, byte-identical to ``compress(x, **kw)`` field by field.
+    """
+
+    def __init__(self, shapes, dtype, kws, schedule=-1, device=0):
+        import torch
+        self.params = [make_params(tuple(s), dtype, **kw) for s, kw in zip(shapes, kws)]
+        self.caps = [sz_compress_bound(p) for p in self.params]
+        self.device = device
+        self.handle = sz_batch_create(context(device), self.params, schedule)
+        self.outs = [torch.empty(c, dtype=torch.uint8, device=f"cuda:{device}") for c in self.caps]
+        self.sizes = torch.zeros(len(shapes), dtype=torch.int64, device=f"cuda:{device}")
+        self.status = torch.zeros(len(shapes), dtype=torch.int32, device=f"cuda:{device}")
+
+    def compress_async(self, xs, use_graph=True, stream=None):
+        for x, p in zip(xs, self.params):
+            if not x.is_cuda or not x.is_contiguous() or tuple(x.shape) != tuple(p.dims[d] for d in range(p.ndim)):
+                raise ValueError("inputs must be contiguous device tensors of the planned shapes")
+        rc = sz_batch_compress(self.handle, [x.data_ptr() for x in xs], [o.data_ptr() for o in self.outs],
+                               self.caps, self.sizes.data_ptr(), self.status.data_ptr(), use_graph, _stream(stream))
+        if rc:
+            raise SzError(rc, "sz_batch_compress")
+
+    def compress(self, xs, use_graph=True, stream=None):
+        self.compress_async(xs, use_graph, stream)
+        st = self.status.cpu().tolist()
+        sz = self.sizes.cpu().tolist()
+        for i, s in enumerate(st):
+            if s:
+                raise SzError(s, f"sz_batch_compress field {i}")
+        return [o[:n] for o, n in zip(self.outs, sz)]
+
+    def info(self):
+        return sz_batch_info(self.handle)
+
+    def close(self):
+        if self.handle:
+            sz_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request server with continuous batching over torch device tensors.
+
+    ``submit_compress(x, out, **kw)`` / ``submit_decompress(comp, out)``
+    queue a request and return its id; ``wait(id)`` returns the result dict
+    (status, out_size, t_submit, t_admit, t_done on the server clock).  The
+    tensors must stay alive until ``wait`` returns.
+    """
+
+    def __init__(self, hbm_budget: int, slots: int = 4, device: int = 0):
+        self.handle = sz_server_create(device, hbm_budget, slots)
+        self._keep = {}
+
+    def submit_compress(self, x, out, **kw):
+        r = SzRequest()
+        r.op = SZ_REQ_COMPRESS
+        r.params = make_params(tuple(x.shape), x.dtype, **kw)
+        r.d_in = x.data_ptr()
+        r.d_out = out.data_ptr()
+        r.out_cap = out.numel() * out.element_size()
+        rc, rid = sz_server_submit(self.handle, r)
+        if rc:
+            raise SzError(rc, "sz_server_submit")
+        self._keep[rid] = (x, out)
+        return rid
+
+    def submit_decompress(self, comp, out, header: bytes = None):
+        r = SzRequest()
+        r.op = SZ_REQ_DECOMPRESS
+        r.d_in = comp.data_ptr()
+        r.in_bytes = comp.numel()
+        hb = None
+        if header is not None:
+            hb = (C.c_uint8 * len(header)).from_buffer_copy(header)
+            r.h_header = C.cast(hb, C.c_void_p).value
+        r.d_out = out.data_ptr()
+        r.out_cap = out.numel() * out.element_size()
+        rc, rid = sz_server_submit(self.handle, r)
+        if rc:
+            raise SzError(rc, "sz_server_submit")
+        self._keep[rid] = (comp, out, hb)
+        return rid
+
+    def wait(self, rid, timeout_ms=-1):
+        rc, r = sz_server_wait(self.handle, rid, timeout_ms)
+        if rc:
+            raise SzError(rc, "sz_server_wait")
+        self._keep.pop(rid, None)
+        return r.as_dict()
+
+    def stats(self):
+        return sz_server_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            sz_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -8,6 +8,9 @@
 #include "sweep.hpp"
 
 namespace szh {
+// Internal linkage: every translation unit that launches these kernels
+// carries its own copy.
+namespace {
 
 // ------------------------------------------------------------ block scans
 // Exclusive scan over a workgroup of NT threads (NT a multiple of 64).
@@ -59,13 +62,17 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, uint64_t n) {
 
 // Zero the first plan->total bytes of the container (sections are written
 // with OR operations and padding must read as zero).
-__global__ void zero_container_kernel(uint32_t* out, const DevPlan* P) {
+__device__ __forceinline__ void zero_container_kernel_dev(uint32_t* out, const DevPlan* P) {
   if (P->status || P->raw) return;
   const uint64_t nw = (P->total + 3) / 4;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw;
        i += (uint64_t)gridDim.x * blockDim.x)
     out[i] = 0;
 }
+__global__ void zero_container_kernel(uint32_t* out, const DevPlan* P) {
+  zero_container_kernel_dev(out, P);
+}
+
 
 struct PlanInit {
   uint32_t m;        // 16 for the first adaptive sweep
@@ -75,7 +82,7 @@ struct PlanInit {
   uint64_t cap;
 };
 
-__global__ void plan_init_kernel(DevPlan* P, PlanInit I) {
+__device__ __forceinline__ void plan_init_kernel_dev(DevPlan* P, PlanInit I) {
   if (threadIdx.x == 0) {
     DevPlan z = {};
     z.m = I.m;
@@ -87,6 +94,10 @@ __global__ void plan_init_kernel(DevPlan* P, PlanInit I) {
     *P = z;
   }
 }
+__global__ void plan_init_kernel(DevPlan* P, PlanInit I) {
+  plan_init_kernel_dev(P, I);
+}
+
 
 // Order-preserving integer images of floating-point values.
 __device__ __forceinline__ uint32_t ord32(float f) {
@@ -118,7 +129,7 @@ __device__ __forceinline__ void mm_update(T f, T& mn, T& mx, uint32_t& nf) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) minmax_kernel(const T* __restrict__ x, uint64_t n, DevPlan* P) {
+__device__ __forceinline__ void minmax_kernel_dev(const T* __restrict__ x, uint64_t n, DevPlan* P) {
   __shared__ uint64_t lmin[4], lmax[4];
   __shared__ uint32_t lnf;
   if (threadIdx.x == 0) lnf = 0;
@@ -179,11 +190,16 @@ __global__ void __launch_bounds__(256) minmax_kernel(const T* __restrict__ x, ui
     if (lnf) atomicOr(&P->nonfinite, 1u);
   }
 }
+template <typename T>
+__global__ void __launch_bounds__(256) minmax_kernel(const T* __restrict__ x, uint64_t n, DevPlan* P) {
+  minmax_kernel_dev<T>(x, n, P);
+}
+
 
 // Error bound in the element type: eb (double) rounded toward zero into T,
 // 2eb = eb + eb and 1/(2eb), each one IEEE operation in T (Metric 1).
 template <typename T>
-__global__ void eb_resolve_kernel(DevPlan* P, PlanInit I) {
+__device__ __forceinline__ void eb_resolve_kernel_dev(DevPlan* P, PlanInit I) {
   using U = typename FTr<T>::U;
   if (threadIdx.x != 0 || P->status) return;
   double eb = I.eb_abs;
@@ -220,10 +236,15 @@ __global__ void eb_resolve_kernel(DevPlan* P, PlanInit I) {
   P->twoeb_bits = (uint64_t)to_bits<T>(two);
   P->inv2eb_bits = (uint64_t)to_bits<T>(inv);
 }
+template <typename T>
+__global__ void eb_resolve_kernel(DevPlan* P, PlanInit I) {
+  eb_resolve_kernel_dev<T>(P, I);
+}
+
 
 // Adaptive interval count (Sec. IV-B): from the 2^16-code histogram, the
 // smallest m whose intervals |k| <= 2^(m-1) - 1 hold theta * N points.
-__global__ void __launch_bounds__(1024) pick_m_kernel(uint32_t* hist, DevPlan* P, uint64_t n, double theta) {
+__device__ __forceinline__ void pick_m_kernel_dev(uint32_t* hist, DevPlan* P, uint64_t n, double theta) {
   __shared__ unsigned long long bucket[17];
   if (P->status) return;
   if (threadIdx.x < 17) bucket[threadIdx.x] = 0;
@@ -258,6 +279,10 @@ __global__ void __launch_bounds__(1024) pick_m_kernel(uint32_t* hist, DevPlan* P
   if (s_m < 16)
     for (int i = threadIdx.x; i < 65536; i += blockDim.x) hist[i] = 0;
 }
+__global__ void __launch_bounds__(1024) pick_m_kernel(uint32_t* hist, DevPlan* P, uint64_t n, double theta) {
+  pick_m_kernel_dev(hist, P, n, theta);
+}
+
 
 // ------------------------------------------------------------ sorting
 // Bitonic sort of n (power of two) 64-bit keys held at `k` (LDS or global)
@@ -304,7 +329,7 @@ constexpr uint32_t kCbLdsSyms = 2048;
 // jumping over the parent links; lengths above 27 are repaired by halving
 // every frequency (keeping it >= 1) and rebuilding.  Canonical codes follow
 // in (length, symbol) order.
-__global__ void __launch_bounds__(kCbNT) codebook_kernel(CodebookArgs A) {
+__device__ __forceinline__ void codebook_kernel_dev(CodebookArgs A) {
   DevPlan* P = A.plan;
   if (P->status) return;
   __shared__ uint64_t s_keys[kCbLdsSyms];
@@ -466,6 +491,10 @@ __global__ void __launch_bounds__(kCbNT) codebook_kernel(CodebookArgs A) {
     P->m_suggested = (hr < A.theta && m < 16) ? m + 1 : m;
   }
 }
+__global__ void __launch_bounds__(kCbNT) codebook_kernel(CodebookArgs A) {
+  codebook_kernel_dev(A);
+}
+
 
 // ---------------------------------------------------------- bit helpers
 // Stream bit b sits in word b/32 at bit 31 - b%32 (MSB first).
@@ -540,7 +569,7 @@ __device__ __forceinline__ uint32_t wave_exscan(uint32_t v) { return wave_inscan
 constexpr uint32_t kHistLds = 16384;
 
 template <typename CT>
-__global__ void __launch_bounds__(1024) hist_kernel(const CT* __restrict__ codes, uint64_t n, uint32_t* hist,
+__device__ __forceinline__ void hist_kernel_dev(const CT* __restrict__ codes, uint64_t n, uint32_t* hist,
                                                     const DevPlan* P, uint32_t pass2) {
   __shared__ uint32_t h[kHistLds];
   if (P->status) return;
@@ -589,6 +618,12 @@ __global__ void __launch_bounds__(1024) hist_kernel(const CT* __restrict__ codes
   for (uint32_t i = threadIdx.x; i < W; i += 1024)
     if (h[i]) atomicAdd(&hist[wbase + i], h[i]);
 }
+template <typename CT>
+__global__ void __launch_bounds__(1024) hist_kernel(const CT* __restrict__ codes, uint64_t n, uint32_t* hist,
+                                                    const DevPlan* P, uint32_t pass2) {
+  hist_kernel_dev<CT>(codes, n, hist, P, pass2);
+}
+
 
 // Four consecutive codes starting at i (a multiple of 4), as one 4- or
 // 8-byte load; codes at or past n read as 0.
@@ -707,7 +742,7 @@ __device__ __forceinline__ void chunk_stats_body(const CT* __restrict__ codes, c
 }
 
 template <typename T, typename CT>
-__global__ void __launch_bounds__(256) chunk_stats_kernel(const CT* __restrict__ codes, const T* __restrict__ x,
+__device__ __forceinline__ void chunk_stats_kernel_dev(const CT* __restrict__ codes, const T* __restrict__ x,
                                                           const uint8_t* __restrict__ len, uint64_t n,
                                                           uint32_t C, uint32_t* cbits, uint32_t* cu,
                                                           uint32_t* ctb, const DevPlan* P) {
@@ -726,10 +761,18 @@ __global__ void __launch_bounds__(256) chunk_stats_kernel(const CT* __restrict__
   else
     chunk_stats_body<T, CT, false>(codes, x, len, s_tab, sc, n, C, cbits, cu, ctb, ebb);
 }
+template <typename T, typename CT>
+__global__ void __launch_bounds__(256) chunk_stats_kernel(const CT* __restrict__ codes, const T* __restrict__ x,
+                                                          const uint8_t* __restrict__ len, uint64_t n,
+                                                          uint32_t C, uint32_t* cbits, uint32_t* cu,
+                                                          uint32_t* ctb, const DevPlan* P) {
+  chunk_stats_kernel_dev<T, CT>(codes, x, len, n, C, cbits, cu, ctb, P);
+}
+
 
 // ------------------------------------------ device-wide exclusive scans
 // Phase 1: per-workgroup sums of 4096-element tiles.
-__global__ void __launch_bounds__(1024) scan_tile_sums(const uint32_t* __restrict__ in, uint64_t n, uint64_t* tsum) {
+__device__ __forceinline__ void scan_tile_sums_dev(const uint32_t* __restrict__ in, uint64_t n, uint64_t* tsum) {
   __shared__ uint64_t red[16];
   const uint64_t t0 = (uint64_t)blockIdx.x * 4096;
   uint64_t s = 0;
@@ -740,8 +783,12 @@ __global__ void __launch_bounds__(1024) scan_tile_sums(const uint32_t* __restric
   s = block_sum<1024, uint64_t>(s, red);
   if (threadIdx.x == 0) tsum[blockIdx.x] = s;
 }
+__global__ void __launch_bounds__(1024) scan_tile_sums(const uint32_t* __restrict__ in, uint64_t n, uint64_t* tsum) {
+  scan_tile_sums_dev(in, n, tsum);
+}
+
 // Phase 2: one workgroup scans the tile sums in place; total to *total.
-__global__ void __launch_bounds__(1024) scan_tile_offsets(uint64_t* tsum, uint64_t ntiles, uint64_t* total) {
+__device__ __forceinline__ void scan_tile_offsets_dev(uint64_t* tsum, uint64_t ntiles, uint64_t* total) {
   __shared__ uint64_t red[16];
   const uint64_t per = (ntiles + 1023) / 1024;
   const uint64_t lo = min(ntiles, (uint64_t)threadIdx.x * per), hi = min(ntiles, lo + per);
@@ -756,8 +803,12 @@ __global__ void __launch_bounds__(1024) scan_tile_offsets(uint64_t* tsum, uint64
   }
   if (threadIdx.x == 0 && total) *total = tot;
 }
+__global__ void __launch_bounds__(1024) scan_tile_offsets(uint64_t* tsum, uint64_t ntiles, uint64_t* total) {
+  scan_tile_offsets_dev(tsum, ntiles, total);
+}
+
 // Phase 3: exclusive prefix of every element.
-__global__ void __launch_bounds__(1024) scan_apply(const uint32_t* __restrict__ in, uint64_t n, const uint64_t* tsum,
+__device__ __forceinline__ void scan_apply_dev(const uint32_t* __restrict__ in, uint64_t n, const uint64_t* tsum,
                                                    uint64_t* out) {
   __shared__ uint64_t red[16];
   const uint64_t t0 = (uint64_t)blockIdx.x * 4096;
@@ -771,6 +822,11 @@ __global__ void __launch_bounds__(1024) scan_apply(const uint32_t* __restrict__ 
     base += tot;
   }
 }
+__global__ void __launch_bounds__(1024) scan_apply(const uint32_t* __restrict__ in, uint64_t n, const uint64_t* tsum,
+                                                   uint64_t* out) {
+  scan_apply_dev(in, n, tsum, out);
+}
+
 
 // --------------------------------------- container layout (after scans)
 struct LayoutArgs {
@@ -784,7 +840,7 @@ struct LayoutArgs {
 };
 __device__ __forceinline__ uint64_t align64(uint64_t v) { return (v + 63) & ~63ull; }
 
-__global__ void layout_kernel(LayoutArgs A) {
+__device__ __forceinline__ void layout_kernel_dev(LayoutArgs A) {
   DevPlan* P = A.plan;
   if (threadIdx.x || P->status) return;
   P->huff_bits = *A.tot_bits;
@@ -800,6 +856,10 @@ __global__ void layout_kernel(LayoutArgs A) {
   if (P->raw) P->total = A.raw_size;
   if (P->total > P->out_cap) P->status = SZ_ECAPACITY;
 }
+__global__ void layout_kernel(LayoutArgs A) {
+  layout_kernel_dev(A);
+}
+
 
 // ------------------------------------------------------- K5c: encoding
 // One wave per chunk: the chunk's codes are staged in LDS, lane offsets come
@@ -906,7 +966,7 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
 }
 
 template <typename T, typename CT>
-__global__ void __launch_bounds__(kEncNT) encode_kernel(const CT* __restrict__ codes, const T* __restrict__ x,
+__device__ __forceinline__ void encode_kernel_dev(const CT* __restrict__ codes, const T* __restrict__ x,
                                                         const uint8_t* __restrict__ len,
                                                         const uint32_t* __restrict__ cw, uint64_t n, uint32_t C,
                                                         const uint32_t* cbits, const uint64_t* boff,
@@ -928,6 +988,16 @@ __global__ void __launch_bounds__(kEncNT) encode_kernel(const CT* __restrict__ c
   else
     encode_body<T, CT, false>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P);
 }
+template <typename T, typename CT>
+__global__ void __launch_bounds__(kEncNT) encode_kernel(const CT* __restrict__ codes, const T* __restrict__ x,
+                                                        const uint8_t* __restrict__ len,
+                                                        const uint32_t* __restrict__ cw, uint64_t n, uint32_t C,
+                                                        const uint32_t* cbits, const uint64_t* boff,
+                                                        const uint64_t* uoff, const uint64_t* toff,
+                                                        uint8_t* out, const DevPlan* P) {
+  encode_kernel_dev<T, CT>(codes, x, len, cw, n, C, cbits, boff, uoff, toff, out, P);
+}
+
 
 // -------------------------------------------------- K7: header + codebook
 struct HeaderArgs {
@@ -944,7 +1014,7 @@ __device__ __forceinline__ void put64(uint8_t* b, uint64_t v) {
   for (int i = 0; i < 8; i++) b[i] = (uint8_t)(v >> (8 * i));
 }
 
-__global__ void __launch_bounds__(256) header_kernel(HeaderArgs A) {
+__device__ __forceinline__ void header_kernel_dev(HeaderArgs A) {
   __shared__ uint8_t h[kHdr];
   __shared__ uint32_t red[8];
   const DevPlan* P = A.plan;
@@ -999,9 +1069,13 @@ __global__ void __launch_bounds__(256) header_kernel(HeaderArgs A) {
     pos++;
   }
 }
+__global__ void __launch_bounds__(256) header_kernel(HeaderArgs A) {
+  header_kernel_dev(A);
+}
+
 
 template <typename T>
-__global__ void raw_copy_kernel(const T* __restrict__ x, uint8_t* out, uint64_t n, const DevPlan* P) {
+__device__ __forceinline__ void raw_copy_kernel_dev(const T* __restrict__ x, uint8_t* out, uint64_t n, const DevPlan* P) {
   if (P->status || !P->raw) return;
   const uint64_t bytes = n * sizeof(T);
   uint8_t* dst = out + kHdr;
@@ -1013,13 +1087,22 @@ __global__ void raw_copy_kernel(const T* __restrict__ x, uint8_t* out, uint64_t 
        i += (uint64_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
 }
+template <typename T>
+__global__ void raw_copy_kernel(const T* __restrict__ x, uint8_t* out, uint64_t n, const DevPlan* P) {
+  raw_copy_kernel_dev<T>(x, out, n, P);
+}
+
 
 // Final status/size words for the asynchronous entry point.
-__global__ void finish_kernel(const DevPlan* P, uint64_t* d_size, int32_t* d_status) {
+__device__ __forceinline__ void finish_kernel_dev(const DevPlan* P, uint64_t* d_size, int32_t* d_status) {
   if (threadIdx.x) return;
   if (d_status) *d_status = P->status;
   if (d_size) *d_size = P->status ? 0 : P->total;
 }
+__global__ void finish_kernel(const DevPlan* P, uint64_t* d_size, int32_t* d_status) {
+  finish_kernel_dev(P, d_size, d_status);
+}
+
 
 // =================================================================== decode
 struct DecTables {
@@ -1319,4 +1402,5 @@ __global__ void check_total_kernel(const uint64_t* got, uint64_t want, DevPlan* 
   if (threadIdx.x == 0 && *got != want) set_status(P, SZ_ECORRUPT);
 }
 
+}  // namespace
 }  // namespace szh

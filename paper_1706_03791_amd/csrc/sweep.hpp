@@ -214,8 +214,25 @@ struct Exporters {
   }
 };
 
+// LDS of one workgroup of the sweep (taken from the dynamic allocation, so
+// that a batched kernel holding several sweep bodies needs only the largest).
 template <typename T, typename CT, int DIM, int NL, bool COMP, int RZ, int RY>
-__global__ void __launch_bounds__(RZ * RY) sweep_kernel(SweepArgs A) {
+struct SweepLds {
+  static constexpr int NT = RZ * RY;
+  static constexpr int R = ring_slots<NL>();
+  static constexpr int XZ = RZ + ((DIM == 3) ? NL : 0), XY = RY + ((DIM >= 2) ? NL : 0);
+  static constexpr size_t a16(size_t v) { return (v + 15) & ~(size_t)15; }
+  static constexpr size_t OFF_X = 0;
+  static constexpr size_t OFF_V = a16(OFF_X + sizeof(T) * R * XZ * XY);
+  static constexpr size_t OFF_C = a16(OFF_V + sizeof(T) * NT * kRing);
+  static constexpr size_t OFF_H = a16(OFF_C + sizeof(CT) * NT * kRing);
+  static constexpr size_t BYTES = a16(OFF_H + 4 * (COMP ? kHistWin : 1));
+};
+
+// One tile of the sweep, run by a workgroup of RZ * RY threads; `lds` is
+// SweepLds::BYTES of dynamic LDS.
+template <typename T, typename CT, int DIM, int NL, bool COMP, int RZ, int RY>
+__device__ __forceinline__ void sweep_body(const SweepArgs& A, const int tile, uint8_t* lds) {
   using U = typename FTr<T>::U;
   constexpr int NT = RZ * RY;
   constexpr int R = ring_slots<NL>();
@@ -234,11 +251,11 @@ __global__ void __launch_bounds__(RZ * RY) sweep_kernel(SweepArgs A) {
   constexpr int XEPL = 16 / (int)sizeof(T);
   constexpr int CEPL = 16 / (int)sizeof(CT);
 
-  __shared__ T xring[R][XZ][XY];
-  __shared__ __align__(16) T vring[NT][kRing];   // compress: input x; decompress: output x'
-  __shared__ __align__(16) CT cring[NT][kRing];  // codes (out for compress, in for decompress)
-  __shared__ uint32_t hl[COMP ? kHistWin : 1];
-  __shared__ int s_tile;
+  using LD = SweepLds<T, CT, DIM, NL, COMP, RZ, RY>;
+  auto& xring = *reinterpret_cast<T (*)[R][XZ][XY]>(lds + LD::OFF_X);
+  auto& vring = *reinterpret_cast<T (*)[NT][kRing]>(lds + LD::OFF_V);   // compress: input x; decompress: output x'
+  auto& cring = *reinterpret_cast<CT (*)[NT][kRing]>(lds + LD::OFF_C);  // codes (out for compress, in for decompress)
+  auto& hl = *reinterpret_cast<uint32_t (*)[COMP ? kHistWin : 1]>(lds + LD::OFF_H);
 
   DevPlan* P = A.plan;
   if (P->status != 0) return;
@@ -250,12 +267,10 @@ __global__ void __launch_bounds__(RZ * RY) sweep_kernel(SweepArgs A) {
   const int s = (DIM == 1) ? 0 : rz + ry;
   const Geom& g = A.g;
 
-  if (tid == 0) s_tile = (int)atomicAdd(A.ticket, 1u);
   for (int i = tid; i < R * XZ * XY; i += NT) (&xring[0][0][0])[i] = T(0);
   if (COMP)
     for (int i = tid; i < kHistWin; i += NT) hl[i] = 0;
   __syncthreads();
-  const int tile = s_tile;
 
   // ---- tile geometry
   int64_t zb0 = 0, zb1 = 1, yb0 = 0, yb1 = 1, xb0 = 0, xb1 = 0, z0 = 0, y0 = 0;
@@ -676,6 +691,18 @@ __global__ void __launch_bounds__(RZ * RY) sweep_kernel(SweepArgs A) {
     for (int i = tid; i < nb; i += NT)
       if (hl[i]) atomicAdd(&A.hist[wbase + i], hl[i]);
   }
+}
+
+// Single-field launch: tiles are claimed through the field's ticket in
+// dependence order.
+template <typename T, typename CT, int DIM, int NL, bool COMP, int RZ, int RY>
+__global__ void __launch_bounds__(RZ * RY) sweep_kernel(SweepArgs A) {
+  extern __shared__ __align__(16) uint8_t sz_lds[];
+  __shared__ int s_tile;
+  if (A.plan->status != 0 || (A.pass2 && !A.plan->rerun)) return;
+  if (threadIdx.x == 0) s_tile = (int)atomicAdd(A.ticket, 1u);
+  __syncthreads();
+  sweep_body<T, CT, DIM, NL, COMP, RZ, RY>(A, s_tile, sz_lds);
 }
 
 }  // namespace szh

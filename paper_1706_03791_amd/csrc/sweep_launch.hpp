@@ -18,13 +18,23 @@ template <> struct TileShape<double, 2> { static constexpr int RZ = 1, RY = 128;
 template <> struct TileShape<float, 1> { static constexpr int RZ = 1, RY = 256; };
 template <> struct TileShape<double, 1> { static constexpr int RZ = 1, RY = 128; };
 
+// Launches pass the body's LDS as dynamic LDS (raising the per-kernel limit
+// when a variant needs more than 64 KiB).
+template <typename T, typename CT, int DIM, int NL, bool COMP, int RZ, int RY>
+inline void launch_sweep_variant(const SweepArgs& a, int grid, hipStream_t st) {
+  constexpr size_t lds = SweepLds<T, CT, DIM, NL, COMP, RZ, RY>::BYTES;
+  auto k = sweep_kernel<T, CT, DIM, NL, COMP, RZ, RY>;
+  if (lds > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(RZ * RY), lds, st, a);
+}
+
 template <typename T, int DIM, int NL, bool COMP>
 inline hipError_t launch_one(int cw, const SweepArgs& a, int grid, hipStream_t st) {
   constexpr int RZ = TileShape<T, DIM>::RZ, RY = TileShape<T, DIM>::RY;
   if (cw == 1)
-    hipLaunchKernelGGL((sweep_kernel<T, uint8_t, DIM, NL, COMP, RZ, RY>), dim3(grid), dim3(RZ * RY), 0, st, a);
+    launch_sweep_variant<T, uint8_t, DIM, NL, COMP, RZ, RY>(a, grid, st);
   else
-    hipLaunchKernelGGL((sweep_kernel<T, uint16_t, DIM, NL, COMP, RZ, RY>), dim3(grid), dim3(RZ * RY), 0, st, a);
+    launch_sweep_variant<T, uint16_t, DIM, NL, COMP, RZ, RY>(a, grid, st);
   return hipGetLastError();
 }
 
@@ -56,25 +66,32 @@ template <> struct WaveShape<double> { static constexpr int NW = 8, AZ = 1; };
 inline int wave_az(int dtype) { return dtype == SZ_F32 ? WaveShape<float>::AZ : WaveShape<double>::AZ; }
 inline int wave_nw(int dtype) { return dtype == SZ_F32 ? WaveShape<float>::NW : WaveShape<double>::NW; }
 
+template <typename T, typename CT, bool COMP, bool DBG>
+inline void launch_wsweep_variant(const WArgs& a, int grid, hipStream_t st) {
+  constexpr int AZ = WaveShape<T>::AZ, NW = WaveShape<T>::NW;
+  constexpr size_t lds = WSweepLds<T, NW, AZ>::BYTES;
+  auto k = wsweep_kernel<T, CT, COMP, NW, AZ, DBG>;
+  if (lds > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(NW * 64), lds, st, a);
+}
+
 template <typename T>
 inline hipError_t launch_wsweep_t(bool comp, int cw, const WArgs& a, int grid, hipStream_t st) {
-  constexpr int AZ = WaveShape<T>::AZ, NW = WaveShape<T>::NW;
-  const dim3 b(NW * 64);
   if (comp && a.export_all) {
     if (cw == 1)
-      hipLaunchKernelGGL((wsweep_kernel<T, uint8_t, true, NW, AZ, true>), dim3(grid), b, 0, st, a);
+      launch_wsweep_variant<T, uint8_t, true, true>(a, grid, st);
     else
-      hipLaunchKernelGGL((wsweep_kernel<T, uint16_t, true, NW, AZ, true>), dim3(grid), b, 0, st, a);
+      launch_wsweep_variant<T, uint16_t, true, true>(a, grid, st);
   } else if (comp) {
     if (cw == 1)
-      hipLaunchKernelGGL((wsweep_kernel<T, uint8_t, true, NW, AZ, false>), dim3(grid), b, 0, st, a);
+      launch_wsweep_variant<T, uint8_t, true, false>(a, grid, st);
     else
-      hipLaunchKernelGGL((wsweep_kernel<T, uint16_t, true, NW, AZ, false>), dim3(grid), b, 0, st, a);
+      launch_wsweep_variant<T, uint16_t, true, false>(a, grid, st);
   } else {
     if (cw == 1)
-      hipLaunchKernelGGL((wsweep_kernel<T, uint8_t, false, NW, AZ, false>), dim3(grid), b, 0, st, a);
+      launch_wsweep_variant<T, uint8_t, false, false>(a, grid, st);
     else
-      hipLaunchKernelGGL((wsweep_kernel<T, uint16_t, false, NW, AZ, false>), dim3(grid), b, 0, st, a);
+      launch_wsweep_variant<T, uint16_t, false, false>(a, grid, st);
   }
   return hipGetLastError();
 }

@@ -159,9 +159,20 @@ __device__ __forceinline__ T rec_elem(u32x4 v, int a) {
     return __builtin_bit_cast(T, ((uint64_t)v[2 * a + 1] << 32) | v[2 * a]);
 }
 
+// LDS of one workgroup of the wave-tiled sweep (dynamic allocation).
+template <typename T, int NW, int AZ>
+struct WSweepLds {
+  static constexpr size_t OFF_RING = 0;
+  static constexpr size_t OFF_XW = OFF_RING + sizeof(T) * NW * AZ * kWRing * 64;
+  static constexpr size_t OFF_YIN = OFF_XW + sizeof(T) * 2 * NW * 2 * 64;
+  static constexpr size_t OFF_YOUT = OFF_YIN + 16 * NW * kWG;
+  static constexpr size_t BYTES = OFF_YOUT + 16 * NW * kWG;
+};
+
+// One tile of the wave-tiled sweep, run by a workgroup of NW waves; `lds` is
+// WSweepLds::BYTES of dynamic LDS.
 template <typename T, typename CT, bool COMP, int NW, int AZ, bool DBG>
-__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
-wsweep_kernel(WArgs A) {
+__device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint8_t* lds) {
   using U = typename FTr<T>::U;
   using CW = CWord<CT>;
   constexpr int G = kWG;
@@ -171,11 +182,13 @@ wsweep_kernel(WArgs A) {
   constexpr int EPP = 16 / (int)sizeof(T);        // values per piece
   static_assert(AZ * sizeof(T) <= 16, "one 16-byte exchange record per step");
 
-  __shared__ T s_ring[NW][AZ][kWRing][64];  // compress: input; decompress: output
-  __shared__ T s_xw[2][NW][2][64];          // last sub-row of each wave: [step parity][wave][out | moved][lane]
-  __shared__ u32x4 s_yin[NW][kWG];          // y-halo records of the group, one per step
-  __shared__ u32x4 s_yout[NW][kWG];         // lane 63's values of the group, one record per step
-  __shared__ int s_tile;
+  using LD = WSweepLds<T, NW, AZ>;
+  // per-row input (compress) or output (decompress) rings
+  auto& s_ring = *reinterpret_cast<T (*)[NW][AZ][kWRing][64]>(lds + LD::OFF_RING);
+  // last sub-row of each wave: [step parity][wave][out | moved][lane]
+  auto& s_xw = *reinterpret_cast<T (*)[2][NW][2][64]>(lds + LD::OFF_XW);
+  auto& s_yin = *reinterpret_cast<u32x4 (*)[NW][kWG]>(lds + LD::OFF_YIN);   // y-halo records, one per step
+  auto& s_yout = *reinterpret_cast<u32x4 (*)[NW][kWG]>(lds + LD::OFF_YOUT);  // lane 63's values, one per step
 
   DevPlan* P = A.plan;
   if (P->status != 0) return;
@@ -184,10 +197,8 @@ wsweep_kernel(WArgs A) {
   const int tid = threadIdx.x;
   const int w = tid >> 6, ly = tid & 63;
   const int wprev = w > 0 ? w - 1 : 0;
-  if (tid == 0) s_tile = (int)atomicAdd(A.ticket, 1u);
   for (int i = tid; i < 2 * NW * 2 * 64; i += NW * 64) (&s_xw[0][0][0][0])[i] = T(0);
   __syncthreads();
-  const int tile = s_tile;
 
   // ---- tile geometry
   const int per_blk = A.tz_per_blk * A.ty_per_blk;
@@ -642,6 +653,19 @@ wsweep_kernel(WArgs A) {
     else
       flush_values(a, q);
   }
+}
+
+// Single-field launch: tiles are claimed through the field's ticket in
+// dependence order.
+template <typename T, typename CT, bool COMP, int NW, int AZ, bool DBG>
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
+wsweep_kernel(WArgs A) {
+  extern __shared__ __align__(16) uint8_t sz_lds[];
+  __shared__ int s_tile;
+  if (A.plan->status != 0 || (A.pass2 && !A.plan->rerun)) return;
+  if (threadIdx.x == 0) s_tile = (int)atomicAdd(A.ticket, 1u);
+  __syncthreads();
+  wsweep_body<T, CT, COMP, NW, AZ, DBG>(A, s_tile, sz_lds);
 }
 
 }  // namespace szh
