@@ -31,7 +31,7 @@ HEADER = 192
 
 def sweep_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sweep.hpp", "common.hpp"):
+    for f in ("sweep.hpp", "wsweep.hpp", "sweep_launch.hpp", "common.hpp"):
         with open(os.path.join(ROOT, "paper_1706_03791_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -66,6 +66,132 @@ def cpu_baseline(x: np.ndarray, planes: int, kw: dict):
                       f"{t1 - t0:.2f} s + decompress {t2 - t1:.2f} s, single thread"}
 
 
+def bench_batched(Z, torch, count=64, reps=5):
+    """Batched form on the uneven 64-field mix (32 square 2D fields of side
+    512..4096, 32 cubes of side 64..384, f32, per-field relative bounds
+    1e-5..1e-3): autotuned persistent launch replayed as a HIP graph, against
+    plain per-field sz_compress calls, with a byte-for-byte check per field."""
+    import fieldgen as F
+    import fieldgen.gpu as G
+    specs = F.batch_fields(count)
+    xs = [G.batch_field(s) for s in specs]
+    kws = [dict(layers=1, m=8, eb_mode="rel", eb_rel=s["eb_rel"]) for s in specs]
+    total = sum(x.numel() * x.element_size() for x in xs)
+    ctx = Z.context(0)
+    st = torch.cuda.current_stream().cuda_stream
+    params = [Z.make_params(tuple(x.shape), "float32", **kw) for x, kw in zip(xs, kws)]
+    caps = [Z.sz_compress_bound(p) for p in params]
+    outs = [torch.empty(c, dtype=torch.uint8, device="cuda") for c in caps]
+    sizes = [0] * len(xs)
+
+    def plain():
+        for i in range(len(xs)):
+            rc, sizes[i], _ = Z.sz_compress(ctx, params[i], xs[i].data_ptr(), outs[i].data_ptr(), caps[i], st)
+            if rc:
+                raise Z.SzError(rc, "sz_compress")
+
+    plain()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plain()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / reps
+
+    B = Z.Batch([x.shape for x in xs], "float32", kws, schedule=-1)
+    t0 = time.perf_counter()
+    B.compress_async(xs)  # autotunes, then captures the graph
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t0
+    B.compress_async(xs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        B.compress_async(xs)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    bsz = B.sizes.cpu().tolist()
+    bst = B.status.cpu().tolist()
+    exact = all(s == 0 for s in bst) and all(
+        bsz[i] == sizes[i] and torch.equal(B.outs[i][: sizes[i]], outs[i][: sizes[i]]) for i in range(len(xs)))
+    sched, tiles, threads, ms = B.info()
+    B.close()
+    return {"fields": len(xs), "input_bytes": int(total), "plain_ms": round(t_plain * 1e3, 3),
+            "batched_ms": round(t_batch * 1e3, 3), "plain_GBps": round(total / t_plain / 1e9, 3),
+            "batched_GBps": round(total / t_batch / 1e9, 3), "speedup": round(t_plain / t_batch, 3),
+            "bit_exact_vs_plain": bool(exact), "schedule": sched, "sweep_tiles": tiles,
+            "threads_per_sweep_wg": threads, "tune_ms": [round(v, 3) for v in ms],
+            "tune_wall_s": round(t_tune, 3), "graph": True}
+
+
+def bench_served(Z, torch, rates=(50, 500), durations=(2.0, 0.4), slots=8, budget=24 << 30):
+    """Served form: Poisson arrivals of compress/decompress requests (sizes
+    lognormal, median 32 MB, clipped to [1 MB, 2 GB], 80/20 f32/f64, 1-3D,
+    relative bounds 1e-6..1e-3) through the request server with `slots`
+    concurrent slots, against the same server with one slot (a plain
+    sequential FIFO).  Latency = completion - arrival."""
+    import fieldgen as F
+    import fieldgen.gpu as G
+    out = {"slots": slots, "hbm_budget_bytes": int(budget), "rates": []}
+    for k, (rate, duration) in enumerate(zip(rates, durations)):
+        reqs = F.request_stream(rate, duration, seed=F.BASE_SEED + 40 + k)
+        print(f"[bench] served: rate {rate}/s, {len(reqs)} requests", file=sys.stderr, flush=True)
+        data = []
+        for r in reqs:
+            data.append(G.request_field(r))
+            torch.cuda.synchronize()
+        kws = [dict(layers=1, m=8, eb_mode="rel", eb_rel=r["eb_rel"]) for r in reqs]
+        print("[bench] served: inputs made", file=sys.stderr, flush=True)
+        comps = {}
+        for i, r in enumerate(reqs):
+            if r["op"] == "decompress":
+                comps[i] = Z.compress(data[i], **kws[i])[0].clone()
+        torch.cuda.synchronize()
+        print("[bench] served: containers made", file=sys.stderr, flush=True)
+        nbytes = sum(x.numel() * x.element_size() for x in data)
+        row = {"rate": rate, "duration_s": duration, "requests": len(reqs), "bytes": int(nbytes)}
+        for mode, ns in (("served", slots), ("sequential", 1)):
+            outs = []
+            for i, (r, x) in enumerate(zip(reqs, data)):
+                if r["op"] == "compress":
+                    cap = Z.sz_compress_bound(Z.make_params(tuple(x.shape), x.dtype, **kws[i]))
+                    outs.append(torch.empty(cap, dtype=torch.uint8, device="cuda"))
+                else:
+                    outs.append(torch.empty_like(x))
+            srv = Z.Server(budget, ns)
+            ids = []
+            t0 = time.perf_counter()
+            for i, r in enumerate(reqs):
+                dt = t0 + r["t"] - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                if r["op"] == "compress":
+                    ids.append(srv.submit_compress(data[i], outs[i], **kws[i]))
+                else:
+                    ids.append(srv.submit_decompress(comps[i], outs[i]))
+            res = []
+            for n_done, i in enumerate(ids):
+                res.append(srv.wait(i, timeout_ms=120000))
+                if n_done % 50 == 49:
+                    print(f"[bench] served: {mode} {n_done + 1} done", file=sys.stderr, flush=True)
+            stats = srv.stats()
+            print(f"[bench] served: {mode} finished", file=sys.stderr, flush=True)
+            srv.close()
+            bad = [x["status"] for x in res if x["status"]]
+            lat = np.array([x["t_done"] - x["t_submit"] for x in res]) * 1e3
+            span = max(x["t_done"] for x in res) - min(x["t_submit"] for x in res)
+            row[mode] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+                         "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                         "GBps": round(nbytes / span / 1e9, 3), "errors": len(bad),
+                         "max_in_flight": stats["max_in_flight"],
+                         "pool_peak_bytes": stats["pool_peak_bytes"]}
+            del outs
+        out["rates"].append(row)
+        del data, comps
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +200,10 @@ def main():
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-planes", type=int, default=32)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="only run a plain 512 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -82,15 +212,25 @@ def main():
 
     import torch
     import fieldgen as F
+    import fieldgen.gpu as G
     import paper_1706_03791_amd as Z
+
+    if args.copy_ref:
+        a = torch.ones(1 << 27, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_ref_bytes": a.numel() * 4, "launches": 3}), flush=True)
+        return
 
     n = args.size
     kw = dict(layers=1, m=8, eb_mode="rel", eb_rel=1e-4)
     print(f"[bench] generating {n}^3 field", file=sys.stderr, flush=True)
-    x = F.cosmo3d((n, n, n))
-    S = x.nbytes
-    xd = torch.from_numpy(x).cuda()
-    p = Z.make_params(x.shape, "float32", **kw)
+    xd = G.cosmo3d((n, n, n), F.BASE_SEED + 2)
+    torch.cuda.synchronize()
+    S = xd.numel() * xd.element_size()
+    p = Z.make_params(tuple(xd.shape), "float32", **kw)
     cap = Z.sz_compress_bound(p)
     comp = torch.empty(cap, dtype=torch.uint8, device="cuda")
     out = torch.empty_like(xd)
@@ -138,8 +278,12 @@ def main():
 
     # dominant kernel stage and its algorithmic bytes per launch
     per_call = {k: (ms / calls if calls else 0.0) for k, (ms, calls) in prof.items()}
-    alg_per_stage = {"range": S, "sweep_compress": S, "encode": Cb, "decode": Cb,
-                     "sweep_decompress": S, "unpred": 0, "dectab": 0, "codebook": 0}
+    # algorithmic bytes per launch: the sweep reads the field and writes one
+    # code byte per point (m = 8); the reconstruction reads the codes and
+    # writes the field; the coder reads the codes and writes the container
+    npts = S // 4
+    alg_per_stage = {"range": S, "sweep_compress": S + npts, "encode": npts + Cb, "decode": Cb + npts,
+                     "sweep_decompress": npts + S, "unpred": 0, "dectab": 0, "codebook": 0, "hist": npts}
     dom = max(("sweep_compress", "sweep_decompress", "encode", "decode", "range"), key=lambda k: per_call[k])
     dom_ms = per_call[dom]
     achieved = alg_per_stage[dom] / (dom_ms / 1e3) / 1e9
@@ -159,8 +303,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"cosmo3d {n}^3 f32 lognormal density (GRF k^-3, std 1.5), 1-layer, "
-                               f"m=8, eb_rel=1e-4, compress+decompress", "n_points": int(x.size),
-                   "field_bytes": int(S)},
+                               f"m=8, eb_rel=1e-4, compress+decompress", "n_points": int(xd.numel()),
+                   "field_bytes": int(S), "generator": "fieldgen.gpu.cosmo3d (torch, seed 20170614)"},
         "compress_GBps": round(S / t_c / 1e9, 3),
         "decompress_GBps": round(S / t_d / 1e9, 3),
         "hbm_frac": round(hbm_frac, 4),
@@ -174,9 +318,19 @@ def main():
                      "algorithmic_bytes_per_launch": int(alg_per_stage[dom]),
                      "launch_ms": round(dom_ms, 4)},
     }
+    x_slab = xd[: args.cpu_planes].cpu().numpy() if not args.no_cpu_baseline else None
+    del xd, out, comp
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        print("[bench] batched form", file=sys.stderr, flush=True)
+        res["batched"] = bench_batched(Z, torch)
+    if not args.no_served:
+        print("[bench] served form", file=sys.stderr, flush=True)
+        res["served"] = bench_served(Z, torch)
+        res["p99_latency_served_ms"] = res["served"]["rates"][-1]["served"]["p99_ms"]
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(x, args.cpu_planes, kw)
+        res["cpu_baseline"] = cpu_baseline(x_slab, args.cpu_planes, kw)
     print(json.dumps(res), flush=True)
 
 

@@ -128,7 +128,8 @@ const char* sz_strerror(int code);
  * sz_ctx_profile_read fills up to n accumulated milliseconds and call
  * counts, in the order: value range + bound, compression sweep, codebook,
  * encoding + container, decode tables, Huffman decode, unpredictable values,
- * reconstruction sweep.  Returns the number of stages. */
+ * reconstruction sweep, code histogram (when it is a kernel of its own).
+ * Returns the number of stages. */
 int sz_ctx_profile(sz_ctx* ctx, int enable);
 int sz_ctx_profile_read(sz_ctx* ctx, double* ms, uint64_t* calls, int n);
 

@@ -27,7 +27,8 @@ EXPORTS = ("sz_ctx_create", "sz_ctx_destroy", "sz_compress_bound", "sz_compress"
            "sz_ctx_profile_read", "sz_batch_create", "sz_batch_compress", "sz_batch_info",
            "sz_batch_destroy", "sz_server_create", "sz_server_submit", "sz_server_wait", "sz_server_stats",
            "sz_server_destroy")
-STAGES = ("range", "sweep_compress", "codebook", "encode", "dectab", "decode", "unpred", "sweep_decompress")
+STAGES = ("range", "sweep_compress", "codebook", "encode", "dectab", "decode", "unpred", "sweep_decompress",
+          "hist")
 
 
 class SzParams(C.Structure):

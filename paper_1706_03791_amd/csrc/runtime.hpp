@@ -28,6 +28,7 @@ enum Stage {
   ST_DECODE,         // Huffman decode + row-segment offsets
   ST_UNPRED,         // unpredictable values
   ST_SWEEP_D,        // reconstruction sweep
+  ST_HIST,           // code histogram (wave-tiled sweep with fixed m)
   ST_COUNT
 };
 
@@ -425,10 +426,17 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
   a.pass2 = 0;
   a.export_all = debug_codes_only ? 1 : 0;
   stage_begin(ctx, ST_SWEEP_C, st);
+  int sweep_stage_open = ST_SWEEP_C;
   if (L.wave) {
     WArgs wa = make_wargs(L, d_in, W.codes, W.xs, W.xchg, W.progress, W.ticket, P);
     wa.export_all = a.export_all;
     if ((rc = launch_wsweep(L, true, wa, st))) return rc;
+    if (!adaptive) {
+      // the sweep alone is timed; the histogram has a stage of its own
+      stage_end(ctx, ST_SWEEP_C, st);
+      stage_begin(ctx, ST_HIST, st);
+      sweep_stage_open = ST_HIST;
+    }
     launch_hist(L, W.codes, W.hist, P, 0, st);
     if (adaptive) {
       hipLaunchKernelGGL(pick_m_kernel, dim3(1), dim3(1024), 0, st, W.hist, P, (uint64_t)L.n, L.theta);
@@ -446,7 +454,7 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
       if ((rc = launch_sweep(L, true, a, st))) return rc;
     }
   }
-  stage_end(ctx, ST_SWEEP_C, st);
+  stage_end(ctx, sweep_stage_open, st);
   if (debug_codes_only) return SZ_OK;
   CodebookArgs cb;
   cb.hist = W.hist;
