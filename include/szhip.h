@@ -133,6 +133,41 @@ const char* sz_strerror(int code);
 int sz_ctx_profile(sz_ctx* ctx, int enable);
 int sz_ctx_profile_read(sz_ctx* ctx, double* ms, uint64_t* calls, int n);
 
+/* ---------------------------------------------------------------- analysis
+ * Error metrics of a reconstruction (Sec. II, Metric 2: RMSE, NRMSE, PSNR;
+ * Metric 3: Pearson correlation coefficient) and the autocorrelation of the
+ * compression errors (Sec. V), computed on the device in double precision
+ * with a fixed reduction order.  e_i = x_i - x'_i in double; value range R_X
+ * = max - min of the original; rmse = sqrt(mean e^2); nrmse = rmse / R_X;
+ * psnr = 20 log10(R_X / rmse); pearson = cov(X, X') / (sigma_X sigma_X').
+ * Autocorrelation at lag k (raster order): sum_{i+k<N} d_i d_{i+k} / sum d_i^2
+ * with d = e - mean(e). */
+typedef struct {
+  uint64_t n;
+  double value_min, value_max, value_range;
+  double max_abs_err, mean_err;
+  double rmse, nrmse, psnr, pearson;
+} sz_quality_t;
+
+/* d_orig and d_recon hold n (>= 2) elements of dtype; max_lag in [0, 255]
+ * autocorrelation coefficients (lags 1..max_lag) go to h_autocorr (host,
+ * may be NULL when max_lag is 0).  Synchronises `stream`; uses the
+ * context's scratch. */
+int sz_quality(sz_ctx* ctx, uint32_t dtype, uint64_t n, const void* d_orig, const void* d_recon,
+               uint32_t max_lag, double* h_autocorr, sz_quality_t* out, void* stream);
+
+/* Best-layer study (Sec. III-B, Table II): for n = 1..4 layers, the
+ * prediction hitting rate R_PH of a centred sub-block of the field (extents
+ * sample[d], slowest first; NULL or 0 = whole extent) with one interval
+ * around the prediction (the quantizer at m = 1: a point is predictable when
+ * it lies within the bound of its prediction), predicting from decompressed
+ * values (rph_decomp[n-1], the compressor's case) and from original values
+ * (rph_orig[n-1]).  The bound is that of the whole field under p's mode and
+ * values; p->layers and p->quant_bits are ignored.  *best_n is the n with the
+ * highest rph_decomp (the smallest such n on ties).  Synchronises `stream`. */
+int sz_layer_survey(sz_ctx* ctx, const sz_params* p, const void* d_in, const uint64_t* sample,
+                    double* rph_decomp, double* rph_orig, uint32_t* best_n, void* stream);
+
 /* ------------------------------------------------------------ batched form
  * Many fields of uneven shape compressed together (not a method of the
  * paper: a throughput form of the same per-field computation).  Every stage

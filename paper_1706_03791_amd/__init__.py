@@ -26,7 +26,7 @@ EXPORTS = ("sz_ctx_create", "sz_ctx_destroy", "sz_compress_bound", "sz_compress"
            "sz_inspect", "sz_decompress", "sz_quantize", "sz_strerror", "sz_ctx_profile",
            "sz_ctx_profile_read", "sz_batch_create", "sz_batch_compress", "sz_batch_info",
            "sz_batch_destroy", "sz_server_create", "sz_server_submit", "sz_server_wait", "sz_server_stats",
-           "sz_server_destroy")
+           "sz_server_destroy", "sz_quality", "sz_layer_survey")
 STAGES = ("range", "sweep_compress", "codebook", "encode", "dectab", "decode", "unpred", "sweep_decompress",
           "hist")
 
@@ -67,6 +67,15 @@ class SzServerStats(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("admitted", C.c_uint64), ("completed", C.c_uint64),
                 ("in_flight", C.c_uint32), ("max_in_flight", C.c_uint32), ("pool_bytes", C.c_uint64),
                 ("pool_peak_bytes", C.c_uint64), ("clock_s", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SzQuality(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("value_min", C.c_double), ("value_max", C.c_double),
+                ("value_range", C.c_double), ("max_abs_err", C.c_double), ("mean_err", C.c_double),
+                ("rmse", C.c_double), ("nrmse", C.c_double), ("psnr", C.c_double), ("pearson", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -116,6 +125,8 @@ def lib():
             L.sz_server_stats.argtypes = [vp, P(SzServerStats)]
             L.sz_server_destroy.argtypes = [vp]
             L.sz_server_destroy.restype = None
+            L.sz_quality.argtypes = [vp, C.c_uint32, C.c_uint64, vp, vp, C.c_uint32, vp, P(SzQuality), vp]
+            L.sz_layer_survey.argtypes = [vp, P(SzParams), vp, vp, vp, vp, P(C.c_uint32), vp]
             _lib = L
         return _lib
 
@@ -259,6 +270,28 @@ def sz_server_stats(server) -> dict:
 
 def sz_server_destroy(server) -> None:
     lib().sz_server_destroy(C.c_void_p(server))
+
+
+def sz_quality(ctx, dtype: int, n: int, d_orig: int, d_recon: int, max_lag: int = 0, stream: int = 0):
+    """Returns (rc, metrics dict, autocorrelation list of max_lag values)."""
+    q = SzQuality()
+    ac = (C.c_double * max(1, max_lag))()
+    rc = lib().sz_quality(C.c_void_p(ctx), int(dtype), int(n), C.c_void_p(d_orig), C.c_void_p(d_recon),
+                          int(max_lag), ac if max_lag else None, C.byref(q), C.c_void_p(stream))
+    return rc, q.as_dict(), [ac[i] for i in range(max_lag)]
+
+
+def sz_layer_survey(ctx, p: SzParams, d_in: int, sample=None, stream: int = 0):
+    """Returns (rc, rph_decomp[4], rph_orig[4], best_n)."""
+    smp = None
+    if sample is not None:
+        smp = (C.c_uint64 * 3)(*[int(v) for v in sample] + [0] * (3 - len(sample)))
+    dec = (C.c_double * 4)()
+    org = (C.c_double * 4)()
+    best = C.c_uint32(0)
+    rc = lib().sz_layer_survey(C.c_void_p(ctx), C.byref(p), C.c_void_p(d_in), smp, dec, org, C.byref(best),
+                               C.c_void_p(stream))
+    return rc, list(dec), list(org), best.value
 
 
 # ------------------------------------------------------- torch conveniences
@@ -470,3 +503,26 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def quality(x, xr, max_lag=0, stream=None):
+    """Error metrics of a reconstruction xr of x (device tensors of one dtype)."""
+    import torch
+    if x.shape != xr.shape or x.dtype != xr.dtype or not (x.is_contiguous() and xr.is_contiguous()):
+        raise ValueError("x and xr must be contiguous tensors of one shape and dtype")
+    rc, q, ac = sz_quality(context(x.device.index or 0), SZ_F32 if x.dtype == torch.float32 else SZ_F64,
+                           x.numel(), x.data_ptr(), xr.data_ptr(), max_lag, _stream(stream))
+    if rc:
+        raise SzError(rc, "sz_quality")
+    if max_lag:
+        q["autocorr"] = ac
+    return q
+
+
+def layer_survey(x, sample=None, stream=None, **kw):
+    """R_PH of n = 1..4 layers from decompressed and original values; best n."""
+    p = make_params(tuple(x.shape), x.dtype, **kw)
+    rc, dec, org, best = sz_layer_survey(context(x.device.index or 0), p, x.data_ptr(), sample, _stream(stream))
+    if rc:
+        raise SzError(rc, "sz_layer_survey")
+    return {"rph_decomp": dec, "rph_orig": org, "best_layers": best}
