@@ -282,7 +282,7 @@ int build_plan(sz_batch* b, int cand, BPlan& P) {
       s.rz = 1;
       s.ry = c.nt;
       s.nw = c.nt / 64;
-      s.az = wave_az(b->dtype);
+      s.az = wave_az(b->dtype, 3);
       if ((rc = resolve(&q, L, &s))) return rc;
     }
     L.cw = b->cw;  // one code width for the whole batch (bytes do not depend on it)

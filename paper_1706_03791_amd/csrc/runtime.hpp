@@ -118,9 +118,9 @@ inline Sched default_sched(int dtype, int ndim, int nl) {
   }();
   Sched s;
   tile_shape(dtype, ndim, s.rz, s.ry);
-  s.wave = ndim == 3 && nl == 1 && !legacy;
-  s.nw = wave_nw(dtype);
-  s.az = wave_az(dtype);
+  s.wave = (ndim == 3 || ndim == 2) && nl == 1 && !legacy;
+  s.nw = wave_nw(dtype, ndim);
+  s.az = wave_az(dtype, ndim);
   return s;
 }
 
@@ -198,9 +198,10 @@ int resolve(const sz_params* p, Layout& L, const Sched* sched_override = nullptr
   const uint64_t tile_span = (L.ndim == 3) ? (uint64_t)rz * L.dims3[1] * L.dims3[2]
                                            : (L.ndim == 2 ? (uint64_t)ry * L.dims3[2] : (uint64_t)ry * L.blk3[2]);
   if (L.xchg_bytes >= 0x7FFFFF00ull || (tile_span + 64) * L.ts >= 0x7FFFFF00ull) return SZ_EINVAL;
-  // 3D fields with the 1-layer predictor use the wave-tiled sweep: tiles of
-  // nw * az z-rows by 64 y-rows, one workgroup of nw waves each.
-  L.wave = sched.wave && L.ndim == 3 && L.nl == 1;
+  // 2D and 3D fields with the 1-layer predictor use the wave-tiled sweep:
+  // tiles of nw * az z-rows by 64 y-rows, one workgroup of nw waves each (a
+  // 2D field is the single z-row of a 1 x Y x X field).
+  L.wave = sched.wave && (L.ndim == 3 || L.ndim == 2) && L.nl == 1;
   L.az = 0;
   L.nw = 0;
   L.xy_bytes = 0;
@@ -218,9 +219,12 @@ int resolve(const sz_params* p, Layout& L, const Sched* sched_override = nullptr
     L.nsp = (uint32_t)(ceil_div(nsteps + kWLanes + tz + 4 * kWG, 16) * 16);
     L.ne = 0;
     L.xy_bytes = (uint64_t)g.ntiles * nw * L.nsp * 16;
-    const uint64_t xz_bytes = (uint64_t)g.ntiles * 2 * 64 * L.nsp * L.ts;
+    // z-exchange records only when a block holds several tiles along z
+    const uint64_t xz_bytes = g.tz_per_blk > 1 ? (uint64_t)g.ntiles * 2 * 64 * L.nsp * L.ts : 0;
     L.xchg_bytes = L.xy_bytes + xz_bytes;
-    const uint64_t span = ((uint64_t)tz + 1) * L.dims3[1] * L.dims3[2] + 4 * (tz + kWLanes + kWG);
+    // elements one tile's input and code descriptors span past their base
+    const uint64_t rows = L.ndim == 2 ? (uint64_t)kWLanes + 1 : ((uint64_t)tz + 1) * L.dims3[1];
+    const uint64_t span = rows * L.dims3[2] + 4 * (tz + kWLanes + kWG);
     if (L.xy_bytes >= 0x7FFFFF00ull || xz_bytes >= 0x7FFFFF00ull || span * L.ts >= 0x7FFFFF00ull ||
         span * L.cw >= 0x7FFFFF00ull)
       return SZ_EINVAL;
@@ -352,7 +356,8 @@ WArgs make_wargs(const Layout& L, const void* x, void* codes, void* xo, void* xc
 }
 
 int launch_wsweep(const Layout& L, bool comp, const WArgs& a, hipStream_t st) {
-  const hipError_t e = L.dtype == SZ_F32 ? wsweep_f32(comp, L.cw, a, L.grid, st) : wsweep_f64(comp, L.cw, a, L.grid, st);
+  const hipError_t e = L.dtype == SZ_F32 ? wsweep_f32(comp, L.cw, L.nw, L.az, a, L.grid, st)
+                                         : wsweep_f64(comp, L.cw, L.nw, L.az, a, L.grid, st);
   return e == hipSuccess ? SZ_OK : SZ_EHIP;
 }
 

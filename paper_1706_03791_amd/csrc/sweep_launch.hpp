@@ -57,47 +57,61 @@ hipError_t sweep_f64_d1(int nl, bool comp, int cw, const SweepArgs& a, int grid,
 hipError_t sweep_f64_d2(int nl, bool comp, int cw, const SweepArgs& a, int grid, hipStream_t st);
 hipError_t sweep_f64_d3(int nl, bool comp, int cw, const SweepArgs& a, int grid, hipStream_t st);
 
-// Wave-tiled sweep (3D, one layer): waves per workgroup and z sub-rows per
-// lane for each element type (two waves per SIMD; one 16-byte exchange
-// record per step).
+// Wave-tiled sweep (one layer): waves per workgroup and z sub-rows per lane.
+// 3D fields take NW waves of AZ sub-rows for each element type (two waves
+// per SIMD; one 16-byte exchange record per step); 2D fields, a single z-row,
+// take one wave per tile.
 template <typename T> struct WaveShape;
 template <> struct WaveShape<float> { static constexpr int NW = 8, AZ = 2; };
 template <> struct WaveShape<double> { static constexpr int NW = 8, AZ = 1; };
-inline int wave_az(int dtype) { return dtype == SZ_F32 ? WaveShape<float>::AZ : WaveShape<double>::AZ; }
-inline int wave_nw(int dtype) { return dtype == SZ_F32 ? WaveShape<float>::NW : WaveShape<double>::NW; }
+inline int wave_az(int dtype, int ndim) {
+  return ndim == 2 ? 1 : (dtype == SZ_F32 ? WaveShape<float>::AZ : WaveShape<double>::AZ);
+}
+inline int wave_nw(int dtype, int ndim) {
+  return ndim == 2 ? 1 : (dtype == SZ_F32 ? WaveShape<float>::NW : WaveShape<double>::NW);
+}
 
-template <typename T, typename CT, bool COMP, bool DBG>
+template <typename T, typename CT, bool COMP, bool DBG, int NW, int AZ>
 inline void launch_wsweep_variant(const WArgs& a, int grid, hipStream_t st) {
-  constexpr int AZ = WaveShape<T>::AZ, NW = WaveShape<T>::NW;
   constexpr size_t lds = WSweepLds<T, NW, AZ>::BYTES;
   auto k = wsweep_kernel<T, CT, COMP, NW, AZ, DBG>;
   if (lds > 65536) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k, dim3(grid), dim3(NW * 64), lds, st, a);
 }
 
-template <typename T>
-inline hipError_t launch_wsweep_t(bool comp, int cw, const WArgs& a, int grid, hipStream_t st) {
+template <typename T, int NW, int AZ>
+inline void launch_wsweep_shape(bool comp, int cw, const WArgs& a, int grid, hipStream_t st) {
   if (comp && a.export_all) {
     if (cw == 1)
-      launch_wsweep_variant<T, uint8_t, true, true>(a, grid, st);
+      launch_wsweep_variant<T, uint8_t, true, true, NW, AZ>(a, grid, st);
     else
-      launch_wsweep_variant<T, uint16_t, true, true>(a, grid, st);
+      launch_wsweep_variant<T, uint16_t, true, true, NW, AZ>(a, grid, st);
   } else if (comp) {
     if (cw == 1)
-      launch_wsweep_variant<T, uint8_t, true, false>(a, grid, st);
+      launch_wsweep_variant<T, uint8_t, true, false, NW, AZ>(a, grid, st);
     else
-      launch_wsweep_variant<T, uint16_t, true, false>(a, grid, st);
+      launch_wsweep_variant<T, uint16_t, true, false, NW, AZ>(a, grid, st);
   } else {
     if (cw == 1)
-      launch_wsweep_variant<T, uint8_t, false, false>(a, grid, st);
+      launch_wsweep_variant<T, uint8_t, false, false, NW, AZ>(a, grid, st);
     else
-      launch_wsweep_variant<T, uint16_t, false, false>(a, grid, st);
+      launch_wsweep_variant<T, uint16_t, false, false, NW, AZ>(a, grid, st);
   }
+}
+
+template <typename T>
+inline hipError_t launch_wsweep_t(bool comp, int cw, int nw, int az, const WArgs& a, int grid, hipStream_t st) {
+  if (nw == WaveShape<T>::NW && az == WaveShape<T>::AZ)
+    launch_wsweep_shape<T, WaveShape<T>::NW, WaveShape<T>::AZ>(comp, cw, a, grid, st);
+  else if (nw == 1 && az == 1)
+    launch_wsweep_shape<T, 1, 1>(comp, cw, a, grid, st);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 // Defined in wsweep_<type>.hip
-hipError_t wsweep_f32(bool comp, int cw, const WArgs& a, int grid, hipStream_t st);
-hipError_t wsweep_f64(bool comp, int cw, const WArgs& a, int grid, hipStream_t st);
+hipError_t wsweep_f32(bool comp, int cw, int nw, int az, const WArgs& a, int grid, hipStream_t st);
+hipError_t wsweep_f64(bool comp, int cw, int nw, int az, const WArgs& a, int grid, hipStream_t st);
 
 inline void tile_shape(int dtype, int ndim, int& rz, int& ry) {
   if (dtype == SZ_F32) {

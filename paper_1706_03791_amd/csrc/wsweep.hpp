@@ -33,6 +33,7 @@ namespace szh {
 constexpr int kWG = 8;       // steps per group (also the chunk length in elements)
 constexpr int kWRing = 16;   // ring slots per row: two chunks
 constexpr int kWLanes = 64;  // y-rows per tile
+constexpr int kHaloStep = 4; // steps of a group before it waits for the next group's halo
 
 struct WArgs {
   int64_t dims[3];   // Z, Y, X
@@ -195,7 +196,7 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   if (A.pass2 && !P->rerun) return;
 
   const int tid = threadIdx.x;
-  const int w = tid >> 6, ly = tid & 63;
+  const int w = NW == 1 ? 0 : tid >> 6, ly = tid & 63;
   const int wprev = w > 0 ? w - 1 : 0;
   for (int i = tid; i < 2 * NW * 2 * 64; i += NW * 64) (&s_xw[0][0][0][0])[i] = T(0);
   __syncthreads();
@@ -246,7 +247,9 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   const uint64_t nsp = A.nsp;
   const __amdgpu_buffer_rsrc_t ry =
       make_rsrc(A.xy, (uint64_t)A.ntiles * NW * nsp * 16);
-  const __amdgpu_buffer_rsrc_t rz = make_rsrc(A.xz, (uint64_t)A.ntiles * 2 * 64 * nsp * sizeof(T));
+  // (no z-exchange when a block holds one tile along z: its loads read zero)
+  const __amdgpu_buffer_rsrc_t rz =
+      make_rsrc(A.xz, A.tz_per_blk > 1 ? (uint64_t)A.ntiles * 2 * 64 * nsp * sizeof(T) : 0);
   auto y_off = [&](int t, int step) -> int {  // record of (tile t, wave w, step)
     return (int)((((int64_t)t * NW + w) * (int64_t)nsp + step) * 16);
   };
@@ -294,19 +297,28 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   };
 
   // ---- halo records of group gr
+  // Loads are issued one group ahead and must stay straight-line code: a
+  // branch around them makes the compiler wait for their data at the join.
+  // A missing predecessor is a descriptor of zero records (its loads read
+  // zero), chosen per tile in scalar registers; only wave 0 needs the z-halo,
+  // so the other waves get the empty descriptor too.
+  const bool wave0 = __builtin_amdgcn_readfirstlane(w) == 0;  // uniform: scalar selects below
+  const __amdgpu_buffer_rsrc_t ry_in = pred_y >= 0 ? ry : make_rsrc(A.xy, 0);
+  const __amdgpu_buffer_rsrc_t rz_in = (pred_z >= 0 && wave0) ? rz : make_rsrc(A.xz, 0);
+  const int pred_y0 = pred_y >= 0 ? pred_y : 0, pred_z0 = pred_z >= 0 ? pred_z : 0;
   // y: lanes 0..G-1 hold the AZ values lane 0 needs at step gr*G + lane
   auto load_yh = [&](int gr) -> u32x4 {
-    const int off = pred_y >= 0 ? y_off(pred_y, gr * G + kWLanes + (ly & (G - 1))) : kOut;
-    return __builtin_amdgcn_raw_buffer_load_b128(ry, off, 0, kCoherent);
+    return __builtin_amdgcn_raw_buffer_load_b128(ry_in, y_off(pred_y0, gr * G + kWLanes + (ly & (G - 1))), 0,
+                                                 kCoherent);
   };
   // z (wave 0): the moved and unmoved values of the row below at steps gr*G - 1 + i
   auto load_zh = [&](int gr, uint4 (&zo)[XPC], uint4 (&zy)[XPC]) {
 #pragma unroll
     for (int j = 0; j < XPC; j++) {
-      const int o0 = pred_z >= 0 ? z_off(pred_z, 0, gr * G + TZ) + 16 * j : kOut;
-      const int o1 = pred_z >= 0 ? z_off(pred_z, 1, gr * G + TZ) + 16 * j : kOut;
-      zo[j] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rz, o0, 0, kCoherent));
-      zy[j] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rz, o1, 0, kCoherent));
+      const int o0 = z_off(pred_z0, 0, gr * G + TZ) + 16 * j;
+      const int o1 = z_off(pred_z0, 1, gr * G + TZ) + 16 * j;
+      zo[j] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rz_in, o0, 0, kCoherent));
+      zy[j] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rz_in, o1, 0, kCoherent));
     }
   };
 
@@ -441,18 +453,22 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   for (int g = 0; g < ngroups; g++) {
     const bool more = g + 1 < ngroups;
     if (ly < G) s_yin[w][ly] = yh_cur;
-    if (more) {
-      wait_preds(g + 1);
-      yh_nxt = load_yh(g + 1);
-      if (w == 0) load_zh(g + 1, zo_nxt, zy_nxt);
+    // lanes 0..G-1 wrote the records every lane of the wave reads below;
+    // keep the compiler from moving the reads above the writes
+    __builtin_amdgcn_wave_barrier();
+    // The next group's loads are issued on every group, also the last (its
+    // records and chunks lie inside the buffers or past them and go unused),
+    // so that no branch joins their registers before the group ends.  The
+    // input chunks go out now; the halo records after step kHaloStep - 1,
+    // which lets this tile run that many steps closer behind its
+    // predecessors while the loads still have the rest of the group to land.
 #pragma unroll
-      for (int a = 0; a < AZ; a++) {
-        const int64_t q = (wlo[a] + (int64_t)(g + 1) * G) >> 3;  // first chunk of the next window
-        if constexpr (COMP)
-          load_x_chunk(q + 1, xpre[a]);
-        else
-          cpre[a] = load_code_chunk<CT>(rin, q + 1 - cbase);
-      }
+    for (int a = 0; a < AZ; a++) {
+      const int64_t q = (wlo[a] + (int64_t)(g + 1) * G) >> 3;  // first chunk of the next window
+      if constexpr (COMP)
+        load_x_chunk(q + 1, xpre[a]);
+      else
+        cpre[a] = load_code_chunk<CT>(rin, q + 1 - cbase);
     }
     // per-group window of each sub-row and its inputs
     int bslot[AZ];
@@ -476,8 +492,9 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
     for (int i = 0; i < G; i++) {
       const int sig = g * G + i;
       // the row below sub-row 0 at step sig - 1
-      const T lo_o = s_xw[(sig - 1) & 1][wprev][0][ly];
-      const T lo_y = s_xw[(sig - 1) & 1][wprev][1][ly];
+      // (a one-wave tile has no row below it inside the workgroup)
+      const T lo_o = NW > 1 ? s_xw[(sig - 1) & 1][wprev][0][ly] : T(0);
+      const T lo_y = NW > 1 ? s_xw[(sig - 1) & 1][wprev][1][ly] : T(0);
       const T vn_o = w > 0 ? lo_o : piece_elem<T>(zo_cur, i);
       const T vn_y = w > 0 ? lo_y : piece_elem<T>(zy_cur, i);
       const u32x4 yrec = s_yin[w][i];  // the y-halo values lane 0 takes at this step
@@ -563,8 +580,10 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
         Y1[a] = ynew[a];
         yk[i][a] = xq[a];
       }
-      s_xw[sig & 1][w][0][ly] = xq[AZ - 1];
-      s_xw[sig & 1][w][1][ly] = ynew[AZ - 1];
+      if constexpr (NW > 1) {
+        s_xw[sig & 1][w][0][ly] = xq[AZ - 1];
+        s_xw[sig & 1][w][1][ly] = ynew[AZ - 1];
+      }
       if (i + 1 < G) {
         ezo[i + 1] = xq[AZ - 1];
         ezy[i + 1] = ynew[AZ - 1];
@@ -572,7 +591,14 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
         co = xq[AZ - 1];
         cy = ynew[AZ - 1];
       }
-      __syncthreads();
+      // the step's exchange between waves; a single wave needs no barrier
+      // (its own LDS accesses complete in order)
+      if constexpr (NW > 1) __syncthreads();
+      if (i == kHaloStep - 1) {
+        if (more) wait_preds(g + 1);
+        yh_nxt = load_yh(g + 1);
+        load_zh(g + 1, zo_nxt, zy_nxt);
+      }
     }
 
     // ---- group end: publish boundary records, then the progress flag
@@ -658,7 +684,7 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
 // Single-field launch: tiles are claimed through the field's ticket in
 // dependence order.
 template <typename T, typename CT, bool COMP, int NW, int AZ, bool DBG>
-__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu((NW + 3) / 4, (NW + 3) / 4)))
 wsweep_kernel(WArgs A) {
   extern __shared__ __align__(16) uint8_t sz_lds[];
   __shared__ int s_tile;
