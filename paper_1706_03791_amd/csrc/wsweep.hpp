@@ -33,7 +33,7 @@ namespace szh {
 constexpr int kWG = 8;       // steps per group (also the chunk length in elements)
 constexpr int kWRing = 16;   // ring slots per row: two chunks
 constexpr int kWLanes = 64;  // y-rows per tile
-constexpr int kHaloStep = 4; // steps of a group before it waits for the next group's halo
+constexpr int kHaloStep = 6; // steps of a group before it waits for the next group's halo
 
 struct WArgs {
   int64_t dims[3];   // Z, Y, X
@@ -300,8 +300,9 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   // Loads are issued one group ahead and must stay straight-line code: a
   // branch around them makes the compiler wait for their data at the join.
   // A missing predecessor is a descriptor of zero records (its loads read
-  // zero), chosen per tile in scalar registers; only wave 0 needs the z-halo,
-  // so the other waves get the empty descriptor too.
+  // zero), chosen per tile in scalar registers.  Only wave 0 needs the
+  // z-halo; the branch around its loads is uniform (`wave0` lives in scalar
+  // registers) and leaves the registers in place.
   const bool wave0 = __builtin_amdgcn_readfirstlane(w) == 0;  // uniform: scalar selects below
   const __amdgpu_buffer_rsrc_t ry_in = pred_y >= 0 ? ry : make_rsrc(A.xy, 0);
   const __amdgpu_buffer_rsrc_t rz_in = (pred_z >= 0 && wave0) ? rz : make_rsrc(A.xz, 0);
@@ -396,16 +397,75 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   T co = T(0), cy = T(0);  // value of the group's last step: record 0 of the next group
 
   uint4 xpre[AZ][COMP ? XPC : 1];  // compress: prefetched input chunk
-  CW c0[AZ], c1[AZ], cpre[AZ];     // decompress: code chunks
+  CW c0[AZ], c1[AZ], c2[AZ], cpre[AZ];  // decompress: code chunks of this window and two ahead
   CW cacc[AZ], cprv[AZ];           // compress: codes of this and the previous group's window
-  uint64_t uidx[AZ];
+  // Decompress: the unpredictable values a group consumes, in a register
+  // window loaded during the group before (values uidx .. uidx + zc - 1 of
+  // the row's raster-ordered stream), so that no step waits for memory
+  // while other waves of the workgroup could run.  A one-wave tile is
+  // latency-bound instead: it loads each value when the one before it is
+  // consumed (`unext`), which costs fewer instructions per step.
+  constexpr bool UWIN = !COMP && NW > 1;
+  constexpr int UW = UWIN ? G : 1;
+  T uw[AZ][UW], uw_nxt[AZ][UW];
   T unext[AZ];
+  int64_t uidx[AZ];  // stream index of the first value this group consumes (next value: one-wave tiles)
+  int zc[AZ];        // values this group consumes
 #pragma unroll
   for (int a = 0; a < AZ; a++) {
-    c0[a] = c1[a] = cpre[a] = cacc[a] = cprv[a] = (CW)0;
+    c0[a] = c1[a] = c2[a] = cpre[a] = cacc[a] = cprv[a] = (CW)0;
     uidx[a] = 0;
+    zc[a] = 0;
     unext[a] = T(0);
+#pragma unroll
+    for (int j = 0; j < UW; j++) uw[a][j] = uw_nxt[a][j] = T(0);
   }
+  // unpredictable values from the tile's first row on: offsets stay below 2 GiB
+  const int64_t ubase =
+      !UWIN ? 0 : (int64_t)A.useg[((z0 * Yd + y0) * (int64_t)A.nblk[2]) + bx];
+  const __amdgpu_buffer_rsrc_t ru =
+      make_rsrc(!UWIN ? nullptr : (const T*)A.uvals + ubase,
+                !UWIN ? 0 : (uint64_t)max((int64_t)0, (int64_t)A.n_unpred - ubase) * sizeof(T));
+  // Zero codes among the active steps of group gr's window `win` of sub-row
+  // a: an exact zero-field mask (high bit of each SB-bit field set iff the
+  // field is 0), restricted to the active steps [i0, i1), then a popcount.
+  auto zeros_in = [&](CW win, int gr, int a) -> int {
+    const int i0 = min(max(sk[a] - gr * G, 0), G);
+    const int i1 = min(max(sk[a] + xlen[a] - gr * G, 0), G);
+    if constexpr (sizeof(CT) == 1) {
+      const uint64_t lo7 = 0x7F7F7F7F7F7F7F7Full;
+      const uint64_t zm = ~(((win & lo7) + lo7) | win | lo7);
+      const uint64_t am = (i1 > i0) ? (((i1 - i0) == 8 ? ~0ull : ((1ull << (8 * (i1 - i0))) - 1)) << (8 * i0)) : 0ull;
+      return __builtin_popcountll(zm & am);
+    } else {
+      const uint64_t lo15 = 0x7FFF7FFF7FFF7FFFull;
+      int z = 0;
+#pragma unroll
+      for (int h = 0; h < 2; h++) {
+        const uint64_t x = (uint64_t)(win >> (64 * h));
+        const uint64_t zm = ~(((x & lo15) + lo15) | x | lo15);
+        const int b0 = min(max(i0 - 4 * h, 0), 4), b1 = min(max(i1 - 4 * h, 0), 4);
+        const uint64_t am = (b1 > b0) ? (((b1 - b0) == 4 ? ~0ull : ((1ull << (16 * (b1 - b0))) - 1)) << (16 * b0)) : 0ull;
+        z += __builtin_popcountll(zm & am);
+      }
+      return z;
+    }
+  };
+  // The z values from stream index u on into dst.  Lanes with z > 0 load the
+  // whole window (entries past z, or past the stream, go unused); lanes with
+  // z == 0 load from an offset past the descriptor.
+  auto load_uw = [&](int64_t u, int z, T (&dst)[UW]) {
+    const int base = z > 0 ? (int)((u - ubase) * (int64_t)sizeof(T)) : kOut;
+#pragma unroll
+    for (int j = 0; j < UW; j++) {
+      if constexpr (sizeof(T) == 4) {
+        dst[j] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(ru, base + 4 * j, 0, 0));
+      } else {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(ru, base + 8 * j, 0, 0);
+        dst[j] = __builtin_bit_cast(T, ((uint64_t)v[1] << 32) | v[0]);
+      }
+    }
+  };
 
   // ---- prologue: group 0's halo and input
   wait_preds(0);
@@ -440,14 +500,25 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
       __amdgpu_buffer_rsrc_t r = rin;
       c0[a] = load_code_chunk<CT>(r, q0 - cbase);
       c1[a] = load_code_chunk<CT>(r, q0 + 1 - cbase);
+      c2[a] = load_code_chunk<CT>(r, q0 + 2 - cbase);
       if (rv[a]) {
         const int64_t seg = ((z0 + AZ * w + a) * Yd + yr) * A.nblk[2] + bx;
-        uidx[a] = A.useg[seg];
-        unext[a] = (uidx[a] < A.n_unpred) ? ((const T*)A.uvals)[uidx[a]] : T(0);
+        uidx[a] = (int64_t)A.useg[seg];
+        if constexpr (!UWIN) unext[a] = ((uint64_t)uidx[a] < A.n_unpred) ? ((const T*)A.uvals)[uidx[a]] : T(0);
       }
     }
   }
   wait_vm();
+  if constexpr (UWIN) {
+    // group 0's window of unpredictable values
+#pragma unroll
+    for (int a = 0; a < AZ; a++) {
+      const int o = (int)(wlo[a] & (G - 1));
+      zc[a] = zeros_in(code_window<CT>(c0[a], c1[a], o), 0, a);
+      load_uw(uidx[a], zc[a], uw[a]);
+    }
+    wait_vm();
+  }
   __syncthreads();
 
   for (int g = 0; g < ngroups; g++) {
@@ -462,13 +533,21 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
     // input chunks go out now; the halo records after step kHaloStep - 1,
     // which lets this tile run that many steps closer behind its
     // predecessors while the loads still have the rest of the group to land.
+    int zn[AZ];  // decompress: values the next group consumes
 #pragma unroll
     for (int a = 0; a < AZ; a++) {
       const int64_t q = (wlo[a] + (int64_t)(g + 1) * G) >> 3;  // first chunk of the next window
-      if constexpr (COMP)
+      if constexpr (COMP) {
         load_x_chunk(q + 1, xpre[a]);
-      else
-        cpre[a] = load_code_chunk<CT>(rin, q + 1 - cbase);
+        zn[a] = 0;
+      } else {
+        cpre[a] = load_code_chunk<CT>(rin, q + 2 - cbase);
+        zn[a] = 0;
+        if constexpr (UWIN) {
+          zn[a] = zeros_in(code_window<CT>(c1[a], c2[a], (int)(wlo[a] & (G - 1))), g + 1, a);
+          load_uw(uidx[a] + zc[a], zn[a], uw_nxt[a]);
+        }
+      }
     }
     // per-group window of each sub-row and its inputs
     int bslot[AZ];
@@ -559,10 +638,19 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
         for (int a = 0; a < AZ; a++) {
           const uint32_t code = (uint32_t)(cwin[a] >> (SB * i)) & ((1u << SB) - 1);
           const T v1 = p[a] + T((int32_t)code - half) * twoeb;
-          xq[a] = act[a] ? (code != 0 ? v1 : unext[a]) : T(0);
-          if (act[a] && code == 0) {
-            uidx[a]++;
-            unext[a] = (uidx[a] < A.n_unpred) ? ((const T*)A.uvals)[uidx[a]] : T(0);
+          if constexpr (UWIN) {
+            xq[a] = act[a] ? (code != 0 ? v1 : uw[a][0]) : T(0);
+            // a consumed value leaves the window (at most G - 1 - i values
+            // remain for the rest of the group)
+            const bool take = act[a] && code == 0;
+#pragma unroll
+            for (int j = 0; j + 1 < UW - i; j++) uw[a][j] = take ? uw[a][j + 1] : uw[a][j];
+          } else {
+            xq[a] = act[a] ? (code != 0 ? v1 : unext[a]) : T(0);
+            if (act[a] && code == 0) {
+              uidx[a]++;
+              unext[a] = ((uint64_t)uidx[a] < A.n_unpred) ? ((const T*)A.uvals)[uidx[a]] : T(0);
+            }
           }
           s_ring[w][a][(bslot[a] + i) & (kWRing - 1)][ly] = xq[a];
         }
@@ -597,7 +685,7 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
       if (i == kHaloStep - 1) {
         if (more) wait_preds(g + 1);
         yh_nxt = load_yh(g + 1);
-        load_zh(g + 1, zo_nxt, zy_nxt);
+        if (wave0) load_zh(g + 1, zo_nxt, zy_nxt);
       }
     }
 
@@ -657,7 +745,14 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
       } else {
         flush_values(a, q);
         c0[a] = c1[a];
-        c1[a] = cpre[a];
+        c1[a] = c2[a];
+        c2[a] = cpre[a];
+        if constexpr (UWIN) {
+          uidx[a] += zc[a];
+          zc[a] = zn[a];
+#pragma unroll
+          for (int j = 0; j < UW; j++) uw[a][j] = uw_nxt[a][j];
+        }
       }
     }
     yh_cur = yh_nxt;
