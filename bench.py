@@ -63,7 +63,184 @@ def cpu_baseline(x: np.ndarray, planes: int, kw: dict):
     return {"value": round(gbps, 6), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"first {planes} z-planes of the same field ({sample.shape[0]}x{sample.shape[1]}x"
                       f"{sample.shape[2]} f32, {sample.nbytes / 2**20:.0f} MiB): compress "
-                      f"{t1 - t0:.2f} s + decompress {t2 - t1:.2f} s, single thread"}
+                      f"{t1 - t0:.2f} s + decompress {t2 - t1:.2f} s, single thread",
+            "cpu_model": cpu_model()}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_WORKER = r"""
+import json, sys, time
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+import oracle as O
+x = np.load(sys.argv[2])
+kw = json.loads(sys.argv[3])
+t0 = time.perf_counter()
+buf, st = O.compress(x, **kw)
+t1 = time.perf_counter()
+out = O.decompress(buf)
+t2 = time.perf_counter()
+assert out.shape == x.shape
+print(json.dumps({"bytes": int(x.nbytes), "t_c": t1 - t0, "t_d": t2 - t1}))
+"""
+
+
+def cpu_all_cores(x: np.ndarray, planes: int, kw: dict, workers: int):
+    """The oracle on every host core at once: one process per core, each
+    compressing and decompressing its own slab of `planes` z-planes (the
+    paper's model of independent per-process fields).  A different, slab-split
+    output: reported beside the single-thread baseline, never used for parity."""
+    import shutil
+    import subprocess
+    import tempfile
+    workers = max(1, min(workers, x.shape[0] // planes))
+    d = tempfile.mkdtemp(prefix="szcpu_", dir="/tmp")
+    try:
+        paths = []
+        for k in range(workers):
+            pth = os.path.join(d, f"slab{k}.npy")
+            np.save(pth, np.ascontiguousarray(x[k * planes:(k + 1) * planes]))
+            paths.append(pth)
+        t0 = time.perf_counter()
+        procs = [subprocess.Popen([sys.executable, "-c", _WORKER, ROOT, pth, json.dumps(kw)],
+                                  stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True) for pth in paths]
+        rows = []
+        for pr in procs:
+            out, err = pr.communicate(timeout=600)
+            if pr.returncode:
+                raise RuntimeError(f"oracle worker failed: {err[-500:]}")
+            rows.append(json.loads(out.strip().splitlines()[-1]))
+        wall = time.perf_counter() - t0
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    total = sum(r["bytes"] for r in rows)
+    return {"value": round(2 * total / wall / 1e9, 6), "unit": "GB/s", "cores": workers,
+            "kind": "oracle, slab-split: one process per core on independent slabs",
+            "sample": f"{workers} slabs of {planes} z-planes ({total / 2**20:.0f} MiB in all), compress + "
+                      f"decompress each, {wall:.2f} s wall including process start",
+            "cpu_model": cpu_model()}
+
+
+def roundtrip(Z, torch, x, kw, steps=3, warmup=1):
+    """Timed compress + decompress of a resident field through the C ABI;
+    returns (row dict, reconstruction, stats)."""
+    p = Z.make_params(tuple(x.shape), x.dtype, **kw)
+    cap = Z.sz_compress_bound(p)
+    comp = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    out = torch.empty_like(x)
+    ctx = Z.context(0)
+    st_ = torch.cuda.current_stream().cuda_stream
+    S = x.numel() * x.element_size()
+    tc, td = [], []
+    for i in range(warmup + steps):
+        t0 = time.perf_counter()
+        rc, size, st = Z.sz_compress(ctx, p, x.data_ptr(), comp.data_ptr(), cap, st_)
+        t1 = time.perf_counter()
+        if rc:
+            raise Z.SzError(rc, "sz_compress")
+        rc = Z.sz_decompress(ctx, comp.data_ptr(), size, out.data_ptr(), S, st_)
+        t2 = time.perf_counter()
+        if rc:
+            raise Z.SzError(rc, "sz_decompress")
+        if i >= warmup:
+            tc.append(t1 - t0)
+            td.append(t2 - t1)
+    t_c, t_d = float(np.mean(tc)), float(np.mean(td))
+    row = {"GBps": round(2 * S / (t_c + t_d) / 1e9, 3), "compress_GBps": round(S / t_c / 1e9, 3),
+           "decompress_GBps": round(S / t_d / 1e9, 3), "compression_factor": round(S / size, 3),
+           "bits_per_value": round(8.0 * size / x.numel(), 4), "hit_rate": round(st.hit_rate, 6),
+           "m_used": int(st.m_used)}
+    del comp
+    return row, out, st
+
+
+def quality_row(Z, x, xr, eb, max_lag=0):
+    """On-device distortion metrics (Sec. II Metrics 2-3, Sec. V autocorrelation)."""
+    q = Z.quality(x, xr, max_lag=max_lag)
+    row = {"psnr_db": round(q["psnr"], 3), "nrmse": q["nrmse"], "rmse": q["rmse"],
+           "pearson": q["pearson"], "max_err_over_eb": round(q["max_abs_err"] / eb, 6)}
+    if max_lag:
+        row["err_autocorr"] = [round(v, 6) for v in q["autocorr"]]
+    return row
+
+
+def bench_cosmo_extras(Z, torch, n, steps=3):
+    """The other two runs of the cosmology workload: the velocity-like field
+    (f32, relative bound 1e-4, m = 8) and the density in f64 at a relative
+    bound of 1e-8 with the adaptive interval count."""
+    import fieldgen as F
+    import fieldgen.gpu as G
+    out = {}
+    runs = (("velocity_f32", lambda: G.velocity3d((n, n, n), F.BASE_SEED + 102), dict(m=8, eb_rel=1e-4)),
+            ("density_f64", lambda: G.cosmo3d((n, n, n), F.BASE_SEED + 2).double(), dict(m=0, eb_rel=1e-8)))
+    for name, make, extra in runs:
+        print(f"[bench] cosmology extra: {name}", file=sys.stderr, flush=True)
+        x = make()
+        torch.cuda.synchronize()
+        kw = dict(layers=1, eb_mode="rel", **extra)
+        row, xr, st = roundtrip(Z, torch, x, kw, steps=steps)
+        row.update(quality_row(Z, x, xr, st.eb_used))
+        row["eb_rel"] = extra["eb_rel"]
+        out[name] = row
+        del x, xr
+        torch.cuda.empty_cache()
+    return out
+
+
+def layer_study(Z, torch, eb_rels=(1e-4,), samples=(None, (900, 1800))):
+    """Best-layer study (Sec. III-B, Table II) on the 1800x3600 climate-like
+    field: R_PH from decompressed and from original neighbours, n = 1..4."""
+    import fieldgen as F
+    import fieldgen.gpu as G
+    x = G.climate2d((1800, 3600), F.BASE_SEED + 1)
+    rows = []
+    for eb in eb_rels:
+        for smp in samples:
+            r = Z.layer_survey(x, sample=smp, eb_mode="rel", eb_rel=eb)
+            rows.append({"eb_rel": eb, "sample": list(smp) if smp else [1800, 3600],
+                         "rph_decomp": [round(v, 6) for v in r["rph_decomp"]],
+                         "rph_orig": [round(v, 6) for v in r["rph_orig"]],
+                         "best_layers": r["best_layers"],
+                         "best_layers_orig": 1 + int(np.argmax(r["rph_orig"]))})
+    del x
+    return rows
+
+
+def study(Z, torch):
+    """Rate-distortion sweep (Sec. V metrics) over the synthetic workloads:
+    bit-rate, compression factor, PSNR, NRMSE, maximum error / bound,
+    hitting rate and chosen m per relative bound, all metrics on the device."""
+    import fieldgen as F
+    import fieldgen.gpu as G
+    fields = (("smooth3d_64", lambda: G.smooth3d((64, 64, 64), F.BASE_SEED + 0), (1,)),
+              ("climate2d_1800x3600", lambda: G.climate2d((1800, 3600), F.BASE_SEED + 1), (1, 2)),
+              ("cosmo3d_512_density", lambda: G.cosmo3d((512, 512, 512), F.BASE_SEED + 2), (1,)))
+    rows = []
+    for name, make, layer_set in fields:
+        x = make()
+        torch.cuda.synchronize()
+        for nl in layer_set:
+            for eb in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
+                print(f"[study] {name} layers {nl} eb_rel {eb:g}", file=sys.stderr, flush=True)
+                row, xr, st = roundtrip(Z, torch, x, dict(layers=nl, m=0, eb_mode="rel", eb_rel=eb), steps=2)
+                row.update(quality_row(Z, x, xr, st.eb_used, max_lag=1))
+                row.update({"field": name, "layers": nl, "eb_rel": eb})
+                rows.append(row)
+                del xr
+        del x
+        torch.cuda.empty_cache()
+    return {"rate_distortion": rows,
+            "layer_study": layer_study(Z, torch, eb_rels=(1e-3, 1e-4, 1e-5, 1e-6))}
 
 
 def bench_batched(Z, torch, count=64, reps=5):
@@ -115,13 +292,22 @@ def bench_batched(Z, torch, count=64, reps=5):
     exact = all(s == 0 for s in bst) and all(
         bsz[i] == sizes[i] and torch.equal(B.outs[i][: sizes[i]], outs[i][: sizes[i]]) for i in range(len(xs)))
     sched, tiles, threads, ms = B.info()
+    # on-device distortion of every field's container, decompressed by the plain path
+    worst_ratio, min_psnr = 0.0, float("inf")
+    for i, x in enumerate(xs):
+        xr = Z.decompress(B.outs[i][: bsz[i]]).view(x.shape)
+        q = Z.quality(x, xr)
+        worst_ratio = max(worst_ratio, q["max_abs_err"] / (kws[i]["eb_rel"] * q["value_range"]))
+        min_psnr = min(min_psnr, q["psnr"])
+        del xr
     B.close()
     return {"fields": len(xs), "input_bytes": int(total), "plain_ms": round(t_plain * 1e3, 3),
             "batched_ms": round(t_batch * 1e3, 3), "plain_GBps": round(total / t_plain / 1e9, 3),
             "batched_GBps": round(total / t_batch / 1e9, 3), "speedup": round(t_plain / t_batch, 3),
             "bit_exact_vs_plain": bool(exact), "schedule": sched, "sweep_tiles": tiles,
             "threads_per_sweep_wg": threads, "tune_ms": [round(v, 3) for v in ms],
-            "tune_wall_s": round(t_tune, 3), "graph": True}
+            "tune_wall_s": round(t_tune, 3), "graph": True,
+            "quality": {"min_psnr_db": round(min_psnr, 3), "max_err_over_eb": round(worst_ratio, 6)}}
 
 
 def bench_served(Z, torch, rates=(50, 500), durations=(2.0, 0.4), slots=8, budget=24 << 30):
@@ -177,6 +363,23 @@ def bench_served(Z, torch, rates=(50, 500), durations=(2.0, 0.4), slots=8, budge
             stats = srv.stats()
             print(f"[bench] served: {mode} finished", file=sys.stderr, flush=True)
             srv.close()
+            qrow = None
+            if mode == "served":
+                # on-device distortion of every served compress result and
+                # every decompress result against its original field
+                worst, min_psnr = 0.0, float("inf")
+                for i, r in enumerate(reqs):
+                    if res[i]["status"]:
+                        continue
+                    if r["op"] == "compress":
+                        xr = Z.decompress(outs[i][: res[i]["out_size"]]).view(data[i].shape)
+                    else:
+                        xr = outs[i]
+                    q = Z.quality(data[i], xr)
+                    worst = max(worst, q["max_abs_err"] / (kws[i]["eb_rel"] * q["value_range"]))
+                    min_psnr = min(min_psnr, q["psnr"])
+                    del xr
+                qrow = {"min_psnr_db": round(min_psnr, 3), "max_err_over_eb": round(worst, 6)}
             bad = [x["status"] for x in res if x["status"]]
             lat = np.array([x["t_done"] - x["t_submit"] for x in res]) * 1e3
             span = max(x["t_done"] for x in res) - min(x["t_submit"] for x in res)
@@ -185,6 +388,8 @@ def bench_served(Z, torch, rates=(50, 500), durations=(2.0, 0.4), slots=8, budge
                          "GBps": round(nbytes / span / 1e9, 3), "errors": len(bad),
                          "max_in_flight": stats["max_in_flight"],
                          "pool_peak_bytes": stats["pool_peak_bytes"]}
+            if qrow:
+                row[mode]["quality"] = qrow
             del outs
         out["rates"].append(row)
         del data, comps
@@ -195,13 +400,19 @@ def bench_served(Z, torch, rates=(50, 500), durations=(2.0, 0.4), slots=8, budge
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-planes", type=int, default=32)
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="processes of the all-cores oracle figure (0 skips it)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the velocity / f64 cosmology runs and the layer study")
+    ap.add_argument("--study", action="store_true",
+                    help="only run the rate-distortion sweep and the best-layer study")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run a plain 512 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -222,6 +433,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_ref_bytes": a.numel() * 4, "launches": 3}), flush=True)
+        return
+
+    if args.study:
+        print(json.dumps(study(Z, torch)), flush=True)
         return
 
     n = args.size
@@ -270,9 +485,22 @@ def main():
     err = (out.double() - xd.double()).abs().max().item()
     assert err < st.eb_used, (err, st.eb_used)
 
+    quality = quality_row(Z, xd, out, st.eb_used, max_lag=4)
+
     Cb = size
-    t_c, t_d = float(np.mean(tc)), float(np.mean(td))
+    t_c, t_d = float(np.median(tc)), float(np.median(td))
     value = 2 * S / (t_c + t_d) / 1e9
+    # a plain device copy of the field for scale (reads S, writes S)
+    cp = torch.empty_like(xd)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    cp.copy_(xd)
+    e0.record()
+    for _ in range(10):
+        cp.copy_(xd)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 2 * S / (e0.elapsed_time(e1) / 10 / 1e3) / 1e9
+    del cp
     alg_bytes = (2 * S + Cb) + (Cb + S)
     hbm_frac = alg_bytes / (t_c + t_d) / 1e9 / HBM_PEAK_GBPS
 
@@ -309,8 +537,14 @@ def main():
         "decompress_GBps": round(S / t_d / 1e9, 3),
         "hbm_frac": round(hbm_frac, 4),
         "compression_factor": round(S / Cb, 3),
+        "bit_rate": round(8.0 * Cb / xd.numel(), 4),
+        "m_used": int(st.m_used),
+        "m_suggested": int(st.m_suggested),
+        "device_copy_GBps": round(copy_gbps, 1),
+        "timing": "median per-step compress and decompress times over the timed steps",
         "hit_rate": st.hit_rate,
         "n_unpred": int(st.n_unpred),
+        "quality": quality,
         "stage_ms": {k: round(v, 4) for k, v in per_call.items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
@@ -318,9 +552,14 @@ def main():
                      "algorithmic_bytes_per_launch": int(alg_per_stage[dom]),
                      "launch_ms": round(dom_ms, 4)},
     }
-    x_slab = xd[: args.cpu_planes].cpu().numpy() if not args.no_cpu_baseline else None
+    x_host = xd.cpu().numpy() if not args.no_cpu_baseline else None
+    x_slab = x_host[: args.cpu_planes] if x_host is not None else None
     del xd, out, comp
     torch.cuda.empty_cache()
+    if not args.no_extras:
+        res["cosmology_extras"] = bench_cosmo_extras(Z, torch, n)
+        print("[bench] layer study", file=sys.stderr, flush=True)
+        res["layer_study"] = layer_study(Z, torch)
     if not args.no_batched:
         print("[bench] batched form", file=sys.stderr, flush=True)
         res["batched"] = bench_batched(Z, torch)
@@ -331,6 +570,9 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(x_slab, args.cpu_planes, kw)
+        if args.cpu_workers > 0:
+            print("[bench] cpu baseline, all cores (oracle on slabs)", file=sys.stderr, flush=True)
+            res["cpu_baseline_all_cores"] = cpu_all_cores(x_host, args.cpu_planes, kw, args.cpu_workers)
     print(json.dumps(res), flush=True)
 
 

@@ -94,6 +94,11 @@ def cosmo3d(shape, seed: int, device="cuda"):
     return grf(shape, -3.0, 1.5, seed, device).exp_()
 
 
+def velocity3d(shape, seed: int, device="cuda"):
+    """Zero-mean velocity-like k^-3 Gaussian random field of std 300 (float32)."""
+    return grf(shape, -3.0, 300.0, seed, device)
+
+
 def batch_field(spec, device="cuda"):
     """A field of ``fieldgen.batch_fields`` made on the device."""
     if spec["kind"] == "climate2d":

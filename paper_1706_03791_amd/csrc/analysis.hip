@@ -109,19 +109,29 @@ __global__ void __launch_bounds__(kQNT) q_pass2(const T* __restrict__ x, const T
   }
 }
 
-// Column sums of a [rows][cols] array of partials, each column summed by one
-// thread in row order (fixed order: deterministic).  op 1 takes the minimum,
+// Column reductions of a [rows][cols] array of partials: one block per
+// column; thread t folds rows t, t + kQNT, ... in order, then a fixed tree
+// folds the threads (a fixed order: deterministic).  op 1 takes the minimum,
 // op 2 the maximum instead of the sum for that column.
-__global__ void q_reduce(const double* part, uint64_t rows, int cols, const int* ops, double* out) {
-  for (int c = threadIdx.x; c < cols; c += blockDim.x) {
-    const int op = ops ? ops[c] : 0;
-    double acc = op == 1 ? __builtin_huge_val() : (op == 2 ? -__builtin_huge_val() : 0.0);
-    for (uint64_t r = 0; r < rows; r++) {
-      const double v = part[r * cols + c];
-      acc = op == 1 ? fmin(acc, v) : (op == 2 ? fmax(acc, v) : acc + v);
-    }
-    out[c] = acc;
+__global__ void __launch_bounds__(kQNT) q_reduce(const double* part, uint64_t rows, int cols, const int* ops,
+                                                 double* out) {
+  __shared__ double red[kQNT / 64];
+  const int c = blockIdx.x;
+  const int op = ops ? ops[c] : 0;
+  const double id = op == 1 ? __builtin_huge_val() : (op == 2 ? -__builtin_huge_val() : 0.0);
+  double acc = id;
+  for (uint64_t r = threadIdx.x; r < rows; r += kQNT) {
+    const double v = part[r * cols + c];
+    acc = op == 1 ? fmin(acc, v) : (op == 2 ? fmax(acc, v) : acc + v);
   }
+  double t;
+  if (op == 0) {
+    t = block_sum_d<kQNT>(acc, red);
+  } else {
+    t = block_max_d<kQNT>(op == 1 ? -acc : acc, red);
+    if (op == 1) t = -t;
+  }
+  if (threadIdx.x == 0) out[c] = t;
 }
 
 __global__ void q_means(const double* sums, uint64_t n, double* means) {
@@ -133,11 +143,15 @@ __global__ void q_means(const double* sums, uint64_t n, double* means) {
 }
 
 // Pass 3, per block of kSeg positions i: for every lag k in 1..K the sum of
-// d_i d_{i+k} with d = e - mean(e), over i + k < n.
+// d_i d_{i+k} with d = e - mean(e), over i + k < n.  The kQNT threads split
+// into K lag groups of P = kQNT / K threads; thread p of lag k sums the
+// positions of part p of the segment in order, and the P part sums of a lag
+// are then added in part order (a fixed order: deterministic).
 template <typename T>
 __global__ void __launch_bounds__(kQNT) q_autocorr(const T* __restrict__ x, const T* __restrict__ y, uint64_t n,
                                                    const double* means, int K, double* part) {
   __shared__ double d[kSeg + kMaxLag];
+  __shared__ double ps[kQNT];
   const double mev = means[2];
   const uint64_t s0 = (uint64_t)blockIdx.x * kSeg;
   for (int j = threadIdx.x; j < kSeg + K; j += kQNT) {
@@ -145,13 +159,24 @@ __global__ void __launch_bounds__(kQNT) q_autocorr(const T* __restrict__ x, cons
     d[j] = i < n ? ((double)x[i] - (double)y[i]) - mev : 0.0;
   }
   __syncthreads();
-  const int k = threadIdx.x + 1;
-  if (k > K) return;
+  const int P = kQNT / K;               // threads per lag (>= 1 since K <= kMaxLag < kQNT)
+  const int k = 1 + (int)threadIdx.x % K;
+  const int pi = (int)threadIdx.x / K;  // part index, < P for the first P * K threads
   const uint64_t lim = n > s0 ? n - s0 : 0;  // positions of this block inside the array
   const int len = (int)(lim < (uint64_t)kSeg ? lim : (uint64_t)kSeg);
   double acc = 0;
-  for (int j = 0; j < len; j++) acc += (s0 + j + k < n) ? d[j] * d[j + k] : 0.0;
-  part[(size_t)blockIdx.x * K + (k - 1)] = acc;
+  if (pi < P) {
+    const int per = (kSeg + P - 1) / P;
+    const int j0 = pi * per, j1 = min(len, j0 + per);
+    for (int j = j0; j < j1; j++) acc += (s0 + j + k < n) ? d[j] * d[j + k] : 0.0;
+  }
+  ps[threadIdx.x] = acc;
+  __syncthreads();
+  if ((int)threadIdx.x < K) {
+    double t = 0;
+    for (int q = 0; q < P; q++) t += ps[q * K + threadIdx.x];
+    part[(size_t)blockIdx.x * K + threadIdx.x] = t;
+  }
 }
 
 // ---- layer survey
@@ -237,16 +262,16 @@ int quality_t(sz_ctx* ctx, uint64_t n, const void* d_x, const void* d_y, uint32_
   const T* x = (const T*)d_x;
   const T* y = (const T*)d_y;
   hipLaunchKernelGGL(q_pass1<T>, dim3(g12), dim3(kQNT), 0, st, x, y, n, part);
-  hipLaunchKernelGGL(q_reduce, dim3(1), dim3(64), 0, st, (const double*)part, (uint64_t)g12, 6, (const int*)ops, sums);
+  hipLaunchKernelGGL(q_reduce, dim3(6), dim3(kQNT), 0, st, (const double*)part, (uint64_t)g12, 6, (const int*)ops, sums);
   hipLaunchKernelGGL(q_means, dim3(1), dim3(64), 0, st, (const double*)sums, n, means);
   double* part2 = part;  // pass 1 partials are no longer needed
   hipLaunchKernelGGL(q_pass2<T>, dim3(g12), dim3(kQNT), 0, st, x, y, n, (const double*)means, part2);
-  hipLaunchKernelGGL(q_reduce, dim3(1), dim3(64), 0, st, (const double*)part2, (uint64_t)g12, 5, (const int*)nullptr,
+  hipLaunchKernelGGL(q_reduce, dim3(5), dim3(kQNT), 0, st, (const double*)part2, (uint64_t)g12, 5, (const int*)nullptr,
                      sums2);
   if (K) {
     hipLaunchKernelGGL(q_autocorr<T>, dim3((unsigned)nseg), dim3(kQNT), 0, st, x, y, n, (const double*)means, (int)K,
                        acpart);
-    hipLaunchKernelGGL(q_reduce, dim3(1), dim3(256), 0, st, (const double*)acpart, nseg, (int)K, (const int*)nullptr,
+    hipLaunchKernelGGL(q_reduce, dim3(K), dim3(kQNT), 0, st, (const double*)acpart, nseg, (int)K, (const int*)nullptr,
                        ac);
   }
   double h_sums[6], h_sums2[5];

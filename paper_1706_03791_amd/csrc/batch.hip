@@ -120,7 +120,7 @@ constexpr size_t b_sweep_lds() {
 template <typename CT>
 __global__ void __launch_bounds__(1024) b_hist(const BJob* J, uint32_t pass2) {
   const BJob& j = J[blockIdx.y];
-  if (j.kind == BK_WAVE3) hist_kernel_dev<CT>((const CT*)j.w.codes, j.n, j.w.hist, j.plan, pass2);
+  if (j.kind == BK_WAVE3) hist_kernel_dev<CT>((const CT*)j.w.codes, j.n, j.w.hist, j.plan, pass2, nullptr);
 }
 
 __global__ void __launch_bounds__(1024) b_pick_m(const BJob* J) {

@@ -563,23 +563,36 @@ __device__ __forceinline__ uint32_t wave_exscan(uint32_t v) { return wave_inscan
 
 // ------------------------------------------------ K3: code histogram
 // Histogram of the codes of a sweep (the wave-tiled sweep writes codes
-// only).  A window of up to 16384 bins around the centre code lives in LDS;
-// the centre and zero codes, the most frequent ones, are counted in
-// registers; codes outside the window go straight to global atomics.
+// only).  The centre and zero codes, the most frequent ones, are counted in
+// registers.  With 1-byte codes (m <= 8) every bin lives in LDS, in 32
+// copies (one per lane pair of a wave, rows padded to 257 words so the
+// copies of one bin sit in different banks): the codes next to the centre
+// are frequent too, and lanes that add to one bin in one copy would
+// serialise.  With 2-byte codes a window of up to 16384 bins around the
+// centre lives in LDS and codes outside it go straight to global atomics.
+// A block's counts reach the histogram by atomics, or, with 1-byte codes and
+// a partials array `hpart` (kHistBlocks rows of 256 bins), by plain stores
+// of its row that hist_reduce_kernel then adds up in a fixed order: the
+// atomics of every block onto the same few cache lines would serialise.
 constexpr uint32_t kHistLds = 16384;
+constexpr uint32_t kHistCopies = 32, kHistRow = 257;
+constexpr uint32_t kHistBlocks = 512;  // grid of the 1-byte path with partials
 
 template <typename CT>
 __device__ __forceinline__ void hist_kernel_dev(const CT* __restrict__ codes, uint64_t n, uint32_t* hist,
-                                                    const DevPlan* P, uint32_t pass2) {
-  __shared__ uint32_t h[kHistLds];
+                                                    const DevPlan* P, uint32_t pass2, uint32_t* hpart) {
+  __shared__ uint32_t h[sizeof(CT) == 1 ? kHistCopies * kHistRow : kHistLds];
   if (P->status) return;
   if (pass2 && !P->rerun) return;
   const uint32_t m = P->m;
   const uint32_t nb = 1u << m, half = 1u << (m - 1);
-  const uint32_t W = nb < kHistLds ? nb : kHistLds;
-  const uint32_t wbase = nb > W ? half - W / 2 : 0;
-  for (uint32_t i = threadIdx.x; i < W; i += 1024) h[i] = 0;
+  constexpr bool kCopies = sizeof(CT) == 1;  // nb <= 256
+  const uint32_t W = kCopies ? nb : (nb < kHistLds ? nb : kHistLds);
+  const uint32_t wbase = (!kCopies && nb > W) ? half - W / 2 : 0;
+  const uint32_t clear = kCopies ? kHistCopies * kHistRow : W;
+  for (uint32_t i = threadIdx.x; i < clear; i += 1024) h[i] = 0;
   __syncthreads();
+  uint32_t* hc = kCopies ? h + (threadIdx.x & (kHistCopies - 1)) * kHistRow : h;  // this lane's copy
   uint32_t c_center = 0, c_zero = 0;
   auto count = [&](uint32_t code) {
     if (code == half) {
@@ -589,16 +602,16 @@ __device__ __forceinline__ void hist_kernel_dev(const CT* __restrict__ codes, ui
     } else {
       const uint32_t w = code - wbase;
       if (w < W)
-        atomicAdd(&h[w], 1u);
+        atomicAdd(&hc[w], 1u);
       else
         atomicAdd(&hist[code], 1u);
     }
   };
   constexpr int E = 16 / sizeof(CT);
+  constexpr int U = 4;  // 16-byte loads in flight per thread
   const uint64_t nv = n / E;
   const uint64_t stride = (uint64_t)gridDim.x * 1024;
-  for (uint64_t v = (uint64_t)blockIdx.x * 1024 + threadIdx.x; v < nv; v += stride) {
-    const uint4 raw = ((const uint4*)codes)[v];
+  auto count_vec = [&](const uint4 raw) {
     const uint32_t wd[4] = {raw.x, raw.y, raw.z, raw.w};
 #pragma unroll
     for (int e = 0; e < E; e++) {
@@ -606,22 +619,66 @@ __device__ __forceinline__ void hist_kernel_dev(const CT* __restrict__ codes, ui
       const int sh = (e % (E / 4)) * 8 * (int)sizeof(CT);
       count((word >> sh) & ((sizeof(CT) == 1) ? 0xFFu : 0xFFFFu));
     }
+  };
+  uint64_t v = (uint64_t)blockIdx.x * 1024 + threadIdx.x;
+  for (; v + (U - 1) * stride < nv; v += U * stride) {
+    uint4 raw[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) raw[u] = ((const uint4*)codes)[v + u * stride];
+#pragma unroll
+    for (int u = 0; u < U; u++) count_vec(raw[u]);
   }
+  for (; v < nv; v += stride) count_vec(((const uint4*)codes)[v]);
   for (uint64_t i = nv * E + (uint64_t)blockIdx.x * 1024 + threadIdx.x; i < n; i += stride) count(codes[i]);
   c_center = wave_sum(c_center);
   c_zero = wave_sum(c_zero);
+  const bool rows = kCopies && hpart != nullptr;
   if ((threadIdx.x & 63) == 0) {
     if (c_center) atomicAdd(&h[half - wbase], c_center);
-    if (c_zero) atomicAdd(&hist[0], c_zero);
+    if (c_zero) {
+      if (rows)
+        atomicAdd(&h[0], c_zero);
+      else
+        atomicAdd(&hist[0], c_zero);
+    }
   }
   __syncthreads();
-  for (uint32_t i = threadIdx.x; i < W; i += 1024)
-    if (h[i]) atomicAdd(&hist[wbase + i], h[i]);
+  if (rows) {
+    for (uint32_t i = threadIdx.x; i < 256; i += 1024) {
+      uint32_t t = 0;
+      if (i < W)
+        for (uint32_t c = 0; c < kHistCopies; c++) t += h[c * kHistRow + i];
+      hpart[(size_t)blockIdx.x * 256 + i] = t;
+    }
+    return;
+  }
+  for (uint32_t i = threadIdx.x; i < W; i += 1024) {
+    uint32_t t = h[i];
+    if constexpr (kCopies)
+      for (uint32_t c = 1; c < kHistCopies; c++) t += h[c * kHistRow + i];
+    if (t) atomicAdd(&hist[wbase + i], t);
+  }
+}
+
+// Bins of the 1-byte histogram from the per-block rows: one block per bin,
+// thread t adding rows t, t + 256, ... in order, then a fixed tree.
+__global__ void __launch_bounds__(256) hist_reduce_kernel(const uint32_t* __restrict__ hpart, uint32_t rows,
+                                                          uint32_t* hist, const DevPlan* P, uint32_t pass2) {
+  __shared__ uint32_t red[4];
+  if (P->status) return;
+  if (pass2 && !P->rerun) return;
+  const uint32_t bin = blockIdx.x;
+  uint32_t t = 0;
+  for (uint32_t r = threadIdx.x; r < rows; r += 256) t += hpart[(size_t)r * 256 + bin];
+  t = wave_sum(t);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) hist[bin] = red[0] + red[1] + red[2] + red[3];
 }
 template <typename CT>
 __global__ void __launch_bounds__(1024) hist_kernel(const CT* __restrict__ codes, uint64_t n, uint32_t* hist,
-                                                    const DevPlan* P, uint32_t pass2) {
-  hist_kernel_dev<CT>(codes, n, hist, P, pass2);
+                                                    const DevPlan* P, uint32_t pass2, uint32_t* hpart) {
+  hist_kernel_dev<CT>(codes, n, hist, P, pass2, hpart);
 }
 
 
@@ -973,10 +1030,13 @@ __device__ __forceinline__ void encode_kernel_dev(const CT* __restrict__ codes, 
                                                         const uint64_t* uoff, const uint64_t* toff,
                                                         uint8_t* out, const DevPlan* P) {
   extern __shared__ uint4 s_dyn[];  // [4][words] then [4][C] codes
-  __shared__ uint32_t s_tab[kTabLds];
+  // 1-byte codes have at most 256 symbols: a table that small leaves room
+  // for a second workgroup per CU
+  constexpr uint32_t kTab = sizeof(CT) == 1 ? 256 : kTabLds;
+  __shared__ uint32_t s_tab[kTab];
   if (P->status || P->raw) return;
   const uint32_t nsym = 1u << P->m;
-  const bool lt = nsym <= kTabLds;
+  const bool lt = nsym <= kTab;
   if (lt)
     for (uint32_t i = threadIdx.x; i < nsym; i += kEncNT) s_tab[i] = ((uint32_t)len[i] << 27) | cw[i];
   __syncthreads();

@@ -250,6 +250,7 @@ struct CompWs {
   void* xs;        // every recorded value (sz_quantize only)
   void* xchg;
   uint32_t* hist;
+  uint32_t* hpart;  // per-block histogram rows (1-byte codes)
   uint32_t* progress;
   uint32_t* ticket;
   uint32_t *cbits, *cu, *ctb;
@@ -270,6 +271,7 @@ size_t carve_comp(const Layout& L, uint8_t* base, CompWs* W, bool keep_values = 
   w.xs = keep_values ? c.take<uint8_t>(L.n * L.ts) : nullptr;
   w.xchg = c.take<uint8_t>(L.xchg_bytes + 512);
   w.hist = c.take<uint32_t>(65536 * 4);
+  w.hpart = L.cw == 1 ? c.take<uint32_t>(kHistBlocks * 256 * 4) : nullptr;
   w.progress = c.take<uint32_t>((L.g.ntiles + 1) * 4);
   w.ticket = w.progress + L.g.ntiles;
   w.cbits = c.take<uint32_t>(L.n_chunks * 4);
@@ -361,15 +363,24 @@ int launch_wsweep(const Layout& L, bool comp, const WArgs& a, hipStream_t st) {
   return e == hipSuccess ? SZ_OK : SZ_EHIP;
 }
 
-void launch_hist(const Layout& L, const void* codes, uint32_t* hist, const DevPlan* P, uint32_t pass2,
-                 hipStream_t st) {
+void launch_hist(const Layout& L, const void* codes, uint32_t* hist, uint32_t* hpart, const DevPlan* P,
+                 uint32_t pass2, hipStream_t st) {
+  if (L.cw == 1 && hpart) {
+    // per-block rows, then one block per bin; bins past 2^m come out zero
+    const uint64_t g = std::min<uint64_t>(ceil_div((uint64_t)L.n, 1024 * 64), kHistBlocks);
+    hipLaunchKernelGGL(hist_kernel<uint8_t>, dim3((unsigned)g), dim3(1024), 0, st, (const uint8_t*)codes,
+                       (uint64_t)L.n, hist, P, pass2, hpart);
+    hipLaunchKernelGGL(hist_reduce_kernel, dim3(256), dim3(256), 0, st, (const uint32_t*)hpart, (uint32_t)g, hist, P,
+                       pass2);
+    return;
+  }
   const uint64_t g = std::min<uint64_t>(ceil_div((uint64_t)L.n, 1024 * 16), 1024);
   if (L.cw == 1)
     hipLaunchKernelGGL(hist_kernel<uint8_t>, dim3((unsigned)g), dim3(1024), 0, st, (const uint8_t*)codes,
-                       (uint64_t)L.n, hist, P, pass2);
+                       (uint64_t)L.n, hist, P, pass2, (uint32_t*)nullptr);
   else
     hipLaunchKernelGGL(hist_kernel<uint16_t>, dim3((unsigned)g), dim3(1024), 0, st, (const uint16_t*)codes,
-                       (uint64_t)L.n, hist, P, pass2);
+                       (uint64_t)L.n, hist, P, pass2, (uint32_t*)nullptr);
 }
 
 void fill(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st) {
@@ -442,13 +453,13 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
       stage_begin(ctx, ST_HIST, st);
       sweep_stage_open = ST_HIST;
     }
-    launch_hist(L, W.codes, W.hist, P, 0, st);
+    launch_hist(L, W.codes, W.hist, W.hpart, P, 0, st);
     if (adaptive) {
       hipLaunchKernelGGL(pick_m_kernel, dim3(1), dim3(1024), 0, st, W.hist, P, (uint64_t)L.n, L.theta);
       fill(W.progress, 0, L.g.ntiles + 1, st);
       wa.pass2 = 1;
       if ((rc = launch_wsweep(L, true, wa, st))) return rc;
-      launch_hist(L, W.codes, W.hist, P, 1, st);
+      launch_hist(L, W.codes, W.hist, W.hpart, P, 1, st);
     }
   } else {
     if ((rc = launch_sweep(L, true, a, st))) return rc;

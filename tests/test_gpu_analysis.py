@@ -162,3 +162,23 @@ def test_survey_full_size_cosmology_sample(Z, M):
     assert g["rph_decomp"] == r["rph_decomp"]
     assert g["rph_orig"] == r["rph_orig"]
     assert g["best_layers"] == r["best_layers"]
+
+
+def test_rate_distortion_invariants(Z):
+    """Over decreasing relative bounds on the climate-like field: the maximum
+    error stays within the bound (Metric 1), so PSNR > 20 log10(1 / eb_rel);
+    PSNR rises and the bit-rate does not fall."""
+    import math
+    import fieldgen.gpu as G
+    x = G.climate2d((360, 720), F.BASE_SEED + 1)
+    prev = None
+    for eb in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
+        comp, st = Z.compress(x, layers=1, m=0, eb_mode="rel", eb_rel=eb)
+        xr = Z.decompress(comp).view(x.shape)
+        q = Z.quality(x, xr)
+        assert q["max_abs_err"] <= st["eb_used"]
+        assert q["psnr"] > 20 * math.log10(1 / eb)
+        bits = 8.0 * comp.numel() / x.numel()
+        if prev:
+            assert q["psnr"] > prev[0] and bits >= prev[1], (eb, q["psnr"], bits, prev)
+        prev = (q["psnr"], bits)
