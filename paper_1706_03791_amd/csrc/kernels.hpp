@@ -1167,6 +1167,10 @@ __global__ void finish_kernel(const DevPlan* P, uint64_t* d_size, int32_t* d_sta
 // =================================================================== decode
 struct DecTables {
   uint32_t lut[4096];       // (len << 16) | sym for codes of length <= 12, 0 if longer
+  // 1-byte codes (m <= 8): the codes that lie wholly inside a 12-bit window,
+  // up to four: symbols in bytes 0..3 (first lowest), count in bits 32..35,
+  // their total length in bits 36..39, how many are 0 in bits 40..42
+  uint64_t mlut[4096];
   uint32_t first[32], count[32], start[32];
   // lim[l]: (first[l] + count[l]) << (27 - l), the first 27-bit left-aligned
   // value past the codes of length <= l (non-decreasing in l)
@@ -1249,6 +1253,25 @@ __global__ void __launch_bounds__(1024) dectab_kernel(const uint8_t* comp, uint6
       for (uint32_t q = a; q < b; q++) D->lut[q] = (l << 16) | sym;
     }
   }
+  if (nsym > 256) return;
+  __syncthreads();  // the single-code table above is complete
+  // greedy decode of each 12-bit window: the codes after the first are read
+  // from the window shifted left, and one that reaches past bit 12 ends it
+  for (uint32_t q = tid; q < (1u << kLutBits); q += 1024) {
+    uint64_t syms = 0;
+    uint32_t k = 0, used = 0, nz = 0;
+    while (k < 4) {
+      const uint32_t e = D->lut[(q << used) & ((1u << kLutBits) - 1)];
+      const uint32_t l = e >> 16;
+      if (!e || used + l > (uint32_t)kLutBits) break;
+      const uint32_t sym = e & 0xFFFF;
+      syms |= (uint64_t)sym << (8 * k);
+      nz += sym == 0 ? 1u : 0u;
+      used += l;
+      k++;
+    }
+    D->mlut[q] = syms | ((uint64_t)k << 32) | ((uint64_t)used << 36) | ((uint64_t)nz << 40);
+  }
 }
 
 // K8: one lane per chunk decodes its symbols sequentially from the chunk's
@@ -1285,9 +1308,15 @@ __global__ void __launch_bounds__(256) decode_kernel(const uint8_t* __restrict__
   __shared__ uint32_t s_first[32], s_start[32], s_lim[32];
   __shared__ uint16_t s_syms[kSymLds];
   __shared__ uint32_t s_win[4][256];  // each lane's current 16-byte group, word-major
+  __shared__ uint2 s_mlut[sizeof(CT) == 1 ? 4096 : 1];
   const uint32_t nsorted = D->nsorted;
   const bool syms_lds = nsorted <= kSymLds;
   for (int i = threadIdx.x; i < 4096; i += 256) lut[i] = D->lut[i];
+  if constexpr (sizeof(CT) == 1)
+    for (int i = threadIdx.x; i < 4096; i += 256) {
+      const uint64_t e = D->mlut[i];
+      s_mlut[i] = make_uint2((uint32_t)e, (uint32_t)(e >> 32));
+    }
   if (syms_lds)
     for (uint32_t i = threadIdx.x; i < nsorted; i += 256) s_syms[i] = (uint16_t)sorted_syms[i];
   if (threadIdx.x < 32) {
@@ -1328,9 +1357,97 @@ __global__ void __launch_bounds__(256) decode_kernel(const uint8_t* __restrict__
   uint32_t zc = 0;
   constexpr int SB = 8 * sizeof(CT);  // bits per code
   constexpr int PER = 128 / SB;       // codes per 16-byte store
+  bool bad = false;
+  if constexpr (sizeof(CT) == 1) {
+    // Up to four codes per table read: a window whose codes all fit in 12
+    // bits, lie inside the chunk and inside the row segment is taken whole;
+    // otherwise one code is decoded as below.  Codes leave in aligned 8-byte
+    // stores from a byte accumulator (first code lowest).
+    uint64_t acc8 = 0;
+    int nab = 0;         // codes pending in acc8 (< 8)
+    uint64_t gpos = i0;  // position of the first pending code, a multiple of 8
+    uint64_t i = i0;
+    while (i < i1) {
+      // refill below 32 bits; only the 16-byte group reload branches
+      if (nb < 32 && wi == 4) {
+        s_win[0][t] = pend.x;
+        s_win[1][t] = pend.y;
+        s_win[2][t] = pend.z;
+        s_win[3][t] = pend.w;
+        __asm__ volatile("" ::: "memory");
+        wg += 4;
+        pend = load_words4(words, nwords, wg + 4);
+        wi = 0;
+      }
+      {
+        const bool rf = nb < 32;
+        const uint32_t wd = s_win[wi & 3][t];
+        buf |= rf ? ((uint64_t)wd << (32 - nb)) : 0ull;
+        nb += rf ? 32 : 0;
+        wi += rf ? 1 : 0;
+      }
+      // both tables are read; selects pick the window or its first code, so
+      // lanes that take either stay on one path
+      const uint32_t w12 = (uint32_t)(buf >> (64 - kLutBits));
+      const uint2 me = s_mlut[w12];
+      const uint32_t e = lut[w12];
+      const uint32_t k = me.y & 0xF;
+      const bool fast = k != 0 && (int64_t)k <= rem && i + k <= i1;
+      uint32_t sym = e & 0xFFFF, l1 = e >> 16;
+      if (e == 0) {
+        // a code longer than the table: its length is the count of limits
+        // its 27-bit window reaches
+        const uint32_t v27 = (uint32_t)(buf >> (64 - kLmax));
+        l1 = kLutBits + 1;
+#pragma unroll
+        for (int q = kLutBits + 1; q < kLmax; q++) l1 += (v27 >= s_lim[q]) ? 1u : 0u;
+        if (v27 >= s_lim[kLmax]) {
+          bad = true;
+          break;
+        }
+        const uint32_t idx = s_start[l1] + ((v27 >> (kLmax - l1)) - s_first[l1]);
+        if (syms_lds) {
+          sym = s_syms[idx];
+        } else {
+          sym = sorted_syms[idx];
+          __builtin_amdgcn_s_waitcnt(0x0F70);
+        }
+      }
+      const uint32_t syms = fast ? me.x : sym;
+      const uint32_t l = fast ? ((me.y >> 4) & 0xF) : l1;
+      const uint32_t nz = fast ? ((me.y >> 8) & 0x7) : (sym == 0 ? 1u : 0u);
+      const uint32_t kk = fast ? k : 1u;
+      buf <<= l;
+      nb -= (int)l;
+      pos += l;
+      zc += nz;
+      acc8 |= (uint64_t)syms << (8 * nab);
+      if (nab + (int)kk >= 8) {
+        *(uint64_t*)(codes + gpos) = acc8;
+        acc8 = (nab + (int)kk > 8) ? ((uint64_t)syms >> (8 * (8 - nab))) : 0ull;
+        nab = nab + (int)kk - 8;
+        gpos += 8;
+      } else {
+        nab += (int)kk;
+      }
+      i += kk;
+      rem -= (int64_t)kk;
+      if (rem == 0) {
+        if (zc) atomicAdd(&segcnt[seg], zc);
+        zc = 0;
+        seg++;
+        if (++bx == nbx) bx = 0;
+        rem = min(X, (bx + 1) * Bx) - bx * Bx;
+      }
+    }
+    if (zc && !bad) atomicAdd(&segcnt[seg], zc);
+    if (!bad)
+      for (int q = 0; q < nab; q++) codes[gpos + q] = (CT)(acc8 >> (8 * q));
+    if (bad || pos != end) set_status(P, SZ_ECORRUPT);
+    return;
+  }
   uint64_t acc_lo = 0, acc_hi = 0;
   int nacc = 0;
-  bool bad = false;
   for (uint64_t i = i0; i < i1; i++) {
     if (nb < 32) {
       if (wi == 4) {
