@@ -1171,6 +1171,11 @@ struct DecTables {
   // up to four: symbols in bytes 0..3 (first lowest), count in bits 32..35,
   // their total length in bits 36..39, how many are 0 in bits 40..42
   uint64_t mlut[4096];
+  // 1-byte codes with at most kLut2Max 12-bit prefixes of longer codes: the
+  // codes of 13..16 bits, (len << 16) | sym, at (prefix - lut2_p0) * 16 plus
+  // the next 4 bits; 0 for longer codes.  lut2_n = 0 when not built.
+  uint32_t lut2[128 * 16];
+  uint32_t lut2_p0, lut2_n;
   uint32_t first[32], count[32], start[32];
   // lim[l]: (first[l] + count[l]) << (27 - l), the first 27-bit left-aligned
   // value past the codes of length <= l (non-decreasing in l)
@@ -1178,6 +1183,7 @@ struct DecTables {
   uint32_t nsorted;
 };
 constexpr int kLutBits = 12;
+constexpr uint32_t kLut2Max = 128;
 
 // Decode tables from the codebook section; checks symbols strictly
 // increasing and the Kraft condition of the canonical code.
@@ -1272,6 +1278,34 @@ __global__ void __launch_bounds__(1024) dectab_kernel(const uint8_t* comp, uint6
     }
     D->mlut[q] = syms | ((uint64_t)k << 32) | ((uint64_t)used << 36) | ((uint64_t)nz << 40);
   }
+  // Codes longer than 12 bits fill the code space after the short ones, so
+  // their 12-bit prefixes are [p0, 4096) with p0 the space the short codes
+  // take (the code is complete).
+  uint32_t p0 = 0;
+  for (int l = 1; l <= kLutBits; l++) p0 += s_cnt[l] << (kLutBits - l);
+  const uint32_t nlong = (1u << kLutBits) - p0;
+  if (nlong > kLut2Max) {
+    if (tid == 0) D->lut2_n = 0;
+    return;
+  }
+  for (uint32_t q = tid; q < kLut2Max * 16; q += 1024) D->lut2[q] = 0;
+  __syncthreads();
+  for (uint32_t v = tid; v < n_used; v += 1024) {
+    const uint32_t sym = (uint32_t)(K[v] & 0xFFFF);
+    const uint32_t l = (uint32_t)(K[v] >> 16);
+    if (l > (uint32_t)kLutBits && l <= 16) {
+      const uint32_t code = s_first[l] + (v - s_start[l]);
+      const uint32_t a = code << (16 - l), b = (code + 1) << (16 - l);
+      for (uint32_t x = a; x < b; x++) {
+        const uint32_t r = (x >> 4) - p0;
+        if (r < kLut2Max) D->lut2[r * 16 + (x & 15)] = (l << 16) | sym;
+      }
+    }
+  }
+  if (tid == 0) {
+    D->lut2_p0 = p0;
+    D->lut2_n = nlong;
+  }
 }
 
 // K8: one lane per chunk decodes its symbols sequentially from the chunk's
@@ -1283,6 +1317,8 @@ __global__ void __launch_bounds__(1024) dectab_kernel(const uint8_t* comp, uint6
 // codes leave in 16-byte stores, and unpredictable codes are counted per
 // row segment (block row) with the segment tracked incrementally.
 constexpr uint32_t kSymLds = 4096;
+constexpr int kDecRing = 16;    // words of bitstream per lane in LDS (1-byte codes)
+constexpr int kDecPeriod = 8;   // iterations between the reloads of all lanes
 
 __device__ __forceinline__ uint4 load_words4(const uint32_t* words, uint64_t nwords, uint64_t w) {
   if (w + 4 <= nwords) return *(const uint4*)(words + w);
@@ -1306,11 +1342,18 @@ __global__ void __launch_bounds__(256) decode_kernel(const uint8_t* __restrict__
                                                      int32_t nbx, DevPlan* P) {
   __shared__ uint32_t lut[4096];
   __shared__ uint32_t s_first[32], s_start[32], s_lim[32];
-  __shared__ uint16_t s_syms[kSymLds];
-  __shared__ uint32_t s_win[4][256];  // each lane's current 16-byte group, word-major
+  constexpr uint32_t kSyms = sizeof(CT) == 1 ? 256 : kSymLds;
+  __shared__ uint16_t s_syms[kSyms];
+  __shared__ uint32_t s_win[sizeof(CT) == 1 ? 1 : 4][256];  // each lane's current 16-byte group, word-major
+  __shared__ uint32_t s_lut2[sizeof(CT) == 1 ? kLut2Max * 16 : 1];
   __shared__ uint2 s_mlut[sizeof(CT) == 1 ? 4096 : 1];
+  __shared__ uint32_t s_ring[sizeof(CT) == 1 ? kDecRing : 1][256];  // 1-byte codes: per-lane bitstream ring
   const uint32_t nsorted = D->nsorted;
-  const bool syms_lds = nsorted <= kSymLds;
+  const bool syms_lds = nsorted <= kSyms;
+  const uint32_t n2 = sizeof(CT) == 1 ? D->lut2_n : 0u, p02 = sizeof(CT) == 1 ? D->lut2_p0 : 0u;
+  if constexpr (sizeof(CT) == 1)
+    if (n2)
+      for (uint32_t i = threadIdx.x; i < kLut2Max * 16; i += 256) s_lut2[i] = D->lut2[i];
   for (int i = threadIdx.x; i < 4096; i += 256) lut[i] = D->lut[i];
   if constexpr (sizeof(CT) == 1)
     for (int i = threadIdx.x; i < 4096; i += 256) {
@@ -1337,18 +1380,22 @@ __global__ void __launch_bounds__(256) decode_kernel(const uint8_t* __restrict__
   const uint64_t end = pos + cbits[c];
   const uint64_t i0 = c * C, i1 = min(n, i0 + C);
   uint64_t wg = (pos >> 5) & ~3ull;
-  {
+  uint4 pend = make_uint4(0, 0, 0, 0);
+  int wi = 0;
+  uint64_t buf = 0;
+  int nb = 0;
+  if constexpr (sizeof(CT) != 1) {
     const uint4 g0 = load_words4(words, nwords, wg);
     s_win[0][t] = g0.x;
     s_win[1][t] = g0.y;
     s_win[2][t] = g0.z;
     s_win[3][t] = g0.w;
+    pend = load_words4(words, nwords, wg + 4);
+    wi = (int)((pos >> 5) - wg);  // index of the next word to take from the slot
+    buf = ((uint64_t)s_win[wi][t] << 32) << (pos & 31);
+    nb = 32 - (int)(pos & 31);
+    wi++;
   }
-  uint4 pend = load_words4(words, nwords, wg + 4);
-  int wi = (int)((pos >> 5) - wg);  // index of the next word to take from the slot
-  uint64_t buf = ((uint64_t)s_win[wi][t] << 32) << (pos & 31);
-  int nb = 32 - (int)(pos & 31);
-  wi++;
   // row segment of i0: seg = row * nbx + col / Bx, rem = elements left in it
   const uint64_t row0 = i0 / (uint64_t)X, col0 = i0 - row0 * (uint64_t)X;
   int64_t bx = (int64_t)(col0 / (uint64_t)Bx);
@@ -1363,28 +1410,58 @@ __global__ void __launch_bounds__(256) decode_kernel(const uint8_t* __restrict__
     // bits, lie inside the chunk and inside the row segment is taken whole;
     // otherwise one code is decoded as below.  Codes leave in aligned 8-byte
     // stores from a byte accumulator (first code lowest).
+    // The bitstream reaches each lane through a ring of kDecRing words in
+    // LDS, refilled 8 words at a time with loads issued every kDecPeriod
+    // iterations and landed at the next period: the waits for them (which
+    // also wait for the code stores before them) then come once per period
+    // for the whole wave rather than whenever one lane runs out.  A lane
+    // that still runs out loads its next word directly (rare).
     uint64_t acc8 = 0;
     int nab = 0;         // codes pending in acc8 (< 8)
     uint64_t gpos = i0;  // position of the first pending code, a multiple of 8
     uint64_t i = i0;
+    const uint64_t w0 = pos >> 5;
+#pragma unroll
+    for (int q = 0; q < kDecRing / 4; q++) {
+      const uint4 g = load_words4(words, nwords, w0 + 4 * q);
+      s_ring[(w0 + 4 * q + 0) & (kDecRing - 1)][t] = g.x;
+      s_ring[(w0 + 4 * q + 1) & (kDecRing - 1)][t] = g.y;
+      s_ring[(w0 + 4 * q + 2) & (kDecRing - 1)][t] = g.z;
+      s_ring[(w0 + 4 * q + 3) & (kDecRing - 1)][t] = g.w;
+    }
+    uint64_t fland = w0 + kDecRing;  // words landed in the ring: [fland - kDecRing, fland)
+    uint64_t fiss = fland;           // words requested (landed or in flight)
+    uint4 p0 = make_uint4(0, 0, 0, 0), p1 = p0;  // in-flight words [fland, fland + 8)
+    // the ring slot of word w is w % kDecRing
+    buf = ((uint64_t)s_ring[w0 & (kDecRing - 1)][t] << 32) << (pos & 31);
+    nb = 32 - (int)(pos & 31);
+    uint64_t rword = w0 + 1;  // next word to take into buf
+    uint32_t it = 0;
     while (i < i1) {
-      // refill below 32 bits; only the 16-byte group reload branches
-      if (nb < 32 && wi == 4) {
-        s_win[0][t] = pend.x;
-        s_win[1][t] = pend.y;
-        s_win[2][t] = pend.z;
-        s_win[3][t] = pend.w;
+      if ((it++ & (kDecPeriod - 1)) == 0) {
+        if (fiss > fland) {
+          const uint32_t wv[8] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
+#pragma unroll
+          for (int q = 0; q < 8; q++) s_ring[(fland + q) & (kDecRing - 1)][t] = wv[q];
+          fland += 8;
+        }
+        if (fland - rword <= (uint64_t)(kDecRing - 8)) {
+          p0 = load_words4(words, nwords, fland);
+          p1 = load_words4(words, nwords, fland + 4);
+          fiss = fland + 8;
+        }
+      }
+      if (nb < 32 && rword >= fland) {
+        // ran out: take the next word directly into its slot
+        s_ring[rword & (kDecRing - 1)][t] = rword < nwords ? words[rword] : 0u;
         __asm__ volatile("" ::: "memory");
-        wg += 4;
-        pend = load_words4(words, nwords, wg + 4);
-        wi = 0;
       }
       {
         const bool rf = nb < 32;
-        const uint32_t wd = s_win[wi & 3][t];
+        const uint32_t wd = s_ring[rword & (kDecRing - 1)][t];
         buf |= rf ? ((uint64_t)wd << (32 - nb)) : 0ull;
         nb += rf ? 32 : 0;
-        wi += rf ? 1 : 0;
+        rword += rf ? 1 : 0;
       }
       // both tables are read; selects pick the window or its first code, so
       // lanes that take either stay on one path
@@ -1394,8 +1471,15 @@ __global__ void __launch_bounds__(256) decode_kernel(const uint8_t* __restrict__
       const uint32_t k = me.y & 0xF;
       const bool fast = k != 0 && (int64_t)k <= rem && i + k <= i1;
       uint32_t sym = e & 0xFFFF, l1 = e >> 16;
-      if (e == 0) {
-        // a code longer than the table: its length is the count of limits
+      uint32_t e2 = 0;
+      if (e == 0 && n2) {
+        // a code of 13..16 bits: the second table, by prefix and next 4 bits
+        e2 = s_lut2[(w12 - p02) * 16 + (uint32_t)((buf >> (64 - 16)) & 15)];
+        sym = e2 & 0xFFFF;
+        l1 = e2 >> 16;
+      }
+      if (e == 0 && e2 == 0) {
+        // a code longer than the tables: its length is the count of limits
         // its 27-bit window reaches
         const uint32_t v27 = (uint32_t)(buf >> (64 - kLmax));
         l1 = kLutBits + 1;
@@ -1444,8 +1528,7 @@ __global__ void __launch_bounds__(256) decode_kernel(const uint8_t* __restrict__
     if (!bad)
       for (int q = 0; q < nab; q++) codes[gpos + q] = (CT)(acc8 >> (8 * q));
     if (bad || pos != end) set_status(P, SZ_ECORRUPT);
-    return;
-  }
+  } else {
   uint64_t acc_lo = 0, acc_hi = 0;
   int nacc = 0;
   for (uint64_t i = i0; i < i1; i++) {
@@ -1520,6 +1603,7 @@ __global__ void __launch_bounds__(256) decode_kernel(const uint8_t* __restrict__
     }
   }
   if (bad || pos != end) set_status(P, SZ_ECORRUPT);
+  }
 }
 
 // K9a: kept-bit count of every unpredictable value, summed per group of 1024.
