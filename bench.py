@@ -197,17 +197,18 @@ def bench_cosmo_extras(Z, torch, n, steps=3):
     return out
 
 
-def layer_study(Z, torch, eb_rels=(1e-4,), samples=(None, (900, 1800))):
-    """Best-layer study (Sec. III-B, Table II) on the 1800x3600 climate-like
-    field: R_PH from decompressed and from original neighbours, n = 1..4."""
+def layer_study(Z, torch, eb_rels=(1e-4,), samples=(None, (900, 1800)), field="climate2d"):
+    """Best-layer study (Sec. III-B, Table II): R_PH from decompressed and
+    from original neighbours, n = 1..4, on the 1800x3600 climate-like field
+    or on the smooth separable-sine 256^3 field."""
     import fieldgen as F
     import fieldgen.gpu as G
-    x = G.climate2d((1800, 3600), F.BASE_SEED + 1)
+    x = G.climate2d((1800, 3600), F.BASE_SEED + 1) if field == "climate2d" else G.sines3d((256, 256, 256))
     rows = []
     for eb in eb_rels:
         for smp in samples:
             r = Z.layer_survey(x, sample=smp, eb_mode="rel", eb_rel=eb)
-            rows.append({"eb_rel": eb, "sample": list(smp) if smp else [1800, 3600],
+            rows.append({"field": field, "eb_rel": eb, "sample": list(smp) if smp else list(x.shape),
                          "rph_decomp": [round(v, 6) for v in r["rph_decomp"]],
                          "rph_orig": [round(v, 6) for v in r["rph_orig"]],
                          "best_layers": r["best_layers"],
@@ -240,7 +241,8 @@ def study(Z, torch):
         del x
         torch.cuda.empty_cache()
     return {"rate_distortion": rows,
-            "layer_study": layer_study(Z, torch, eb_rels=(1e-3, 1e-4, 1e-5, 1e-6))}
+            "layer_study": layer_study(Z, torch, eb_rels=(1e-3, 1e-4, 1e-5, 1e-6))
+            + layer_study(Z, torch, eb_rels=(1e-3, 1e-4, 1e-5), samples=(None, (64, 64, 64)), field="sines3d")}
 
 
 def bench_batched(Z, torch, count=64, reps=5):

@@ -94,6 +94,17 @@ def cosmo3d(shape, seed: int, device="cuda"):
     return grf(shape, -3.0, 1.5, seed, device).exp_()
 
 
+def sines3d(shape, device="cuda"):
+    """sin(0.1x) cos(0.07y) sin(0.05z) on integer indices (x fastest): the
+    separable component of the small-case recipe, without Gaussians or noise."""
+    import torch
+    nz, ny, nx = shape
+    z = torch.arange(nz, device=device, dtype=torch.float64)[:, None, None]
+    y = torch.arange(ny, device=device, dtype=torch.float64)[None, :, None]
+    x = torch.arange(nx, device=device, dtype=torch.float64)[None, None, :]
+    return (torch.sin(0.1 * x) * torch.cos(0.07 * y) * torch.sin(0.05 * z)).float().contiguous()
+
+
 def velocity3d(shape, seed: int, device="cuda"):
     """Zero-mean velocity-like k^-3 Gaussian random field of std 300 (float32)."""
     return grf(shape, -3.0, 300.0, seed, device)

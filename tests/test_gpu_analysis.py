@@ -182,3 +182,15 @@ def test_rate_distortion_invariants(Z):
         if prev:
             assert q["psnr"] > prev[0] and bits >= prev[1], (eb, q["psnr"], bits, prev)
         prev = (q["psnr"], bits)
+
+
+def test_survey_smooth_field_prefers_more_layers_on_original_values(Z, M):
+    """On the smooth separable-sine field, original neighbours favour two or
+    more layers while decompressed neighbours favour one (Table II's effect)."""
+    import fieldgen.gpu as G
+    x = G.sines3d((64, 64, 64))
+    g = Z.layer_survey(x, eb_mode="rel", eb_rel=1e-4)
+    r = M.layer_survey(x.cpu().numpy(), eb_mode="rel", eb_rel=1e-4)
+    assert g["rph_decomp"] == r["rph_decomp"] and g["rph_orig"] == r["rph_orig"]
+    assert g["best_layers"] == 1
+    assert max(range(4), key=lambda n: g["rph_orig"][n]) >= 1
