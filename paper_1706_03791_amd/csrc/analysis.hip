@@ -309,7 +309,7 @@ int survey_t(sz_ctx* ctx, const sz_params* p, const Layout& Lf, const void* d_in
   I.dtype = (uint32_t)Lf.dtype;
   hipLaunchKernelGGL(plan_init_kernel, dim3(1), dim3(64), 0, st, P, I);
   if (Lf.eb_mode != SZ_EB_ABS) {
-    const uint64_t g = std::min<uint64_t>(ceil_div((uint64_t)Lf.n, 256 * 16 / sizeof(T)) + 1, 4096);
+    const uint64_t g = std::min<uint64_t>(ceil_div((uint64_t)Lf.n, 256 * 16 / sizeof(T)) + 1, 512);
     hipLaunchKernelGGL(minmax_kernel<T>, dim3((unsigned)g), dim3(256), 0, st, (const T*)d_in, (uint64_t)Lf.n, P);
   }
   hipLaunchKernelGGL(eb_resolve_kernel<T>, dim3(1), dim3(64), 0, st, P, I);

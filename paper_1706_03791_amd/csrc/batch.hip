@@ -295,7 +295,7 @@ int build_plan(sz_batch* b, int cand, BPlan& P) {
     // dependence chain of the sweep, in steps: the longest raster path
     cost[i] = (double)(L.dims3[0] + L.dims3[1] + L.dims3[2]) + 1e-9 * (double)L.n;
     const uint64_t ts = (uint64_t)L.ts;
-    P.gx_mm = std::max<unsigned>(P.gx_mm, (unsigned)std::min<uint64_t>(ceil_div(L.n, 256 * 16 / ts) + 1, 4096));
+    P.gx_mm = std::max<unsigned>(P.gx_mm, (unsigned)std::min<uint64_t>(ceil_div(L.n, 256 * 16 / ts) + 1, 512));
     P.gx_zero = std::max<unsigned>(P.gx_zero, (unsigned)std::min<uint64_t>(ceil_div(65536 + L.g.ntiles, 256), 512));
     P.gx_hist = std::max<unsigned>(P.gx_hist, (unsigned)std::min<uint64_t>(ceil_div(L.n, 1024 * 16), 1024));
     P.gx_ch = std::max<unsigned>(P.gx_ch, (unsigned)std::min<uint64_t>(ceil_div(L.n_chunks, 4), 8192));

@@ -306,6 +306,74 @@ __device__ void bitonic_sort(uint64_t* k, uint32_t n) {
   }
 }
 
+// The same network for n keys in global memory (n a power of two), run by one
+// workgroup: the passes whose stride stays inside an aligned chunk of CH keys
+// run on that chunk in LDS (`buf`, CH keys), the wider ones as global passes
+// that load 8 pairs per thread before comparing.  Directions follow the
+// global index, so the result is that of bitonic_sort.
+template <int NT>
+__device__ void bitonic_sort_big(uint64_t* k, uint32_t n, uint64_t* buf, uint32_t CH) {
+  if (n <= CH) {
+    for (uint32_t e = threadIdx.x; e < n; e += NT) buf[e] = k[e];
+    __syncthreads();
+    bitonic_sort<NT>(buf, n);
+    for (uint32_t e = threadIdx.x; e < n; e += NT) k[e] = buf[e];
+    __syncthreads();
+    return;
+  }
+  // strides size_lo .. 1 of sizes size_lo * 2 .. size_hi, chunk by chunk in LDS
+  auto chunks = [&](uint32_t size_first, uint32_t size_last, uint32_t first_stride) {
+    for (uint32_t c0 = 0; c0 < n; c0 += CH) {
+      for (uint32_t e = threadIdx.x; e < CH; e += NT) buf[e] = k[c0 + e];
+      __syncthreads();
+      for (uint32_t size = size_first; size <= size_last; size <<= 1) {
+        for (uint32_t stride = min(size >> 1, first_stride); stride > 0; stride >>= 1) {
+          for (uint32_t t = threadIdx.x; t < CH / 2; t += NT) {
+            const uint32_t lo = 2 * t - (t & (stride - 1)), hi = lo + stride;
+            const bool up = (((c0 + lo) & size) == 0);
+            const uint64_t a = buf[lo], b = buf[hi];
+            if ((a > b) == up) {
+              buf[lo] = b;
+              buf[hi] = a;
+            }
+          }
+          __syncthreads();
+        }
+      }
+      for (uint32_t e = threadIdx.x; e < CH; e += NT) k[c0 + e] = buf[e];
+      __syncthreads();
+    }
+  };
+  chunks(2, CH, CH);
+  for (uint32_t size = 2 * CH; size <= n; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride >= CH; stride >>= 1) {
+      constexpr int B = 8;
+      for (uint32_t t0 = threadIdx.x; t0 < n / 2; t0 += NT * B) {
+        uint64_t a[B], b[B];
+        uint32_t lo[B];
+#pragma unroll
+        for (int u = 0; u < B; u++) {
+          const uint32_t t = t0 + u * NT;
+          lo[u] = 2 * t - (t & (stride - 1));
+          a[u] = t < n / 2 ? k[lo[u]] : 0;
+          b[u] = t < n / 2 ? k[lo[u] + stride] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < B; u++) {
+          const uint32_t t = t0 + u * NT;
+          const bool up = ((lo[u] & size) == 0);
+          if (t < n / 2 && (a[u] > b[u]) == up) {
+            k[lo[u]] = b[u];
+            k[lo[u] + stride] = a[u];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    chunks(size, size, CH >> 1);
+  }
+}
+
 // --------------------------------------------------- K4: Huffman codebook
 struct CodebookArgs {
   const uint32_t* hist;
@@ -377,29 +445,47 @@ __device__ __forceinline__ void codebook_kernel_dev(CodebookArgs A) {
     }
   } else {
     for (int attempt = 0; attempt < 64; attempt++) {
-      bitonic_sort<kCbNT>(K, np2);
+      if (in_lds)
+        bitonic_sort<kCbNT>(K, np2);
+      else
+        bitonic_sort_big<kCbNT>(K, np2, s_w, 2 * kCbLdsSyms);
       if (tid == 0) {
-        // two-queue merge: leaves 0..s-1, internal nodes s..2s-2
+        // two-queue merge: leaves 0..s-1, internal nodes s..2s-2.  The two
+        // heads of each queue live in registers and the value after a head
+        // is read when that head is taken, so a pick rarely waits on memory.
+        constexpr uint64_t kInf = ~0ull;
         uint32_t i = 0, j = s, next = s;
+        uint64_t l0 = K[0] >> 16, l1 = (1 < s) ? (K[1] >> 16) : kInf;  // leaves i, i + 1
+        uint64_t n0 = kInf, n1 = kInf;  // internal nodes j, j + 1 (when below next)
         for (uint32_t step = 0; step + 1 < s; step++) {
           uint32_t pk[2];
           uint64_t wk[2];
+#pragma unroll
           for (int q = 0; q < 2; q++) {
-            const uint64_t wl = (i < s) ? (K[i] >> 16) : ~0ull;
-            const uint64_t wi = (j < next) ? W[j] : ~0ull;
-            if (i < s && (j >= next || wl <= wi)) {
+            if (i < s && (j >= next || l0 <= n0)) {
               pk[q] = i;
-              wk[q] = wl;
+              wk[q] = l0;
               i++;
+              l0 = l1;
+              l1 = (i + 1 < s) ? (K[i + 1] >> 16) : kInf;
             } else {
               pk[q] = j;
-              wk[q] = wi;
+              wk[q] = n0;
               j++;
+              n0 = n1;
+              n1 = (j + 1 < next) ? W[j + 1] : kInf;
             }
           }
-          W[next] = wk[0] + wk[1];
+          const uint64_t wsum = wk[0] + wk[1];
+          W[next] = wsum;
           PAR[pk[0]] = next;
           PAR[pk[1]] = next;
+          // the new node joins the internal queue as its head or second entry
+          // when the queue held fewer than two
+          if (next == j)
+            n0 = wsum;
+          else if (next == j + 1)
+            n1 = wsum;
           next++;
         }
         PAR[2 * s - 2] = 2 * s - 2;
@@ -425,10 +511,29 @@ __device__ __forceinline__ void codebook_kernel_dev(CodebookArgs A) {
       }
       __syncthreads();
       for (uint32_t span = 1; span < nn; span <<= 1) {
-        for (uint32_t v = tid; v < nn; v += kCbNT) {
-          const uint32_t a = ANC[v];
-          DEP2[v] = DEP[v] + DEP[a];
-          ANC2[v] = ANC[a];
+        // 4 nodes per thread at a time, so their loads overlap
+        for (uint32_t v0 = tid; v0 < nn; v0 += 4 * kCbNT) {
+          uint32_t a[4], d[4];
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            const uint32_t v = v0 + u * kCbNT;
+            a[u] = v < nn ? ANC[v] : 0u;
+            d[u] = v < nn ? DEP[v] : 0u;
+          }
+          uint32_t da[4], aa[4];
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            da[u] = DEP[a[u]];
+            aa[u] = ANC[a[u]];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            const uint32_t v = v0 + u * kCbNT;
+            if (v < nn) {
+              DEP2[v] = d[u] + da[u];
+              ANC2[v] = aa[u];
+            }
+          }
         }
         __syncthreads();
         uint32_t* t0 = ANC; ANC = ANC2; ANC2 = t0;
@@ -479,7 +584,10 @@ __device__ __forceinline__ void codebook_kernel_dev(CodebookArgs A) {
         start += s_cnt[l];
       }
     }
-    bitonic_sort<kCbNT>(K, np2);
+    if (in_lds)
+      bitonic_sort<kCbNT>(K, np2);
+    else
+      bitonic_sort_big<kCbNT>(K, np2, s_w, 2 * kCbLdsSyms);
     for (uint32_t v = tid; v < s; v += kCbNT) {
       const uint32_t sym = (uint32_t)(K[v] & 0xFFFF);
       const uint32_t l = (uint32_t)(K[v] >> 16);
@@ -1248,7 +1356,10 @@ __global__ void __launch_bounds__(1024) dectab_kernel(const uint8_t* comp, uint6
     if (tid == 0) set_status(P, SZ_ECORRUPT);
     return;
   }
-  bitonic_sort<1024>(K, np2);
+  if (K == s_keys)
+    bitonic_sort<1024>(K, np2);
+  else
+    bitonic_sort_big<1024>(K, np2, s_keys, 4096);
   for (uint32_t v = tid; v < n_used; v += 1024) {
     const uint32_t sym = (uint32_t)(K[v] & 0xFFFF);
     const uint32_t l = (uint32_t)(K[v] >> 16);

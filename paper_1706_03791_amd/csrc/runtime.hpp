@@ -416,7 +416,9 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
   hipLaunchKernelGGL(plan_init_kernel, dim3(1), dim3(64), 0, st, P, I);
   stage_begin(ctx, ST_RANGE, st);
   if (L.eb_mode != SZ_EB_ABS) {
-    const uint64_t g = std::min<uint64_t>(ceil_div(L.n, 256 * 16 / sizeof(T)) + 1, 4096);
+    // 512 blocks (four loads in flight per thread) reach the copy bandwidth;
+    // more would only add same-address atomics at the end
+    const uint64_t g = std::min<uint64_t>(ceil_div(L.n, 256 * 16 / sizeof(T)) + 1, 512);
     hipLaunchKernelGGL(minmax_kernel<T>, dim3((unsigned)g), dim3(256), 0, st, (const T*)d_in, (uint64_t)L.n, P);
   }
   hipLaunchKernelGGL(eb_resolve_kernel<T>, dim3(1), dim3(64), 0, st, P, I);
