@@ -1083,6 +1083,14 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
     uint64_t zpos = uoff[c] + wave_exscan(myz);
     uint64_t tpos = toff[c] + wave_exscan(mytb);
     __builtin_amdgcn_wave_barrier();
+    // The lane's bits gather left-aligned in a 64-bit register from bit
+    // (bpos % 32) of word bpos / 32 on.  Words wholly inside the lane's range
+    // get plain stores; its first and last words, which it may share with the
+    // neighbouring lanes, are ORed in.
+    uint32_t aw = (uint32_t)(bpos >> 5);  // word the accumulator starts at
+    const uint32_t w_first = aw;
+    int used = (int)(bpos & 31);          // bits of that word before the lane's own
+    uint64_t acc = 0;
     for (uint32_t j = 0; j < per; j += 4) {
       uint32_t sym[4];
       lds_code4<CT>(sc, k0 + j, sym);
@@ -1093,14 +1101,17 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
         const uint32_t e = code_entry<LT>(code, s_tab, len, cw);
         const int l = (int)(e >> 27);
         const uint32_t v = e & 0x07FFFFFFu;
-        const uint32_t w = (uint32_t)(bpos >> 5);
-        const int off = (int)(bpos & 31);
-        if (off + l <= 32) {
-          atomicOr(&words[w], v << (32 - off - l));
-        } else {
-          const int first = 32 - off;
-          atomicOr(&words[w], v >> (l - first));
-          atomicOr(&words[w + 1], v << (32 - (l - first)));
+        acc |= (uint64_t)v << (64 - used - l);  // used < 32 and l <= 27: inside 64 bits
+        used += l;
+        if (used >= 32) {
+          const uint32_t word = (uint32_t)(acc >> 32);
+          if (aw == w_first)
+            atomicOr(&words[aw], word);
+          else
+            words[aw] = word;
+          aw++;
+          acc <<= 32;
+          used -= 32;
         }
         bpos += l;
         if (code == 0) {
@@ -1114,6 +1125,7 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
         }
       }
     }
+    if (used > 0) atomicOr(&words[aw], (uint32_t)(acc >> 32));
     __builtin_amdgcn_wave_barrier();
     const uint64_t gw0 = b0 >> 5;
     const uint64_t bend = b0 + nb;
