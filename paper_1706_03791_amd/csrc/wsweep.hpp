@@ -339,6 +339,38 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
 #pragma unroll
     for (int e = 0; e < G; e++) s_ring[w][a][(int)((q * G + e) & (kWRing - 1))][ly] = piece_elem<T>(src, e);
   };
+  // Compression refills the rings cooperatively: each 16-byte load of the
+  // wave takes XPC lanes per row (piece ly % XPC of row ly / XPC + h * 64 /
+  // XPC), so it touches 64 / XPC cache lines rather than 64, and the pieces
+  // go to their rows' ring columns.  Row r's window of group gr starts at
+  // element rbase + r * X - (AZ w + a + r).
+  constexpr int RPI = 64 / XPC;  // rows per load instruction
+  int64_t rbase[AZ];
+#pragma unroll
+  for (int a = 0; a < AZ; a++) rbase[a] = rb[a] - (int64_t)ly * Xd;
+  auto coop_chunk = [&](int a, int h, int gr) -> int64_t {  // chunk after row r's first chunk of group gr
+    const int r = ly / XPC + RPI * h;
+    const int64_t wl = rbase[a] + (int64_t)r * Xd - (int64_t)(AZ * w + a + r);
+    return ((wl + (int64_t)gr * G) >> 3) + 1;
+  };
+  auto coop_load = [&](int a, int gr, uint4 (&dst)[XPC]) {
+#pragma unroll
+    for (int h = 0; h < XPC; h++) {
+      const int off = chunk_off(coop_chunk(a, h, gr));
+      dst[h] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                             rin, off == kOut ? kOut : off + 16 * (ly % XPC), 0, 0));
+    }
+  };
+  auto coop_put = [&](int a, int gr, const uint4 (&src)[XPC]) {
+#pragma unroll
+    for (int h = 0; h < XPC; h++) {
+      const int r = ly / XPC + RPI * h, pc = ly % XPC;
+      const int64_t q = coop_chunk(a, h, gr);
+#pragma unroll
+      for (int e = 0; e < EPP; e++)
+        s_ring[w][a][(int)((q * G + pc * EPP + e) & (kWRing - 1))][r] = piece_elem<T>(&src[h], e);
+    }
+  };
 
   // Output chunk q of sub-row a: only the elements of this row are written.
   auto store_codes = [&](int a, int64_t q, CW word) {
@@ -538,7 +570,8 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
     for (int a = 0; a < AZ; a++) {
       const int64_t q = (wlo[a] + (int64_t)(g + 1) * G) >> 3;  // first chunk of the next window
       if constexpr (COMP) {
-        load_x_chunk(q + 1, xpre[a]);
+        (void)q;
+        coop_load(a, g + 1, xpre[a]);
         zn[a] = 0;
       } else {
         cpre[a] = load_code_chunk<CT>(rin, q + 2 - cbase);
@@ -741,7 +774,7 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
         store_codes(a, q, word);
         cprv[a] = cacc[a];
         cacc[a] = (CW)0;
-        if (more) ring_put(a, q + 2, xpre[a]);
+        if (more) coop_put(a, g + 1, xpre[a]);
       } else {
         flush_values(a, q);
         c0[a] = c1[a];
