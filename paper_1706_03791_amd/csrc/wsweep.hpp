@@ -361,6 +361,31 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
                                              rin, off == kOut ? kOut : off + 16 * (ly % XPC), 0, 0));
     }
   };
+  // Decompression flushes the same way: lane ly stores piece ly % XPC of the
+  // chunk row r completed in group gr, reading the values from r's column.
+  auto coop_flush = [&](int a, int gr) {
+    T* xg = (T*)A.xo;
+    const int64_t zr = z0 + AZ * w + a;
+#pragma unroll
+    for (int h = 0; h < XPC; h++) {
+      const int r = ly / XPC + RPI * h, pc = ly % XPC;
+      if (!(zr < zb1 && y0 + r < yb1)) continue;
+      const int64_t lo = rbase[a] + (int64_t)r * Xd, hi = lo + BX;
+      const int64_t wl = lo - (int64_t)(AZ * w + a + r);
+      const int64_t e0 = ((wl + (int64_t)gr * G) >> 3) * G + pc * EPP;  // first element of the piece
+      if (e0 + EPP <= lo || e0 >= hi) continue;
+      T v[EPP];
+#pragma unroll
+      for (int e = 0; e < EPP; e++) v[e] = s_ring[w][a][(int)((e0 + e) & (kWRing - 1))][r];
+      if (e0 >= lo && e0 + EPP <= hi) {
+        *(uint4*)(xg + e0) = pack_piece<T>(v, 0);
+      } else {
+#pragma unroll
+        for (int e = 0; e < EPP; e++)
+          if (e0 + e >= lo && e0 + e < hi) xg[e0 + e] = v[e];
+      }
+    }
+  };
   auto coop_put = [&](int a, int gr, const uint4 (&src)[XPC]) {
 #pragma unroll
     for (int h = 0; h < XPC; h++) {
@@ -776,7 +801,8 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
         cacc[a] = (CW)0;
         if (more) coop_put(a, g + 1, xpre[a]);
       } else {
-        flush_values(a, q);
+        (void)q;
+        coop_flush(a, g);
         c0[a] = c1[a];
         c1[a] = c2[a];
         c2[a] = cpre[a];
