@@ -418,6 +418,27 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
       }
     }
   };
+  // Chunks 2k and 2k + 1 of a row leave as one aligned store when both lie
+  // inside the row (half the store instructions and cache-line writes);
+  // otherwise each chunk is stored on its own.
+  auto store_pair = [&](int a, int64_t qe, CW w0, CW w1) {
+    if (!rv[a]) return;
+    const int64_t e0 = qe * G, lo = rb[a], hi = rb[a] + BX;
+    if (e0 >= lo && e0 + 2 * G <= hi) {
+      CT* cg = (CT*)A.codes;
+      if constexpr (sizeof(CT) == 1) {
+        const uint64_t a0 = (uint64_t)w0, a1 = (uint64_t)w1;
+        *(uint4*)(cg + e0) = make_uint4((uint32_t)a0, (uint32_t)(a0 >> 32), (uint32_t)a1, (uint32_t)(a1 >> 32));
+      } else {
+        const uint64_t a0 = (uint64_t)w0, a1 = (uint64_t)(w0 >> 64), b0 = (uint64_t)w1, b1 = (uint64_t)(w1 >> 64);
+        *(uint4*)(cg + e0) = make_uint4((uint32_t)a0, (uint32_t)(a0 >> 32), (uint32_t)a1, (uint32_t)(a1 >> 32));
+        *(uint4*)(cg + e0 + G) = make_uint4((uint32_t)b0, (uint32_t)(b0 >> 32), (uint32_t)b1, (uint32_t)(b1 >> 32));
+      }
+    } else {
+      store_codes(a, qe, w0);
+      store_codes(a, qe + 1, w1);
+    }
+  };
   auto flush_values = [&](int a, int64_t q) {
     if (!rv[a]) return;
     const int64_t e0 = q * G, lo = rb[a], hi = rb[a] + BX;
@@ -456,6 +477,8 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   uint4 xpre[AZ][COMP ? XPC : 1];  // compress: prefetched input chunk
   CW c0[AZ], c1[AZ], c2[AZ], cpre[AZ];  // decompress: code chunks of this window and two ahead
   CW cacc[AZ], cprv[AZ];           // compress: codes of this and the previous group's window
+  CW chold[AZ];                    // compress: an even chunk waiting for its partner
+  int64_t qhold[AZ];               // its index, -1 for none
   // Decompress: the unpredictable values a group consumes, in a register
   // window loaded during the group before (values uidx .. uidx + zc - 1 of
   // the row's raster-ordered stream), so that no step waits for memory
@@ -470,7 +493,8 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   int zc[AZ];        // values this group consumes
 #pragma unroll
   for (int a = 0; a < AZ; a++) {
-    c0[a] = c1[a] = c2[a] = cpre[a] = cacc[a] = cprv[a] = (CW)0;
+    c0[a] = c1[a] = c2[a] = cpre[a] = cacc[a] = cprv[a] = chold[a] = (CW)0;
+    qhold[a] = -1;
     uidx[a] = 0;
     zc[a] = 0;
     unext[a] = T(0);
@@ -796,7 +820,15 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
       const int o = (int)(lo & (G - 1));
       if constexpr (COMP) {
         const CW word = o ? ((cprv[a] >> (SB * (G - o))) | (cacc[a] << (SB * o))) : cacc[a];
-        store_codes(a, q, word);
+        if ((q & 1) == 0) {
+          chold[a] = word;
+          qhold[a] = q;
+        } else if (qhold[a] == q - 1) {
+          store_pair(a, q - 1, chold[a], word);
+          qhold[a] = -1;
+        } else {
+          store_codes(a, q, word);
+        }
         cprv[a] = cacc[a];
         cacc[a] = (CW)0;
         if (more) coop_put(a, g + 1, xpre[a]);
@@ -827,11 +859,20 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
     const int64_t lo = wlo[a] + (int64_t)(ngroups - 1) * G;
     const int64_t q = (lo >> 3) + 1;
     const int o = (int)(lo & (G - 1));
-    if (o == 0) continue;
-    if constexpr (COMP)
-      store_codes(a, q, cprv[a] >> (SB * (G - o)));
-    else
-      flush_values(a, q);
+    if constexpr (COMP) {
+      if (o != 0) {
+        const CW word = cprv[a] >> (SB * (G - o));
+        if (qhold[a] == q - 1 && (q & 1)) {
+          store_pair(a, q - 1, chold[a], word);
+          qhold[a] = -1;
+        } else {
+          store_codes(a, q, word);
+        }
+      }
+      if (qhold[a] >= 0) store_codes(a, qhold[a], chold[a]);
+    } else {
+      if (o != 0) flush_values(a, q);
+    }
   }
 }
 
