@@ -208,6 +208,8 @@ int resolve(const sz_params* p, Layout& L, const Sched* sched_override = nullptr
   if (L.wave) {
     const int az = sched.az, nw = sched.nw, tz = nw * az;
     g.tz_per_blk = (int32_t)ceil_div(L.blk3[0], tz);
+    // the z-exchange is read in whole 16-byte pieces of records
+    if (g.tz_per_blk > 1 && tz % (16 / L.ts) != 0) return SZ_EINVAL;
     g.ty_per_blk = (int32_t)ceil_div(L.blk3[1], kWLanes);
     const uint64_t nt = (uint64_t)g.nblk[0] * g.nblk[1] * g.nblk[2] * g.tz_per_blk * g.ty_per_blk;
     if (nt >= (1ull << 31)) return SZ_EINVAL;

@@ -45,7 +45,7 @@ struct WArgs {
   void* codes;       // compress: output codes; decompress: input codes
   void* xo;          // compress (debug): every recorded value; decompress: output field
   void* xy;          // exchange towards the next tile along y: [tile][wave][step][AZ]
-  void* xz;          // exchange towards the next tile along z: [tile][out | y-moved][lane][step + 1]
+  void* xz;          // exchange towards the next tile along z: [tile][out | y-moved][group][piece][lane]
   const void* uvals; // decompress: unpredictable values in raster order
   const uint64_t* useg;
   uint64_t n_unpred;
@@ -253,8 +253,13 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   auto y_off = [&](int t, int step) -> int {  // record of (tile t, wave w, step)
     return (int)((((int64_t)t * NW + w) * (int64_t)nsp + step) * 16);
   };
-  auto z_off = [&](int t, int kind, int idx) -> int {  // element (tile t, kind, lane, idx)
-    return (int)(((((int64_t)t * 2 + kind) * 64 + ly) * (int64_t)nsp + idx) * (int64_t)sizeof(T));
+  // z records: [tile][out | y-moved][group][piece][lane] of 16-byte pieces,
+  // so one wave's access to a piece of a group is 1 KiB of whole cache lines
+  auto z_piece = [&](int t, int kind, int grp, int j) -> int {  // piece j of group grp of lane ly
+    return (int)((((((int64_t)t * 2 + kind) * (int64_t)(nsp / G) + grp) * XPC + j) * 64 + ly) * 16);
+  };
+  auto z_off = [&](int t, int kind, int idx) -> int {  // element idx (tile t, kind, lane ly)
+    return z_piece(t, kind, idx / G, (idx % G) / EPP) + (idx % EPP) * (int)sizeof(T);
   };
   constexpr int kOut = 0x7FFFFF00;  // offset past every descriptor: loads read zero
 
@@ -313,11 +318,13 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
                                                  kCoherent);
   };
   // z (wave 0): the moved and unmoved values of the row below at steps gr*G - 1 + i
+  // (TZ is a multiple of EPP whenever tiles exchange along z, so the records
+  // of indices gr * G + TZ on form whole pieces)
   auto load_zh = [&](int gr, uint4 (&zo)[XPC], uint4 (&zy)[XPC]) {
 #pragma unroll
     for (int j = 0; j < XPC; j++) {
-      const int o0 = z_off(pred_z0, 0, gr * G + TZ) + 16 * j;
-      const int o1 = z_off(pred_z0, 1, gr * G + TZ) + 16 * j;
+      const int o0 = z_off(pred_z0, 0, gr * G + TZ + EPP * j);
+      const int o1 = z_off(pred_z0, 1, gr * G + TZ + EPP * j);
       zo[j] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rz_in, o0, 0, kCoherent));
       zy[j] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rz_in, o1, 0, kCoherent));
     }
@@ -783,9 +790,9 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
 #pragma unroll
       for (int j = 0; j < XPC; j++) {
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, pack_piece<T>(ezo, j)), rz,
-                                               z_off(tile, 0, g * G) + 16 * j, 0, kCoherent);
+                                               z_piece(tile, 0, g, j), 0, kCoherent);
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, pack_piece<T>(ezy, j)), rz,
-                                               z_off(tile, 1, g * G) + 16 * j, 0, kCoherent);
+                                               z_piece(tile, 1, g, j), 0, kCoherent);
       }
     }
     if (succ_z && w == NW - 1 && !more) {
