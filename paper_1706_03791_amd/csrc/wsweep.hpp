@@ -237,7 +237,7 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
 
   const uint32_t m = P->m;
   const int32_t half = 1 << (m - 1);
-  const T halfT = T(half), halfm1T = T(half - 1);
+  const T halfm1T = T(half - 1);
   const T ebT = bits_to<T>((U)P->ebT_bits);
   const T twoeb = bits_to<T>((U)P->twoeb_bits);
   const T inv2eb = bits_to<T>((U)P->inv2eb_bits);
@@ -708,15 +708,31 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
         for (int a = 0; a < AZ; a++) rk[a] = rint(t[a]);
 #pragma unroll
         for (int a = 0; a < AZ; a++) xqq[a] = p[a] + rk[a] * twoeb;
+        // |rk| <= half - 1 implies |t| < half (rint moves t by at most 1/2),
+        // so the format's test |t| < half needs no instruction of its own
 #pragma unroll
-        for (int a = 0; a < AZ; a++)
-          ok[a] = (fabs(t[a]) < halfT) & (fabs(rk[a]) <= halfm1T) & (fabs(xin[a][i] - xqq[a]) < ebT);
+        for (int a = 0; a < AZ; a++) ok[a] = (fabs(rk[a]) <= halfm1T) & (fabs(xin[a][i] - xqq[a]) < ebT);
+        U xb[AZ];
+        bool bad = false;
 #pragma unroll
         for (int a = 0; a < AZ; a++) {
-          // select by masks (keeps the step one basic block)
-          const U xt = trunc_masked<T>(to_bits<T>(xin[a][i]), e_eb);
-          const U okm = (U)0 - (U)ok[a], am = (U)0 - (U)act[a];
-          xq[a] = bits_to<T>(((to_bits<T>(xqq[a]) & okm) | (xt & ~okm)) & am);
+          xb[a] = to_bits<T>(xqq[a]);
+          bad |= !ok[a];
+        }
+        // Unpredictable points are rare: the reduced representation is
+        // computed only in steps where a lane of the wave has one (a
+        // wave-uniform branch).
+        if (__builtin_amdgcn_ballot_w64(bad) != 0) {
+#pragma unroll
+          for (int a = 0; a < AZ; a++) {
+            const U okm = (U)0 - (U)ok[a];
+            xb[a] = (xb[a] & okm) | (trunc_masked<T>(to_bits<T>(xin[a][i]), e_eb) & ~okm);
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < AZ; a++) {
+          const U am = (U)0 - (U)act[a];
+          xq[a] = bits_to<T>(xb[a] & am);
           const uint32_t code = ok[a] ? (uint32_t)((int)rk[a] + half) : 0u;
           cacc[a] |= (CW)code << (SB * i);
           if constexpr (DBG)
