@@ -220,7 +220,7 @@ int resolve(const sz_params* p, Layout& L, const Sched* sched_override = nullptr
     const uint64_t nsteps = (uint64_t)L.blk3[2] + (tz - 1) + (kWLanes - 1);
     L.nsp = (uint32_t)(ceil_div(nsteps + kWLanes + tz + 4 * kWG, 16) * 16);
     L.ne = 0;
-    L.xy_bytes = (uint64_t)g.ntiles * nw * L.nsp * 16;
+    L.xy_bytes = (uint64_t)g.ntiles * nw * L.nsp * 8;  // 8-byte records
     // z-exchange records only when a block holds several tiles along z
     const uint64_t xz_bytes = g.tz_per_blk > 1 ? (uint64_t)g.ntiles * 2 * 64 * L.nsp * L.ts : 0;
     L.xchg_bytes = L.xy_bytes + xz_bytes;

@@ -34,6 +34,8 @@ constexpr int kWG = 8;       // steps per group (also the chunk length in elemen
 constexpr int kWRing = 16;   // ring slots per row: two chunks
 constexpr int kWLanes = 64;  // y-rows per tile
 constexpr int kHaloStep = 6; // steps of a group before it waits for the next group's halo
+constexpr int kPollStep = 2; // step of a group after which each wave reads its predecessors' progress
+static_assert(kPollStep < kHaloStep, "progress is read before it is checked");
 
 struct WArgs {
   int64_t dims[3];   // Z, Y, X
@@ -119,15 +121,18 @@ __device__ __forceinline__ CWord<CT> code_window(CWord<CT> c0, CWord<CT> c1, int
   return (c0 >> (SB * o)) | (c1 << (BITS - SB * o));
 }
 
-// The AZ values of one step as a 16-byte exchange record.
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// The AZ values of one step as an 8-byte y-exchange record (a single f32
+// value takes the low word).
 template <typename T, int AZ>
-__device__ __forceinline__ u32x4 pack_rec(const T (&v)[AZ]) {
+__device__ __forceinline__ u32x2 pack_rec(const T (&v)[AZ]) {
+  static_assert(AZ * sizeof(T) <= 8, "one 8-byte exchange record per step");
   if constexpr (sizeof(T) == 4) {
-    return u32x4{__builtin_bit_cast(uint32_t, v[0]), __builtin_bit_cast(uint32_t, v[1 % AZ]),
-                 __builtin_bit_cast(uint32_t, v[2 % AZ]), __builtin_bit_cast(uint32_t, v[3 % AZ])};
+    return u32x2{__builtin_bit_cast(uint32_t, v[0]), AZ > 1 ? __builtin_bit_cast(uint32_t, v[AZ - 1]) : 0u};
   } else {
-    const uint64_t a0 = __builtin_bit_cast(uint64_t, v[0]), a1 = __builtin_bit_cast(uint64_t, v[1 % AZ]);
-    return u32x4{(uint32_t)a0, (uint32_t)(a0 >> 32), (uint32_t)a1, (uint32_t)(a1 >> 32)};
+    const uint64_t a0 = __builtin_bit_cast(uint64_t, v[0]);
+    return u32x2{(uint32_t)a0, (uint32_t)(a0 >> 32)};
   }
 }
 
@@ -151,13 +156,13 @@ __device__ __forceinline__ typename FTr<T>::U trunc_masked(typename FTr<T>::U u,
   return u & m;
 }
 
-// Element a of a 16-byte exchange record.
+// Element a of an 8-byte exchange record.
 template <typename T>
-__device__ __forceinline__ T rec_elem(u32x4 v, int a) {
+__device__ __forceinline__ T rec_elem(u32x2 v, int a) {
   if constexpr (sizeof(T) == 4)
     return __builtin_bit_cast(T, (uint32_t)v[a]);
   else
-    return __builtin_bit_cast(T, ((uint64_t)v[2 * a + 1] << 32) | v[2 * a]);
+    return __builtin_bit_cast(T, ((uint64_t)v[1] << 32) | v[0]);
 }
 
 // LDS of one workgroup of the wave-tiled sweep (dynamic allocation).
@@ -166,8 +171,7 @@ struct WSweepLds {
   static constexpr size_t OFF_RING = 0;
   static constexpr size_t OFF_XW = OFF_RING + sizeof(T) * NW * AZ * kWRing * 64;
   static constexpr size_t OFF_YIN = OFF_XW + sizeof(T) * 2 * NW * 2 * 64;
-  static constexpr size_t OFF_YOUT = OFF_YIN + 16 * NW * kWG;
-  static constexpr size_t BYTES = OFF_YOUT + 16 * NW * kWG;
+  static constexpr size_t BYTES = OFF_YIN + 8 * NW * kWG;
 };
 
 // One tile of the wave-tiled sweep, run by a workgroup of NW waves; `lds` is
@@ -181,15 +185,14 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   constexpr int SB = 8 * sizeof(CT);
   constexpr int XPC = (G * (int)sizeof(T)) / 16;  // 16-byte pieces per chunk of values
   constexpr int EPP = 16 / (int)sizeof(T);        // values per piece
-  static_assert(AZ * sizeof(T) <= 16, "one 16-byte exchange record per step");
+  static_assert(AZ * sizeof(T) <= 8, "one 8-byte y-exchange record per step");
 
   using LD = WSweepLds<T, NW, AZ>;
   // per-row input (compress) or output (decompress) rings
   auto& s_ring = *reinterpret_cast<T (*)[NW][AZ][kWRing][64]>(lds + LD::OFF_RING);
   // last sub-row of each wave: [step parity][wave][out | moved][lane]
   auto& s_xw = *reinterpret_cast<T (*)[2][NW][2][64]>(lds + LD::OFF_XW);
-  auto& s_yin = *reinterpret_cast<u32x4 (*)[NW][kWG]>(lds + LD::OFF_YIN);   // y-halo records, one per step
-  auto& s_yout = *reinterpret_cast<u32x4 (*)[NW][kWG]>(lds + LD::OFF_YOUT);  // lane 63's values, one per step
+  auto& s_yin = *reinterpret_cast<u32x2 (*)[NW][kWG]>(lds + LD::OFF_YIN);   // y-halo records, one per step
 
   DevPlan* P = A.plan;
   if (P->status != 0) return;
@@ -246,12 +249,12 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   // ---- exchange descriptors (one each for all tiles; offsets < 2 GiB)
   const uint64_t nsp = A.nsp;
   const __amdgpu_buffer_rsrc_t ry =
-      make_rsrc(A.xy, (uint64_t)A.ntiles * NW * nsp * 16);
+      make_rsrc(A.xy, (uint64_t)A.ntiles * NW * nsp * 8);
   // (no z-exchange when a block holds one tile along z: its loads read zero)
   const __amdgpu_buffer_rsrc_t rz =
       make_rsrc(A.xz, A.tz_per_blk > 1 ? (uint64_t)A.ntiles * 2 * 64 * nsp * sizeof(T) : 0);
-  auto y_off = [&](int t, int step) -> int {  // record of (tile t, wave w, step)
-    return (int)((((int64_t)t * NW + w) * (int64_t)nsp + step) * 16);
+  auto y_off = [&](int t, int step) -> int {  // 8-byte record of (tile t, wave w, step)
+    return (int)((((int64_t)t * NW + w) * (int64_t)nsp + step) * 8);
   };
   // z records: [tile][out | y-moved][group][piece][lane] of 16-byte pieces,
   // so one wave's access to a piece of a group is 1 KiB of whole cache lines
@@ -276,15 +279,16 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
                                                        sizeof(CT));
 
   // ---- waits on predecessor tiles: the records a group needs
+  // y records of steps [gr*G + 64, +G) are written by the predecessor's
+  // group (gr*G + 64 + G - 1) / G; z records of indices [gr*G + TZ, +G)
+  // (index k holds step k - 1) by its group (gr*G + TZ + G - 1) / G.
+  auto need_of = [&](int gr, int lead) -> uint32_t {  // progress a predecessor must reach for group gr
+    return (uint32_t)(((gr * G + lead + G - 1) / G + 1) * G);
+  };
   auto wait_preds = [&](int gr) {
     if (tid == 0) {
-      // y records of steps [gr*G + 64, +G) are written by the predecessor's
-      // group (gr*G + 64 + G - 1) / G; z records of indices [gr*G + TZ, +G)
-      // (index k holds step k - 1) by its group (gr*G + TZ + G - 1) / G.
-      const uint32_t need_y = (uint32_t)(((gr * G + kWLanes + G - 1) / G + 1) * G);
-      const uint32_t need_z = (uint32_t)(((gr * G + TZ + G - 1) / G + 1) * G);
       const int preds[2] = {pred_z, pred_y};
-      const uint32_t needs[2] = {need_z, need_y};
+      const uint32_t needs[2] = {need_of(gr, TZ), need_of(gr, kWLanes)};
       for (int q = 0; q < 2; q++) {
         if (preds[q] < 0) continue;
         uint32_t spins = 0;
@@ -300,6 +304,28 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
     }
     __syncthreads();
   };
+  // In the loop every wave reads its predecessors' progress itself: the
+  // reads go out after step kPollStep - 1 and are checked after step
+  // kHaloStep - 1, so a predecessor that is already far enough costs no
+  // round trip and no workgroup barrier.  Otherwise the wave polls.
+  const uint32_t* prog_z = &A.progress[pred_z >= 0 ? pred_z : tile];
+  const uint32_t* prog_y = &A.progress[pred_y >= 0 ? pred_y : tile];
+  auto ready_for = [&](int gr, uint32_t pz, uint32_t py) -> bool {
+    return (pred_z < 0 || pz >= need_of(gr, TZ)) && (pred_y < 0 || py >= need_of(gr, kWLanes));
+  };
+  auto wave_wait = [&](int gr, uint32_t pz, uint32_t py) {
+    uint32_t spins = 0;
+    while (!ready_for(gr, pz, py)) {
+      if (__hip_atomic_load(&P->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+      if (++spins > kSpinLimit) {
+        if (ly == 0) atomicCAS(&P->status, 0, kStatusStalled);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      pz = __builtin_amdgcn_readfirstlane(__hip_atomic_load(prog_z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      py = __builtin_amdgcn_readfirstlane(__hip_atomic_load(prog_y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
+  };
 
   // ---- halo records of group gr
   // Loads are issued one group ahead and must stay straight-line code: a
@@ -313,9 +339,9 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   const __amdgpu_buffer_rsrc_t rz_in = (pred_z >= 0 && wave0) ? rz : make_rsrc(A.xz, 0);
   const int pred_y0 = pred_y >= 0 ? pred_y : 0, pred_z0 = pred_z >= 0 ? pred_z : 0;
   // y: lanes 0..G-1 hold the AZ values lane 0 needs at step gr*G + lane
-  auto load_yh = [&](int gr) -> u32x4 {
-    return __builtin_amdgcn_raw_buffer_load_b128(ry_in, y_off(pred_y0, gr * G + kWLanes + (ly & (G - 1))), 0,
-                                                 kCoherent);
+  auto load_yh = [&](int gr) -> u32x2 {
+    return __builtin_amdgcn_raw_buffer_load_b64(ry_in, y_off(pred_y0, gr * G + kWLanes + (ly & (G - 1))), 0,
+                                                kCoherent);
   };
   // z (wave 0): the moved and unmoved values of the row below at steps gr*G - 1 + i
   // (TZ is a multiple of EPP whenever tiles exchange along z, so the records
@@ -472,7 +498,7 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   for (int a = 0; a < AZ; a++) O1[a] = O2[a] = Y1[a] = Y2[a] = Y3[a] = T(0);
   T VO1 = T(0), VO2 = T(0), VY1 = T(0), VY2 = T(0), VY3 = T(0);  // row below sub-row 0
 
-  u32x4 yh_cur = {0, 0, 0, 0}, yh_nxt = {0, 0, 0, 0};
+  u32x2 yh_cur = {0, 0}, yh_nxt = {0, 0};
   uint4 zo_cur[XPC], zy_cur[XPC], zo_nxt[XPC], zy_nxt[XPC];
 #pragma unroll
   for (int j = 0; j < XPC; j++) zo_cur[j] = zy_cur[j] = zo_nxt[j] = zy_nxt[j] = make_uint4(0, 0, 0, 0);
@@ -564,7 +590,7 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
     // produced x = 0 at step -1, and the corner row (z-1, y-1; skew -2) at
     // step -2.  Their values enter the histories before step 0.
     if (pred_y >= 0) {
-      const u32x4 r = __builtin_amdgcn_raw_buffer_load_b128(ry, y_off(pred_y, kWLanes - 1), 0, kCoherent);
+      const u32x2 r = __builtin_amdgcn_raw_buffer_load_b64(ry, y_off(pred_y, kWLanes - 1), 0, kCoherent);
       const T v = rec_elem<T>(r, 0);
       Y1[0] = ly == 0 ? v : T(0);
     }
@@ -609,6 +635,7 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   }
   __syncthreads();
 
+  uint32_t pz_v = 0, py_v = 0;  // predecessors' progress, read during the group
   for (int g = 0; g < ngroups; g++) {
     const bool more = g + 1 < ngroups;
     if (ly < G) s_yin[w][ly] = yh_cur;
@@ -665,7 +692,7 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
       const T lo_y = NW > 1 ? s_xw[(sig - 1) & 1][wprev][1][ly] : T(0);
       const T vn_o = w > 0 ? lo_o : piece_elem<T>(zo_cur, i);
       const T vn_y = w > 0 ? lo_y : piece_elem<T>(zy_cur, i);
-      const u32x4 yrec = s_yin[w][i];  // the y-halo values lane 0 takes at this step
+      const u32x2 yrec = s_yin[w][i];  // the y-halo values lane 0 takes at this step
       VO2 = VO1;
       VO1 = vn_o;
       VY3 = VY2;
@@ -787,20 +814,28 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
       // the step's exchange between waves; a single wave needs no barrier
       // (its own LDS accesses complete in order)
       if constexpr (NW > 1) __syncthreads();
+      if (i == kPollStep - 1) {
+        pz_v = __hip_atomic_load(prog_z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        py_v = __hip_atomic_load(prog_y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       if (i == kHaloStep - 1) {
-        if (more) wait_preds(g + 1);
+        const uint32_t pz = __builtin_amdgcn_readfirstlane(pz_v), py = __builtin_amdgcn_readfirstlane(py_v);
+        if (more && !ready_for(g + 1, pz, py)) wave_wait(g + 1, pz, py);
         yh_nxt = load_yh(g + 1);
         if (wave0) load_zh(g + 1, zo_nxt, zy_nxt);
       }
     }
 
     // ---- group end: publish boundary records, then the progress flag
-    if (succ_y) {
-      if (ly == kWLanes - 1) {
+    if (succ_y && ly == kWLanes - 1) {
+      // lane 63 stores the group's G records itself, two per 16-byte store
+      // (no values move between lanes)
 #pragma unroll
-        for (int i = 0; i < G; i++) s_yout[w][i] = pack_rec<T, AZ>(yk[i]);
+      for (int i = 0; i < G; i += 2) {
+        const u32x2 r0 = pack_rec<T, AZ>(yk[i]), r1 = pack_rec<T, AZ>(yk[i + 1]);
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{r0[0], r0[1], r1[0], r1[1]}, ry, y_off(tile, g * G + i), 0,
+                                               kCoherent);
       }
-      if (ly < G) __builtin_amdgcn_raw_buffer_store_b128(s_yout[w][ly], ry, y_off(tile, g * G + ly), 0, kCoherent);
     }
     if (succ_z && w == NW - 1) {
 #pragma unroll
@@ -819,7 +854,6 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, cy), rz, z_off(tile, 1, (g + 1) * G), 0,
                                               kCoherent);
       } else {
-        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
         const uint64_t uo = __builtin_bit_cast(uint64_t, co), uy = __builtin_bit_cast(uint64_t, cy);
         __builtin_amdgcn_raw_buffer_store_b64(u32x2{(uint32_t)uo, (uint32_t)(uo >> 32)}, rz,
                                               z_off(tile, 0, (g + 1) * G), 0, kCoherent);
