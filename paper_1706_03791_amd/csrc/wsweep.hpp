@@ -156,6 +156,16 @@ __device__ __forceinline__ typename FTr<T>::U trunc_masked(typename FTr<T>::U u,
   return u & m;
 }
 
+// A 16-byte store marked non-temporal: codes and reconstructed values are
+// written once and not read again by the sweep, so their partly written
+// lines should not take L2 capacity from the input lines still being read.
+__device__ __forceinline__ void st_nt(void* p, uint4 v) {
+  __builtin_nontemporal_store(u32x4{v.x, v.y, v.z, v.w}, (u32x4*)p);
+}
+__device__ __forceinline__ void st_nt(void* p, uint64_t v) {
+  __builtin_nontemporal_store(v, (uint64_t*)p);
+}
+
 // Element a of an 8-byte exchange record.
 template <typename T>
 __device__ __forceinline__ T rec_elem(u32x2 v, int a) {
@@ -411,7 +421,7 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
 #pragma unroll
       for (int e = 0; e < EPP; e++) v[e] = s_ring[w][a][(int)((e0 + e) & (kWRing - 1))][r];
       if (e0 >= lo && e0 + EPP <= hi) {
-        *(uint4*)(xg + e0) = pack_piece<T>(v, 0);
+        st_nt(xg + e0, pack_piece<T>(v, 0));
       } else {
 #pragma unroll
         for (int e = 0; e < EPP; e++)
@@ -438,10 +448,10 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
     CT* cg = (CT*)A.codes;
     if (e0 >= lo && e0 + G <= hi) {
       if constexpr (sizeof(CT) == 1) {
-        *(uint64_t*)(cg + e0) = (uint64_t)word;
+        st_nt(cg + e0, (uint64_t)word);
       } else {
         const uint64_t w0 = (uint64_t)word, w1 = (uint64_t)(word >> 64);
-        *(uint4*)(cg + e0) = make_uint4((uint32_t)w0, (uint32_t)(w0 >> 32), (uint32_t)w1, (uint32_t)(w1 >> 32));
+        st_nt(cg + e0, make_uint4((uint32_t)w0, (uint32_t)(w0 >> 32), (uint32_t)w1, (uint32_t)(w1 >> 32)));
       }
     } else {
 #pragma unroll
@@ -461,11 +471,11 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
       CT* cg = (CT*)A.codes;
       if constexpr (sizeof(CT) == 1) {
         const uint64_t a0 = (uint64_t)w0, a1 = (uint64_t)w1;
-        *(uint4*)(cg + e0) = make_uint4((uint32_t)a0, (uint32_t)(a0 >> 32), (uint32_t)a1, (uint32_t)(a1 >> 32));
+        st_nt(cg + e0, make_uint4((uint32_t)a0, (uint32_t)(a0 >> 32), (uint32_t)a1, (uint32_t)(a1 >> 32)));
       } else {
         const uint64_t a0 = (uint64_t)w0, a1 = (uint64_t)(w0 >> 64), b0 = (uint64_t)w1, b1 = (uint64_t)(w1 >> 64);
-        *(uint4*)(cg + e0) = make_uint4((uint32_t)a0, (uint32_t)(a0 >> 32), (uint32_t)a1, (uint32_t)(a1 >> 32));
-        *(uint4*)(cg + e0 + G) = make_uint4((uint32_t)b0, (uint32_t)(b0 >> 32), (uint32_t)b1, (uint32_t)(b1 >> 32));
+        st_nt(cg + e0, make_uint4((uint32_t)a0, (uint32_t)(a0 >> 32), (uint32_t)a1, (uint32_t)(a1 >> 32)));
+        st_nt(cg + e0 + G, make_uint4((uint32_t)b0, (uint32_t)(b0 >> 32), (uint32_t)b1, (uint32_t)(b1 >> 32)));
       }
     } else {
       store_codes(a, qe, w0);
@@ -482,7 +492,7 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
     for (int j = 0; j < G; j++) v[j] = s_ring[w][a][(int)((e0 + j) & (kWRing - 1))][ly];
     if (e0 >= lo && e0 + G <= hi) {
 #pragma unroll
-      for (int j = 0; j < XPC; j++) *(uint4*)(xg + e0 + EPP * j) = pack_piece<T>(v, j);
+      for (int j = 0; j < XPC; j++) st_nt(xg + e0 + EPP * j, pack_piece<T>(v, j));
     } else {
 #pragma unroll
       for (int j = 0; j < G; j++) {
