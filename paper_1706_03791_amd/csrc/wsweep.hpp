@@ -575,13 +575,13 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
       return z;
     }
   };
-  // The z values from stream index u on into dst.  Lanes with z > 0 load the
-  // whole window (entries past z, or past the stream, go unused); lanes with
-  // z == 0 load from an offset past the descriptor.
-  auto load_uw = [&](int64_t u, int z, T (&dst)[UW]) {
-    const int base = z > 0 ? (int)((u - ubase) * (int64_t)sizeof(T)) : kOut;
+  // The z values from stream index u on into dst, entries [j0, j1) of the
+  // window.  Lanes with z > j0 load them all (entries past z, or past the
+  // stream, go unused); other lanes load from an offset past the descriptor.
+  auto load_uw = [&](int64_t u, int z, T (&dst)[UW], int j0, int j1) {
+    const int base = z > j0 ? (int)((u - ubase) * (int64_t)sizeof(T)) : kOut;
 #pragma unroll
-    for (int j = 0; j < UW; j++) {
+    for (int j = j0; j < j1; j++) {
       if constexpr (sizeof(T) == 4) {
         dst[j] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(ru, base + 4 * j, 0, 0));
       } else {
@@ -639,7 +639,7 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
     for (int a = 0; a < AZ; a++) {
       const int o = (int)(wlo[a] & (G - 1));
       zc[a] = zeros_in(code_window<CT>(c0[a], c1[a], o), 0, a);
-      load_uw(uidx[a], zc[a], uw[a]);
+      load_uw(uidx[a], zc[a], uw[a], 0, UW);
     }
     wait_vm();
   }
@@ -671,8 +671,20 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
         zn[a] = 0;
         if constexpr (UWIN) {
           zn[a] = zeros_in(code_window<CT>(c1[a], c2[a], (int)(wlo[a] & (G - 1))), g + 1, a);
-          load_uw(uidx[a] + zc[a], zn[a], uw_nxt[a]);
+          load_uw(uidx[a] + zc[a], zn[a], uw_nxt[a], 0, 2);
         }
+      }
+    }
+    if constexpr (UWIN) {
+      // Most windows hold at most two unpredictable values: two loads per
+      // sub-row go out above.  Only when a lane of the wave needs more does
+      // the wave load the rest of its window.
+      bool several = false;
+#pragma unroll
+      for (int a = 0; a < AZ; a++) several |= zn[a] > 2;
+      if (__builtin_amdgcn_ballot_w64(several) != 0) {
+#pragma unroll
+        for (int a = 0; a < AZ; a++) load_uw(uidx[a] + zc[a], zn[a], uw_nxt[a], 2, UW);
       }
     }
     // per-group window of each sub-row and its inputs
