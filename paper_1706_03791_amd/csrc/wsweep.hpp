@@ -250,7 +250,7 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
 
   const uint32_t m = P->m;
   const int32_t half = 1 << (m - 1);
-  const T halfm1T = T(half - 1);
+  const T halfT = T(half), halfm1T = T(half - 1);
   const T ebT = bits_to<T>((U)P->ebT_bits);
   const T twoeb = bits_to<T>((U)P->twoeb_bits);
   const T inv2eb = bits_to<T>((U)P->inv2eb_bits);
@@ -396,12 +396,30 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
     const int64_t wl = rbase[a] + (int64_t)r * Xd - (int64_t)(AZ * w + a + r);
     return ((wl + (int64_t)gr * G) >> 3) + 1;
   };
+  // Each group moves a row's window by one chunk, so the byte offset of a
+  // lane's piece grows by one chunk per group and its ring slot flips bit 3
+  // (slots are taken mod 16 and a chunk is 8 elements): both are computed
+  // once per tile.
+  int cb0[AZ][XPC];         // input byte offset of the lane's chunk for group 0 (< 0: before the buffer)
+  uint32_t cput0[AZ][XPC];  // s_ring byte offset of the lane's piece for group 0
+  if constexpr (COMP) {
+#pragma unroll
+    for (int a = 0; a < AZ; a++)
+#pragma unroll
+      for (int h = 0; h < XPC; h++) {
+        const int r = ly / XPC + RPI * h, pc = ly % XPC;
+        const int64_t q = coop_chunk(a, h, 0);
+        cb0[a][h] = (int)((q - cbase) * (int64_t)(G * sizeof(T)));
+        const uint32_t slot = (uint32_t)((q * G + pc * EPP) & (kWRing - 1));
+        cput0[a][h] = ((((uint32_t)w * AZ + a) * kWRing + slot) * 64 + (uint32_t)r) * (uint32_t)sizeof(T);
+      }
+  }
   auto coop_load = [&](int a, int gr, uint4 (&dst)[XPC]) {
 #pragma unroll
     for (int h = 0; h < XPC; h++) {
-      const int off = chunk_off(coop_chunk(a, h, gr));
+      const int bo = cb0[a][h] + gr * (int)(G * sizeof(T));
       dst[h] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
-                                             rin, off == kOut ? kOut : off + 16 * (ly % XPC), 0, 0));
+                                             rin, bo < 0 ? kOut : bo + 16 * (ly % XPC), 0, 0));
     }
   };
   // Decompression flushes the same way: lane ly stores piece ly % XPC of the
@@ -430,13 +448,12 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
     }
   };
   auto coop_put = [&](int a, int gr, const uint4 (&src)[XPC]) {
+    const uint32_t flip = (uint32_t)(gr & 1) * (8u * 64u * (uint32_t)sizeof(T));
 #pragma unroll
     for (int h = 0; h < XPC; h++) {
-      const int r = ly / XPC + RPI * h, pc = ly % XPC;
-      const int64_t q = coop_chunk(a, h, gr);
+      T* p = (T*)((uint8_t*)&s_ring[0][0][0][0] + (cput0[a][h] ^ flip));
 #pragma unroll
-      for (int e = 0; e < EPP; e++)
-        s_ring[w][a][(int)((q * G + pc * EPP + e) & (kWRing - 1))][r] = piece_elem<T>(&src[h], e);
+      for (int e = 0; e < EPP; e++) p[e * 64] = piece_elem<T>(&src[h], e);
     }
   };
 
@@ -522,6 +539,10 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   CW cacc[AZ], cprv[AZ];           // compress: codes of this and the previous group's window
   CW chold[AZ];                    // compress: an even chunk waiting for its partner
   int64_t qhold[AZ];               // its index, -1 for none
+  uint32_t cpk[AZ][2];             // compress, 1-byte codes: the group's codes, four per word
+  // Groups whose odd chunk q completes a pair (q - 1, q) that lies wholly
+  // inside the row: [gpa, gpb] (the chunk of group g is (wlo >> 3) + g).
+  int gpa[AZ], gpb[AZ];
   // Decompress: the unpredictable values a group consumes, in a register
   // window loaded during the group before (values uidx .. uidx + zc - 1 of
   // the row's raster-ordered stream), so that no step waits for memory
@@ -538,6 +559,10 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   for (int a = 0; a < AZ; a++) {
     c0[a] = c1[a] = c2[a] = cpre[a] = cacc[a] = cprv[a] = chold[a] = (CW)0;
     qhold[a] = -1;
+    cpk[a][0] = cpk[a][1] = 0;
+    const int64_t q0 = wlo[a] >> 3;
+    gpa[a] = (int)(((rb[a] + G - 1) >> 3) + 1 - q0);
+    gpb[a] = rv[a] ? (int)(((rb[a] + BX) >> 3) - 1 - q0) : -1;
     uidx[a] = 0;
     zc[a] = 0;
     unext[a] = T(0);
@@ -782,8 +807,15 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
         for (int a = 0; a < AZ; a++) {
           const U am = (U)0 - (U)act[a];
           xq[a] = bits_to<T>(xb[a] & am);
-          const uint32_t code = ok[a] ? (uint32_t)((int)rk[a] + half) : 0u;
-          cacc[a] |= (CW)code << (SB * i);
+          if constexpr (sizeof(CT) == 1) {
+            // the code as a float (an exact integer below 256) packed into
+            // byte i % 4 of word i / 4
+            const float cf = ok[a] ? (float)(rk[a] + halfT) : 0.0f;
+            cpk[a][i >> 2] = __builtin_amdgcn_cvt_pk_u8_f32(cf, (uint32_t)(i & 3), cpk[a][i >> 2]);
+          } else {
+            const uint32_t code = ok[a] ? (uint32_t)((int)rk[a] + half) : 0u;
+            cacc[a] |= (CW)code << (SB * i);
+          }
           if constexpr (DBG)
             if (act[a]) ((T*)A.xo)[rb[a] + (sig - sk[a])] = xq[a];
         }
@@ -898,16 +930,32 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
       const int64_t q = lo >> 3;
       const int o = (int)(lo & (G - 1));
       if constexpr (COMP) {
+        if constexpr (sizeof(CT) == 1) cacc[a] = ((CW)cpk[a][1] << 32) | cpk[a][0];
         const CW word = o ? ((cprv[a] >> (SB * (G - o))) | (cacc[a] << (SB * o))) : cacc[a];
-        if ((q & 1) == 0) {
-          chold[a] = word;
-          qhold[a] = q;
-        } else if (qhold[a] == q - 1) {
-          store_pair(a, q - 1, chold[a], word);
-          qhold[a] = -1;
-        } else {
-          store_codes(a, q, word);
+        const bool qodd = (q & 1) != 0;
+        // An even chunk waits for its partner; an odd one completes the pair:
+        // one aligned store when the pair lies inside the row (all groups but
+        // those at the row's ends), else chunk by chunk in a branch that the
+        // wave takes only when one of its lanes needs it.
+        const bool pair_ok = qodd && g >= gpa[a] && g <= gpb[a];
+        if (pair_ok) {
+          CT* cg = (CT*)A.codes + (q - 1) * G;
+          if constexpr (sizeof(CT) == 1) {
+            st_nt(cg, make_uint4((uint32_t)chold[a], (uint32_t)(chold[a] >> 32), (uint32_t)word,
+                                 (uint32_t)(word >> 32)));
+          } else {
+            store_pair(a, q - 1, chold[a], word);
+          }
         }
+        const bool edge = qodd && !pair_ok && rv[a];
+        if (__builtin_amdgcn_ballot_w64(edge) != 0) {
+          if (edge) {
+            if (qhold[a] == q - 1) store_codes(a, q - 1, chold[a]);
+            store_codes(a, q, word);
+          }
+        }
+        if (!qodd) chold[a] = word;
+        qhold[a] = qodd ? -1 : q;
         cprv[a] = cacc[a];
         cacc[a] = (CW)0;
         if (more) coop_put(a, g + 1, xpre[a]);
