@@ -917,62 +917,71 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
     }
     ezo[0] = co;
     ezy[0] = cy;
+    // ---- completed chunk of each row, input refill, register rotation.
+    // None of it depends on the records just stored.  Compression (and any
+    // one-wave tile) does it while they drain, so the wait below rarely
+    // stalls; the reconstruction of a 3D tile does it after the flag, since
+    // its own output stores would otherwise join that wait.
+    constexpr bool kEndFirst = COMP || NW == 1;
+    auto group_end_work = [&]() {
+#pragma unroll
+      for (int a = 0; a < AZ; a++) {
+        const int64_t lo = wlo[a] + (int64_t)g * G;
+        const int64_t q = lo >> 3;
+        const int o = (int)(lo & (G - 1));
+        if constexpr (COMP) {
+          if constexpr (sizeof(CT) == 1) cacc[a] = ((CW)cpk[a][1] << 32) | cpk[a][0];
+          const CW word = o ? ((cprv[a] >> (SB * (G - o))) | (cacc[a] << (SB * o))) : cacc[a];
+          const bool qodd = (q & 1) != 0;
+          // An even chunk waits for its partner; an odd one completes the pair:
+          // one aligned store when the pair lies inside the row (all groups but
+          // those at the row's ends), else chunk by chunk in a branch that the
+          // wave takes only when one of its lanes needs it.
+          const bool pair_ok = qodd && g >= gpa[a] && g <= gpb[a];
+          if (pair_ok) {
+            CT* cg = (CT*)A.codes + (q - 1) * G;
+            if constexpr (sizeof(CT) == 1) {
+              st_nt(cg, make_uint4((uint32_t)chold[a], (uint32_t)(chold[a] >> 32), (uint32_t)word,
+                                   (uint32_t)(word >> 32)));
+            } else {
+              store_pair(a, q - 1, chold[a], word);
+            }
+          }
+          const bool edge = qodd && !pair_ok && rv[a];
+          if (__builtin_amdgcn_ballot_w64(edge) != 0) {
+            if (edge) {
+              if (qhold[a] == q - 1) store_codes(a, q - 1, chold[a]);
+              store_codes(a, q, word);
+            }
+          }
+          if (!qodd) chold[a] = word;
+          qhold[a] = qodd ? -1 : q;
+          cprv[a] = cacc[a];
+          cacc[a] = (CW)0;
+          if (more) coop_put(a, g + 1, xpre[a]);
+        } else {
+          (void)q;
+          coop_flush(a, g);
+          c0[a] = c1[a];
+          c1[a] = c2[a];
+          c2[a] = cpre[a];
+          if constexpr (UWIN) {
+            uidx[a] += zc[a];
+            zc[a] = zn[a];
+#pragma unroll
+            for (int j = 0; j < UW; j++) uw[a][j] = uw_nxt[a][j];
+          }
+        }
+      }
+    };
+    if constexpr (kEndFirst) group_end_work();
     wait_vm();
     __syncthreads();
     if (tid == 0) {
       const uint32_t done = more ? (uint32_t)((g + 1) * G) : kDone;
       __hip_atomic_store(&A.progress[tile], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    // ---- completed chunk of each row, input refill, register rotation
-#pragma unroll
-    for (int a = 0; a < AZ; a++) {
-      const int64_t lo = wlo[a] + (int64_t)g * G;
-      const int64_t q = lo >> 3;
-      const int o = (int)(lo & (G - 1));
-      if constexpr (COMP) {
-        if constexpr (sizeof(CT) == 1) cacc[a] = ((CW)cpk[a][1] << 32) | cpk[a][0];
-        const CW word = o ? ((cprv[a] >> (SB * (G - o))) | (cacc[a] << (SB * o))) : cacc[a];
-        const bool qodd = (q & 1) != 0;
-        // An even chunk waits for its partner; an odd one completes the pair:
-        // one aligned store when the pair lies inside the row (all groups but
-        // those at the row's ends), else chunk by chunk in a branch that the
-        // wave takes only when one of its lanes needs it.
-        const bool pair_ok = qodd && g >= gpa[a] && g <= gpb[a];
-        if (pair_ok) {
-          CT* cg = (CT*)A.codes + (q - 1) * G;
-          if constexpr (sizeof(CT) == 1) {
-            st_nt(cg, make_uint4((uint32_t)chold[a], (uint32_t)(chold[a] >> 32), (uint32_t)word,
-                                 (uint32_t)(word >> 32)));
-          } else {
-            store_pair(a, q - 1, chold[a], word);
-          }
-        }
-        const bool edge = qodd && !pair_ok && rv[a];
-        if (__builtin_amdgcn_ballot_w64(edge) != 0) {
-          if (edge) {
-            if (qhold[a] == q - 1) store_codes(a, q - 1, chold[a]);
-            store_codes(a, q, word);
-          }
-        }
-        if (!qodd) chold[a] = word;
-        qhold[a] = qodd ? -1 : q;
-        cprv[a] = cacc[a];
-        cacc[a] = (CW)0;
-        if (more) coop_put(a, g + 1, xpre[a]);
-      } else {
-        (void)q;
-        coop_flush(a, g);
-        c0[a] = c1[a];
-        c1[a] = c2[a];
-        c2[a] = cpre[a];
-        if constexpr (UWIN) {
-          uidx[a] += zc[a];
-          zc[a] = zn[a];
-#pragma unroll
-          for (int j = 0; j < UW; j++) uw[a][j] = uw_nxt[a][j];
-        }
-      }
-    }
+    if constexpr (!kEndFirst) group_end_work();
     yh_cur = yh_nxt;
 #pragma unroll
     for (int j = 0; j < XPC; j++) {
