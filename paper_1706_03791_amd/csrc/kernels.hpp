@@ -992,6 +992,25 @@ __global__ void __launch_bounds__(1024) scan_apply(const uint32_t* __restrict__ 
   scan_apply_dev(in, n, tsum, out);
 }
 
+// Three scans of n elements each in one launch per phase (blockIdx.y picks
+// the array): the same per-array work as scan_tile_sums, scan_tile_offsets
+// and scan_apply.
+struct Scan3 {
+  const uint32_t* in[3];
+  uint64_t* out[3];
+  uint64_t* tsum[3];
+  uint64_t* total[3];
+};
+__global__ void __launch_bounds__(1024) scan3_tile_sums(Scan3 S, uint64_t n) {
+  scan_tile_sums_dev(S.in[blockIdx.y], n, S.tsum[blockIdx.y]);
+}
+__global__ void __launch_bounds__(1024) scan3_tile_offsets(Scan3 S, uint64_t ntiles) {
+  scan_tile_offsets_dev(S.tsum[blockIdx.y], ntiles, S.total[blockIdx.y]);
+}
+__global__ void __launch_bounds__(1024) scan3_apply(Scan3 S, uint64_t n) {
+  scan_apply_dev(S.in[blockIdx.y], n, S.tsum[blockIdx.y], S.out[blockIdx.y]);
+}
+
 
 // --------------------------------------- container layout (after scans)
 struct LayoutArgs {

@@ -397,6 +397,13 @@ void scan_u32(const uint32_t* in, uint64_t n, uint64_t* out, uint64_t* tsum, uin
   hipLaunchKernelGGL(scan_tile_offsets, dim3(1), dim3(1024), 0, st, tsum, nt, total);
   hipLaunchKernelGGL(scan_apply, dim3((unsigned)nt), dim3(1024), 0, st, in, n, (const uint64_t*)tsum, out);
 }
+// Three scans of n elements each (one launch per phase).
+void scan3_u32(const Scan3& S, uint64_t n, hipStream_t st) {
+  const uint64_t nt = ceil_div(n, 4096);
+  hipLaunchKernelGGL(scan3_tile_sums, dim3((unsigned)nt, 3), dim3(1024), 0, st, S, n);
+  hipLaunchKernelGGL(scan3_tile_offsets, dim3(1, 3), dim3(1024), 0, st, S, nt);
+  hipLaunchKernelGGL(scan3_apply, dim3((unsigned)nt, 3), dim3(1024), 0, st, S, n);
+}
 
 template <typename T>
 int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const void* d_in, void* d_out, size_t cap,
@@ -502,9 +509,12 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
     hipLaunchKernelGGL((chunk_stats_kernel<T, uint16_t>), dim3(nch), dim3(256), cs_lds, st, (const uint16_t*)W.codes,
                        (const T*)d_in, (const uint8_t*)W.len, (uint64_t)L.n, L.chunk, W.cbits, W.cu, W.ctb,
                        (const DevPlan*)P);
-  scan_u32(W.cbits, L.n_chunks, W.boff, W.tsum_b, W.tot + 0, st);
-  scan_u32(W.cu, L.n_chunks, W.uoff, W.tsum_u, W.tot + 1, st);
-  scan_u32(W.ctb, L.n_chunks, W.toff, W.tsum_t, W.tot + 2, st);
+  {
+    // bit, unpredictable and tail-bit offsets of every chunk
+    const Scan3 S{{W.cbits, W.cu, W.ctb}, {W.boff, W.uoff, W.toff}, {W.tsum_b, W.tsum_u, W.tsum_t},
+                  {W.tot + 0, W.tot + 1, W.tot + 2}};
+    scan3_u32(S, L.n_chunks, st);
+  }
   LayoutArgs la;
   la.plan = P;
   la.tot_bits = W.tot + 0;
