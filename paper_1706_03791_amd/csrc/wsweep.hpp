@@ -820,17 +820,15 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
             if (act[a]) ((T*)A.xo)[rb[a] + (sig - sk[a])] = xq[a];
         }
       } else {
+        bool took[AZ], any_took = false;
 #pragma unroll
         for (int a = 0; a < AZ; a++) {
           const uint32_t code = (uint32_t)(cwin[a] >> (SB * i)) & ((1u << SB) - 1);
           const T v1 = p[a] + T((int32_t)code - half) * twoeb;
           if constexpr (UWIN) {
             xq[a] = act[a] ? (code != 0 ? v1 : uw[a][0]) : T(0);
-            // a consumed value leaves the window (at most G - 1 - i values
-            // remain for the rest of the group)
-            const bool take = act[a] && code == 0;
-#pragma unroll
-            for (int j = 0; j + 1 < UW - i; j++) uw[a][j] = take ? uw[a][j + 1] : uw[a][j];
+            took[a] = act[a] && code == 0;
+            any_took |= took[a];
           } else {
             xq[a] = act[a] ? (code != 0 ? v1 : unext[a]) : T(0);
             if (act[a] && code == 0) {
@@ -839,6 +837,18 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
             }
           }
           s_ring[w][a][(bslot[a] + i) & (kWRing - 1)][ly] = xq[a];
+        }
+        if constexpr (UWIN) {
+          // A consumed value leaves the window (at most G - 1 - i values
+          // remain for the rest of the group).  Unpredictable points are
+          // rare: the shift runs only in steps where a lane of the wave took
+          // one (a wave-uniform branch).
+          if (__builtin_amdgcn_ballot_w64(any_took) != 0) {
+#pragma unroll
+            for (int a = 0; a < AZ; a++)
+#pragma unroll
+              for (int j = 0; j + 1 < UW - i; j++) uw[a][j] = took[a] ? uw[a][j + 1] : uw[a][j];
+          }
         }
       }
       // y-moved values: lane 0 takes the last row of the tile before along y
