@@ -444,155 +444,164 @@ __device__ __forceinline__ void codebook_kernel_dev(CodebookArgs A) {
       P->max_len = 1;
     }
   } else {
-    for (int attempt = 0; attempt < 64; attempt++) {
-      if (in_lds)
+    // The construction takes its arrays as arguments so that, called with
+    // the LDS arrays, every access compiles to LDS instructions (a pointer
+    // that may address LDS or global memory compiles to slower generic ones).
+    auto build = [&](uint64_t* K, uint64_t* W, uint32_t* PAR, uint32_t* ANC_a, uint32_t* ANC_b, uint32_t* DEP_a,
+                     uint32_t* DEP_b, bool lds) {
+      for (int attempt = 0; attempt < 64; attempt++) {
+        if (lds)
+          bitonic_sort<kCbNT>(K, np2);
+        else
+          bitonic_sort_big<kCbNT>(K, np2, s_w, 2 * kCbLdsSyms);
+        if (tid == 0) {
+          // two-queue merge: leaves 0..s-1, internal nodes s..2s-2.  The next
+          // kLA weights of each queue live in registers and a weight is read
+          // kLA - 1 picks before it can be needed, so picks do not wait on
+          // memory.
+          constexpr uint64_t kInf = ~0ull;
+          constexpr uint32_t kLA = 4;
+          uint32_t i = 0, j = s, next = s;
+          uint64_t lw[kLA];  // leaves i .. i + kLA - 1 (kInf past s)
+          uint64_t nw[kLA];  // internal nodes j .. j + kLA - 1 (kInf at or past next)
+#pragma unroll
+          for (uint32_t q = 0; q < kLA; q++) {
+            lw[q] = q < s ? (K[q] >> 16) : kInf;
+            nw[q] = kInf;
+          }
+          for (uint32_t step = 0; step + 1 < s; step++) {
+            uint32_t pk[2];
+            uint64_t wk[2];
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+              if (i < s && (j >= next || lw[0] <= nw[0])) {
+                pk[q] = i;
+                wk[q] = lw[0];
+                i++;
+#pragma unroll
+                for (uint32_t r = 0; r + 1 < kLA; r++) lw[r] = lw[r + 1];
+                lw[kLA - 1] = (i + kLA - 1 < s) ? (K[i + kLA - 1] >> 16) : kInf;
+              } else {
+                pk[q] = j;
+                wk[q] = nw[0];
+                j++;
+#pragma unroll
+                for (uint32_t r = 0; r + 1 < kLA; r++) nw[r] = nw[r + 1];
+                nw[kLA - 1] = (j + kLA - 1 < next) ? W[j + kLA - 1] : kInf;
+              }
+            }
+            const uint64_t wsum = wk[0] + wk[1];
+            W[next] = wsum;
+            PAR[pk[0]] = next;
+            PAR[pk[1]] = next;
+            // the new node enters the register window when it is one of the
+            // next kLA internal nodes
+            const uint32_t d = next - j;
+#pragma unroll
+            for (uint32_t r = 0; r < kLA; r++)
+              if (d == r) nw[r] = wsum;
+            next++;
+          }
+          PAR[2 * s - 2] = 2 * s - 2;
+        }
+        __syncthreads();
+        // depths by pointer jumping (double-buffered ancestor/depth arrays)
+        const uint32_t nn = 2 * s - 1;
+        uint32_t *ANC = ANC_a, *DEP = DEP_a, *ANC2 = ANC_b, *DEP2 = DEP_b;
+        for (uint32_t v = tid; v < nn; v += kCbNT) {
+          ANC[v] = PAR[v];
+          DEP[v] = (v == nn - 1) ? 0u : 1u;
+        }
+        __syncthreads();
+        for (uint32_t span = 1; span < nn; span <<= 1) {
+          // 4 nodes per thread at a time, so their loads overlap
+          for (uint32_t v0 = tid; v0 < nn; v0 += 4 * kCbNT) {
+            uint32_t a[4], d[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+              const uint32_t v = v0 + u * kCbNT;
+              a[u] = v < nn ? ANC[v] : 0u;
+              d[u] = v < nn ? DEP[v] : 0u;
+            }
+            uint32_t da[4], aa[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+              da[u] = DEP[a[u]];
+              aa[u] = ANC[a[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+              const uint32_t v = v0 + u * kCbNT;
+              if (v < nn) {
+                DEP2[v] = d[u] + da[u];
+                ANC2[v] = aa[u];
+              }
+            }
+          }
+          __syncthreads();
+          uint32_t* t0 = ANC; ANC = ANC2; ANC2 = t0;
+          uint32_t* t1 = DEP; DEP = DEP2; DEP2 = t1;
+        }
+        uint32_t md = 0;
+        for (uint32_t v = tid; v < s; v += kCbNT) md = max(md, DEP[v]);
+        for (int o = 32; o >= 1; o >>= 1) md = max(md, (uint32_t)__shfl_xor(md, o, 64));
+        if (tid == 0) s_maxd = 0;
+        __syncthreads();
+        if ((tid & 63) == 0) atomicMax(&s_maxd, md);
+        __syncthreads();
+        const uint32_t maxd = s_maxd;
+        if (maxd <= (uint32_t)kLmax) {
+          for (uint32_t v = tid; v < s; v += kCbNT) A.len[K[v] & 0xFFFF] = (uint8_t)DEP[v];
+          if (tid == 0) {
+            P->n_used = s;
+            P->max_len = maxd;
+          }
+          __syncthreads();
+          break;
+        }
+        // halve frequencies, keep >= 1
+        for (uint32_t v = tid; v < s; v += kCbNT) {
+          uint64_t f = K[v] >> 16;
+          f >>= 1;
+          if (!f) f = 1;
+          K[v] = (f << 16) | (K[v] & 0xFFFF);
+        }
+        __syncthreads();
+      }
+      // canonical codes: sort used symbols by (length, symbol)
+      if (tid < 32) s_cnt[tid] = 0;
+      __syncthreads();
+      for (uint32_t v = tid; v < s; v += kCbNT) {
+        const uint32_t sym = (uint32_t)(K[v] & 0xFFFF);
+        const uint32_t l = A.len[sym];
+        K[v] = ((uint64_t)l << 16) | sym;
+        atomicAdd(&s_cnt[l], 1u);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        uint32_t code = 0, start = 0;
+        for (int l = 1; l <= kLmax; l++) {
+          s_first[l] = code;
+          s_start[l] = start;
+          code = (code + s_cnt[l]) << 1;
+          start += s_cnt[l];
+        }
+      }
+      if (lds)
         bitonic_sort<kCbNT>(K, np2);
       else
         bitonic_sort_big<kCbNT>(K, np2, s_w, 2 * kCbLdsSyms);
-      if (tid == 0) {
-        // two-queue merge: leaves 0..s-1, internal nodes s..2s-2.  The two
-        // heads of each queue live in registers and the value after a head
-        // is read when that head is taken, so a pick rarely waits on memory.
-        constexpr uint64_t kInf = ~0ull;
-        uint32_t i = 0, j = s, next = s;
-        uint64_t l0 = K[0] >> 16, l1 = (1 < s) ? (K[1] >> 16) : kInf;  // leaves i, i + 1
-        uint64_t n0 = kInf, n1 = kInf;  // internal nodes j, j + 1 (when below next)
-        for (uint32_t step = 0; step + 1 < s; step++) {
-          uint32_t pk[2];
-          uint64_t wk[2];
-#pragma unroll
-          for (int q = 0; q < 2; q++) {
-            if (i < s && (j >= next || l0 <= n0)) {
-              pk[q] = i;
-              wk[q] = l0;
-              i++;
-              l0 = l1;
-              l1 = (i + 1 < s) ? (K[i + 1] >> 16) : kInf;
-            } else {
-              pk[q] = j;
-              wk[q] = n0;
-              j++;
-              n0 = n1;
-              n1 = (j + 1 < next) ? W[j + 1] : kInf;
-            }
-          }
-          const uint64_t wsum = wk[0] + wk[1];
-          W[next] = wsum;
-          PAR[pk[0]] = next;
-          PAR[pk[1]] = next;
-          // the new node joins the internal queue as its head or second entry
-          // when the queue held fewer than two
-          if (next == j)
-            n0 = wsum;
-          else if (next == j + 1)
-            n1 = wsum;
-          next++;
-        }
-        PAR[2 * s - 2] = 2 * s - 2;
-      }
-      __syncthreads();
-      // depths by pointer jumping (double-buffered ancestor/depth arrays)
-      const uint32_t nn = 2 * s - 1;
-      uint32_t *ANC, *DEP, *ANC2, *DEP2;
-      if (in_lds) {
-        ANC = (uint32_t*)s_w;  // merge weights are no longer needed
-        ANC2 = (uint32_t*)s_w + 2 * kCbLdsSyms;
-        DEP = s_dep;
-        DEP2 = s_par2;
-      } else {
-        ANC = A.ganc;
-        ANC2 = A.ganc + 131072;
-        DEP = A.gdep;
-        DEP2 = A.gdep + 131072;
-      }
-      for (uint32_t v = tid; v < nn; v += kCbNT) {
-        ANC[v] = PAR[v];
-        DEP[v] = (v == nn - 1) ? 0u : 1u;
-      }
-      __syncthreads();
-      for (uint32_t span = 1; span < nn; span <<= 1) {
-        // 4 nodes per thread at a time, so their loads overlap
-        for (uint32_t v0 = tid; v0 < nn; v0 += 4 * kCbNT) {
-          uint32_t a[4], d[4];
-#pragma unroll
-          for (int u = 0; u < 4; u++) {
-            const uint32_t v = v0 + u * kCbNT;
-            a[u] = v < nn ? ANC[v] : 0u;
-            d[u] = v < nn ? DEP[v] : 0u;
-          }
-          uint32_t da[4], aa[4];
-#pragma unroll
-          for (int u = 0; u < 4; u++) {
-            da[u] = DEP[a[u]];
-            aa[u] = ANC[a[u]];
-          }
-#pragma unroll
-          for (int u = 0; u < 4; u++) {
-            const uint32_t v = v0 + u * kCbNT;
-            if (v < nn) {
-              DEP2[v] = d[u] + da[u];
-              ANC2[v] = aa[u];
-            }
-          }
-        }
-        __syncthreads();
-        uint32_t* t0 = ANC; ANC = ANC2; ANC2 = t0;
-        uint32_t* t1 = DEP; DEP = DEP2; DEP2 = t1;
-      }
-      uint32_t md = 0;
-      for (uint32_t v = tid; v < s; v += kCbNT) md = max(md, DEP[v]);
-      for (int o = 32; o >= 1; o >>= 1) md = max(md, (uint32_t)__shfl_xor(md, o, 64));
-      if (tid == 0) s_maxd = 0;
-      __syncthreads();
-      if ((tid & 63) == 0) atomicMax(&s_maxd, md);
-      __syncthreads();
-      const uint32_t maxd = s_maxd;
-      if (maxd <= (uint32_t)kLmax) {
-        for (uint32_t v = tid; v < s; v += kCbNT) A.len[K[v] & 0xFFFF] = (uint8_t)DEP[v];
-        if (tid == 0) {
-          P->n_used = s;
-          P->max_len = maxd;
-        }
-        __syncthreads();
-        break;
-      }
-      // halve frequencies, keep >= 1
       for (uint32_t v = tid; v < s; v += kCbNT) {
-        uint64_t f = K[v] >> 16;
-        f >>= 1;
-        if (!f) f = 1;
-        K[v] = (f << 16) | (K[v] & 0xFFFF);
+        const uint32_t sym = (uint32_t)(K[v] & 0xFFFF);
+        const uint32_t l = (uint32_t)(K[v] >> 16);
+        A.cw[sym] = s_first[l] + (v - s_start[l]);
       }
-      __syncthreads();
-    }
-    // canonical codes: sort used symbols by (length, symbol)
-    if (tid < 32) s_cnt[tid] = 0;
-    __syncthreads();
-    for (uint32_t v = tid; v < s; v += kCbNT) {
-      const uint32_t sym = (uint32_t)(K[v] & 0xFFFF);
-      const uint32_t l = A.len[sym];
-      K[v] = ((uint64_t)l << 16) | sym;
-      atomicAdd(&s_cnt[l], 1u);
-    }
-    __syncthreads();
-    if (tid == 0) {
-      uint32_t code = 0, start = 0;
-      for (int l = 1; l <= kLmax; l++) {
-        s_first[l] = code;
-        s_start[l] = start;
-        code = (code + s_cnt[l]) << 1;
-        start += s_cnt[l];
-      }
-    }
+    };
     if (in_lds)
-      bitonic_sort<kCbNT>(K, np2);
+      // merge weights are no longer needed once the depths are computed
+      build(s_keys, s_w, s_par, (uint32_t*)s_w, (uint32_t*)s_w + 2 * kCbLdsSyms, s_dep, s_par2, true);
     else
-      bitonic_sort_big<kCbNT>(K, np2, s_w, 2 * kCbLdsSyms);
-    for (uint32_t v = tid; v < s; v += kCbNT) {
-      const uint32_t sym = (uint32_t)(K[v] & 0xFFFF);
-      const uint32_t l = (uint32_t)(K[v] >> 16);
-      A.cw[sym] = s_first[l] + (v - s_start[l]);
-    }
+      build(A.gkeys, A.gw, A.gpar, A.ganc, A.ganc + 131072, A.gdep, A.gdep + 131072, false);
   }
   if (tid == 0) {
     const double hr = 1.0 - (double)A.hist[0] / (double)A.n;
