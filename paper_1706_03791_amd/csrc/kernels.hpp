@@ -1339,12 +1339,13 @@ __global__ void __launch_bounds__(1024) dectab_kernel(const uint8_t* comp, uint6
                                                       uint32_t m, DecTables* D, uint64_t* gkeys,
                                                       uint32_t* sorted_syms, DevPlan* P) {
   __shared__ uint64_t s_keys[4096];
+  __shared__ uint32_t s_lut[4096];  // the single-code table, built here and copied out once
   __shared__ uint32_t s_cnt[32], s_first[32], s_start[32];
   __shared__ int s_bad;
   const int tid = threadIdx.x;
   if (tid == 0) s_bad = 0;
   if (tid < 32) s_cnt[tid] = 0;
-  for (int i = tid; i < 4096; i += 1024) D->lut[i] = 0;
+  for (int i = tid; i < 4096; i += 1024) s_lut[i] = 0;
   __syncthreads();
   const uint32_t nsym = 1u << m;
   if (n_used == 0 || n_used > nsym) {
@@ -1353,110 +1354,119 @@ __global__ void __launch_bounds__(1024) dectab_kernel(const uint8_t* comp, uint6
   }
   uint32_t np2 = 1;
   while (np2 < n_used) np2 <<= 1;
-  uint64_t* K = (np2 <= 4096) ? s_keys : gkeys;
-  for (uint32_t e = tid; e < np2; e += 1024) {
-    if (e < n_used) {
-      const uint8_t* b = comp + off_cb + 3ull * e;
-      const uint32_t sym = b[0] | (b[1] << 8);
-      const uint32_t l = b[2];
-      if (sym >= nsym || l == 0 || l > kLmax) s_bad = 1;
-      if (e > 0) {
-        const uint8_t* pb = b - 3;
-        if ((uint32_t)(pb[0] | (pb[1] << 8)) >= sym) s_bad = 1;
+  // The rest takes the key array as an argument so that, called with the LDS
+  // array, its accesses compile to LDS instructions (a pointer that may
+  // address LDS or global memory compiles to slower generic ones).
+  auto build = [&](uint64_t* K, bool lds) {
+    for (uint32_t e = tid; e < np2; e += 1024) {
+      if (e < n_used) {
+        const uint8_t* b = comp + off_cb + 3ull * e;
+        const uint32_t sym = b[0] | (b[1] << 8);
+        const uint32_t l = b[2];
+        if (sym >= nsym || l == 0 || l > kLmax) s_bad = 1;
+        if (e > 0) {
+          const uint8_t* pb = b - 3;
+          if ((uint32_t)(pb[0] | (pb[1] << 8)) >= sym) s_bad = 1;
+        }
+        K[e] = ((uint64_t)l << 16) | sym;
+        if (l >= 1 && l <= kLmax) atomicAdd(&s_cnt[l], 1u);
+      } else {
+        K[e] = ~0ull;
       }
-      K[e] = ((uint64_t)l << 16) | sym;
-      if (l >= 1 && l <= kLmax) atomicAdd(&s_cnt[l], 1u);
-    } else {
-      K[e] = ~0ull;
     }
-  }
-  __syncthreads();
-  if (tid == 0) {
-    uint64_t code = 0;
-    uint32_t start = 0;
-    for (int l = 1; l <= kLmax; l++) {
-      s_first[l] = (uint32_t)code;
-      s_start[l] = start;
-      if (code + s_cnt[l] > (1ull << l)) s_bad = 1;
-      code = (code + s_cnt[l]) << 1;
-      start += s_cnt[l];
+    __syncthreads();
+    if (tid == 0) {
+      uint64_t code = 0;
+      uint32_t start = 0;
+      for (int l = 1; l <= kLmax; l++) {
+        s_first[l] = (uint32_t)code;
+        s_start[l] = start;
+        if (code + s_cnt[l] > (1ull << l)) s_bad = 1;
+        code = (code + s_cnt[l]) << 1;
+        start += s_cnt[l];
+      }
+      for (int l = 0; l < 32; l++) {
+        const bool in = l >= 1 && l <= kLmax;
+        D->first[l] = in ? s_first[l] : 0;
+        D->count[l] = s_cnt[l];
+        D->start[l] = in ? s_start[l] : 0;
+        // Kraft-valid lengths keep first + count <= 2^l, so lim <= 2^27
+        D->lim[l] = in ? (uint32_t)(((uint64_t)s_first[l] + s_cnt[l]) << (kLmax - l)) : (l ? (1u << kLmax) : 0u);
+      }
+      D->nsorted = n_used;
     }
-    for (int l = 0; l < 32; l++) {
-      const bool in = l >= 1 && l <= kLmax;
-      D->first[l] = in ? s_first[l] : 0;
-      D->count[l] = s_cnt[l];
-      D->start[l] = in ? s_start[l] : 0;
-      // Kraft-valid lengths keep first + count <= 2^l, so lim <= 2^27
-      D->lim[l] = in ? (uint32_t)(((uint64_t)s_first[l] + s_cnt[l]) << (kLmax - l)) : (l ? (1u << kLmax) : 0u);
+    __syncthreads();
+    if (s_bad) {
+      if (tid == 0) set_status(P, SZ_ECORRUPT);
+      return;
     }
-    D->nsorted = n_used;
-  }
-  __syncthreads();
-  if (s_bad) {
-    if (tid == 0) set_status(P, SZ_ECORRUPT);
-    return;
-  }
-  if (K == s_keys)
-    bitonic_sort<1024>(K, np2);
+    if (lds)
+      bitonic_sort<1024>(K, np2);
+    else
+      bitonic_sort_big<1024>(K, np2, s_keys, 4096);
+    for (uint32_t v = tid; v < n_used; v += 1024) {
+      const uint32_t sym = (uint32_t)(K[v] & 0xFFFF);
+      const uint32_t l = (uint32_t)(K[v] >> 16);
+      sorted_syms[v] = sym;
+      if (l <= (uint32_t)kLutBits) {
+        const uint32_t code = s_first[l] + (v - s_start[l]);
+        const uint32_t a = code << (kLutBits - l), b = (code + 1) << (kLutBits - l);
+        for (uint32_t q = a; q < b; q++) s_lut[q] = (l << 16) | sym;
+      }
+    }
+    __syncthreads();  // the single-code table is complete
+    for (int i = tid; i < 4096; i += 1024) D->lut[i] = s_lut[i];
+    if (nsym > 256) return;
+    // greedy decode of each 12-bit window: the codes after the first are read
+    // from the window shifted left, and one that reaches past bit 12 ends it
+    for (uint32_t q = tid; q < (1u << kLutBits); q += 1024) {
+      uint64_t syms = 0;
+      uint32_t k = 0, used = 0, nz = 0;
+      while (k < 4) {
+        const uint32_t e = s_lut[(q << used) & ((1u << kLutBits) - 1)];
+        const uint32_t l = e >> 16;
+        if (!e || used + l > (uint32_t)kLutBits) break;
+        const uint32_t sym = e & 0xFFFF;
+        syms |= (uint64_t)sym << (8 * k);
+        nz += sym == 0 ? 1u : 0u;
+        used += l;
+        k++;
+      }
+      D->mlut[q] = syms | ((uint64_t)k << 32) | ((uint64_t)used << 36) | ((uint64_t)nz << 40);
+    }
+    // Codes longer than 12 bits fill the code space after the short ones, so
+    // their 12-bit prefixes are [p0, 4096) with p0 the space the short codes
+    // take (the code is complete).
+    uint32_t p0 = 0;
+    for (int l = 1; l <= kLutBits; l++) p0 += s_cnt[l] << (kLutBits - l);
+    const uint32_t nlong = (1u << kLutBits) - p0;
+    if (nlong > kLut2Max) {
+      if (tid == 0) D->lut2_n = 0;
+      return;
+    }
+    for (uint32_t q = tid; q < kLut2Max * 16; q += 1024) D->lut2[q] = 0;
+    __syncthreads();
+    for (uint32_t v = tid; v < n_used; v += 1024) {
+      const uint32_t sym = (uint32_t)(K[v] & 0xFFFF);
+      const uint32_t l = (uint32_t)(K[v] >> 16);
+      if (l > (uint32_t)kLutBits && l <= 16) {
+        const uint32_t code = s_first[l] + (v - s_start[l]);
+        const uint32_t a = code << (16 - l), b = (code + 1) << (16 - l);
+        for (uint32_t x = a; x < b; x++) {
+          const uint32_t r = (x >> 4) - p0;
+          if (r < kLut2Max) D->lut2[r * 16 + (x & 15)] = (l << 16) | sym;
+        }
+      }
+    }
+    if (tid == 0) {
+      D->lut2_p0 = p0;
+      D->lut2_n = nlong;
+    }
+  };
+  if (np2 <= 4096)
+    build(s_keys, true);
   else
-    bitonic_sort_big<1024>(K, np2, s_keys, 4096);
-  for (uint32_t v = tid; v < n_used; v += 1024) {
-    const uint32_t sym = (uint32_t)(K[v] & 0xFFFF);
-    const uint32_t l = (uint32_t)(K[v] >> 16);
-    sorted_syms[v] = sym;
-    if (l <= (uint32_t)kLutBits) {
-      const uint32_t code = s_first[l] + (v - s_start[l]);
-      const uint32_t a = code << (kLutBits - l), b = (code + 1) << (kLutBits - l);
-      for (uint32_t q = a; q < b; q++) D->lut[q] = (l << 16) | sym;
-    }
-  }
-  if (nsym > 256) return;
-  __syncthreads();  // the single-code table above is complete
-  // greedy decode of each 12-bit window: the codes after the first are read
-  // from the window shifted left, and one that reaches past bit 12 ends it
-  for (uint32_t q = tid; q < (1u << kLutBits); q += 1024) {
-    uint64_t syms = 0;
-    uint32_t k = 0, used = 0, nz = 0;
-    while (k < 4) {
-      const uint32_t e = D->lut[(q << used) & ((1u << kLutBits) - 1)];
-      const uint32_t l = e >> 16;
-      if (!e || used + l > (uint32_t)kLutBits) break;
-      const uint32_t sym = e & 0xFFFF;
-      syms |= (uint64_t)sym << (8 * k);
-      nz += sym == 0 ? 1u : 0u;
-      used += l;
-      k++;
-    }
-    D->mlut[q] = syms | ((uint64_t)k << 32) | ((uint64_t)used << 36) | ((uint64_t)nz << 40);
-  }
-  // Codes longer than 12 bits fill the code space after the short ones, so
-  // their 12-bit prefixes are [p0, 4096) with p0 the space the short codes
-  // take (the code is complete).
-  uint32_t p0 = 0;
-  for (int l = 1; l <= kLutBits; l++) p0 += s_cnt[l] << (kLutBits - l);
-  const uint32_t nlong = (1u << kLutBits) - p0;
-  if (nlong > kLut2Max) {
-    if (tid == 0) D->lut2_n = 0;
-    return;
-  }
-  for (uint32_t q = tid; q < kLut2Max * 16; q += 1024) D->lut2[q] = 0;
-  __syncthreads();
-  for (uint32_t v = tid; v < n_used; v += 1024) {
-    const uint32_t sym = (uint32_t)(K[v] & 0xFFFF);
-    const uint32_t l = (uint32_t)(K[v] >> 16);
-    if (l > (uint32_t)kLutBits && l <= 16) {
-      const uint32_t code = s_first[l] + (v - s_start[l]);
-      const uint32_t a = code << (16 - l), b = (code + 1) << (16 - l);
-      for (uint32_t x = a; x < b; x++) {
-        const uint32_t r = (x >> 4) - p0;
-        if (r < kLut2Max) D->lut2[r * 16 + (x & 15)] = (l << 16) | sym;
-      }
-    }
-  }
-  if (tid == 0) {
-    D->lut2_p0 = p0;
-    D->lut2_n = nlong;
-  }
+    build(gkeys, false);
 }
 
 // K8: one lane per chunk decodes its symbols sequentially from the chunk's
