@@ -59,6 +59,16 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, uint64_t n) {
        i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = v;
 }
+// Two arrays zeroed by one launch.
+__global__ void zero2_u32_kernel(uint32_t* p, uint64_t n, uint32_t* q, uint64_t m) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n + m;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    if (i < n)
+      p[i] = 0;
+    else
+      q[i - n] = 0;
+  }
+}
 
 // Zero the first plan->total bytes of the container (sections are written
 // with OR operations and padding must read as zero).
@@ -980,6 +990,13 @@ __device__ __forceinline__ void scan_tile_offsets_dev(uint64_t* tsum, uint64_t n
 __global__ void __launch_bounds__(1024) scan_tile_offsets(uint64_t* tsum, uint64_t ntiles, uint64_t* total) {
   scan_tile_offsets_dev(tsum, ntiles, total);
 }
+// Phase 2 of a scan whose total must equal `want` (else the container is
+// corrupt).
+__global__ void __launch_bounds__(1024) scan_tile_offsets_check(uint64_t* tsum, uint64_t ntiles, uint64_t* total,
+                                                                uint64_t want, DevPlan* P) {
+  scan_tile_offsets_dev(tsum, ntiles, total);
+  if (threadIdx.x == 0 && *total != want) set_status(P, SZ_ECORRUPT);
+}
 
 // Phase 3: exclusive prefix of every element.
 __device__ __forceinline__ void scan_apply_dev(const uint32_t* __restrict__ in, uint64_t n, const uint64_t* tsum,
@@ -1297,6 +1314,13 @@ __device__ __forceinline__ void raw_copy_kernel_dev(const T* __restrict__ x, uin
 }
 template <typename T>
 __global__ void raw_copy_kernel(const T* __restrict__ x, uint8_t* out, uint64_t n, const DevPlan* P) {
+  raw_copy_kernel_dev<T>(x, out, n, P);
+}
+// The container's body before the encoder fills it: zeroed (the encoder ORs
+// its bits in) or, for a raw container, the field itself; one launch for both.
+template <typename T>
+__global__ void container_prep_kernel(const T* __restrict__ x, uint8_t* out, uint64_t n, const DevPlan* P) {
+  zero_container_kernel_dev((uint32_t*)out, P);
   raw_copy_kernel_dev<T>(x, out, n, P);
 }
 

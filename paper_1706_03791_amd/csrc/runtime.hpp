@@ -391,6 +391,20 @@ void fill(uint32_t* p, uint32_t v, uint64_t n, hipStream_t st) {
   hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)g), dim3(256), 0, st, p, v, n);
 }
 
+void zero2(uint32_t* p, uint64_t n, uint32_t* q, uint64_t m, hipStream_t st) {
+  const uint64_t g = std::min<uint64_t>(ceil_div(n + m, 256), 4096);
+  hipLaunchKernelGGL(zero2_u32_kernel, dim3((unsigned)g), dim3(256), 0, st, p, n, q, m);
+}
+
+// A scan whose total must equal `want` (a corrupt container otherwise).
+void scan_u32_check(const uint32_t* in, uint64_t n, uint64_t* out, uint64_t* tsum, uint64_t* total, uint64_t want,
+                    DevPlan* P, hipStream_t st) {
+  const uint64_t nt = ceil_div(n, 4096);
+  hipLaunchKernelGGL(scan_tile_sums, dim3((unsigned)nt), dim3(1024), 0, st, in, n, tsum);
+  hipLaunchKernelGGL(scan_tile_offsets_check, dim3(1), dim3(1024), 0, st, tsum, nt, total, want, P);
+  hipLaunchKernelGGL(scan_apply, dim3((unsigned)nt), dim3(1024), 0, st, in, n, (const uint64_t*)tsum, out);
+}
+
 void scan_u32(const uint32_t* in, uint64_t n, uint64_t* out, uint64_t* tsum, uint64_t* total, hipStream_t st) {
   const uint64_t nt = ceil_div(n, 4096);
   hipLaunchKernelGGL(scan_tile_sums, dim3((unsigned)nt), dim3(1024), 0, st, in, n, tsum);
@@ -432,8 +446,7 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
   }
   hipLaunchKernelGGL(eb_resolve_kernel<T>, dim3(1), dim3(64), 0, st, P, I);
   stage_end(ctx, ST_RANGE, st);
-  fill(W.hist, 0, 65536, st);
-  fill(W.progress, 0, L.g.ntiles + 1, st);
+  zero2(W.hist, 65536, W.progress, L.g.ntiles + 1, st);
   SweepArgs a;
   a.g = L.g;
   a.x = d_in;
@@ -525,9 +538,11 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
   la.head_bits = 1 + FTr<T>::EXPB;
   hipLaunchKernelGGL(layout_kernel, dim3(1), dim3(64), 0, st, la);
   {
-    const uint64_t g = std::min<uint64_t>(ceil_div(cap / 4 + 1, 256), 8192);
-    hipLaunchKernelGGL(zero_container_kernel, dim3((unsigned)g), dim3(256), 0, st, (uint32_t*)d_out,
-                       (const DevPlan*)P);
+    // zeroed container body, or the raw field when the layout chose raw
+    const uint64_t gz = std::min<uint64_t>(ceil_div(cap / 4 + 1, 256), 8192);
+    const uint64_t gr = std::min<uint64_t>(ceil_div((uint64_t)L.n * L.ts / 16 + 1, 256), 8192);
+    hipLaunchKernelGGL(container_prep_kernel<T>, dim3((unsigned)std::max(gz, gr)), dim3(256), 0, st, (const T*)d_in,
+                       (uint8_t*)d_out, (uint64_t)L.n, (const DevPlan*)P);
   }
   const unsigned enc_lds = enc_lds_bytes(L.chunk, (uint32_t)L.cw);
   if (L.cw == 1) {
@@ -564,11 +579,6 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
   h.n = (uint64_t)L.n;
   h.n_chunks = L.n_chunks;
   hipLaunchKernelGGL(header_kernel, dim3(1), dim3(256), 0, st, h);
-  {
-    const uint64_t g = std::min<uint64_t>(ceil_div((uint64_t)L.n * L.ts / 16 + 1, 256), 8192);
-    hipLaunchKernelGGL(raw_copy_kernel<T>, dim3((unsigned)g), dim3(256), 0, st, (const T*)d_in, (uint8_t*)d_out,
-                       (uint64_t)L.n, (const DevPlan*)P);
-  }
   stage_end(ctx, ST_ENCODE, st);
   return hipGetLastError() == hipSuccess ? SZ_OK : SZ_EHIP;
 }
@@ -733,9 +743,8 @@ int enqueue_decompress_t(sz_ctx* ctx, const Layout& L, const Hdr& h, const void*
   stage_begin(ctx, ST_DECTAB, st);
   hipLaunchKernelGGL(dectab_kernel, dim3(1), dim3(1024), 0, st, comp, h.off_cb, h.n_used, h.m, W.tabs, W.gkeys,
                      W.sorted, P);
-  scan_u32((const uint32_t*)(comp + h.off_ch), L.n_chunks, W.boff, W.tsum_b, W.tot + 0, st);
-  hipLaunchKernelGGL(check_total_kernel, dim3(1), dim3(64), 0, st, (const uint64_t*)(W.tot + 0), h.huff_bits, P);
-  fill(W.segcnt, 0, L.nseg, st);
+  scan_u32_check((const uint32_t*)(comp + h.off_ch), L.n_chunks, W.boff, W.tsum_b, W.tot + 0, h.huff_bits, P, st);
+  zero2(W.segcnt, L.nseg, W.progress, L.g.ntiles + 1, st);
   stage_end(ctx, ST_DECTAB, st);
   stage_begin(ctx, ST_DECODE, st);
   const uint64_t nwords = (h.huff_bits + 31) / 32;
@@ -752,8 +761,7 @@ int enqueue_decompress_t(sz_ctx* ctx, const Layout& L, const Hdr& h, const void*
                        (uint64_t)L.n, L.chunk, L.n_chunks, (const uint32_t*)(comp + h.off_ch),
                        (const uint64_t*)W.boff, (const DecTables*)W.tabs, (const uint32_t*)W.sorted,
                        (uint16_t*)W.codes, W.segcnt, X, Bx, nbx, P);
-  scan_u32(W.segcnt, L.nseg, W.useg, W.tsum_s, W.tot + 1, st);
-  hipLaunchKernelGGL(check_total_kernel, dim3(1), dim3(64), 0, st, (const uint64_t*)(W.tot + 1), U, P);
+  scan_u32_check(W.segcnt, L.nseg, W.useg, W.tsum_s, W.tot + 1, U, P, st);
   stage_end(ctx, ST_DECODE, st);
   stage_begin(ctx, ST_UNPRED, st);
   if (U) {
@@ -767,7 +775,6 @@ int enqueue_decompress_t(sz_ctx* ctx, const Layout& L, const Hdr& h, const void*
                        h.off_tl, tlw, U, h.ebT_bits, (const uint64_t*)W.roff, h.tail_bits, (T*)W.uvals, P);
   }
   stage_end(ctx, ST_UNPRED, st);
-  fill(W.progress, 0, L.g.ntiles + 1, st);
   stage_begin(ctx, ST_SWEEP_D, st);
   SweepArgs a;
   a.g = L.g;
