@@ -897,19 +897,35 @@ __device__ __forceinline__ void chunk_stats_body(const CT* __restrict__ codes, c
   const int lane = threadIdx.x & 63;
   const uint32_t per = C / 64;
   for (uint64_t c = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < n_chunks; c += (uint64_t)gridDim.x * 4) {
-    const uint32_t cnt = stage_codes<CT>(codes, n, c, C, sc, lane);
     const uint32_t k0 = (uint32_t)lane * per;
     uint32_t b = 0, z = 0, tb = 0;
-    for (uint32_t j = 0; j < per; j += 4) {
-      uint32_t sym[4];
-      lds_code4<CT>(sc, k0 + j, sym);
+    if (sizeof(CT) == 1 && per == 16 && (c + 1) * C <= n) {
+      // a whole chunk of 1-byte codes: the lane's 16 codes are one aligned
+      // 16-byte vector, read straight into registers
+      const uint4 v = ((const uint4*)(codes + c * C))[lane];
+      const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-      for (int k = 0; k < 4; k++) {
-        const bool real = k0 + j + k < cnt;
-        b += real ? (code_entry<LT>(sym[k], s_tab, len, nullptr) >> 27) : 0u;
-        if (real && sym[k] == 0) {
+      for (int k = 0; k < 16; k++) {
+        const uint32_t sym = (wv[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+        b += code_entry<LT>(sym, s_tab, len, nullptr) >> 27;
+        if (sym == 0) {
           z++;
-          tb += (uint32_t)kept_bits<T>(x[c * C + k0 + j + k], ebb);
+          tb += (uint32_t)kept_bits<T>(x[c * C + k0 + k], ebb);
+        }
+      }
+    } else {
+      const uint32_t cnt = stage_codes<CT>(codes, n, c, C, sc, lane);
+      for (uint32_t j = 0; j < per; j += 4) {
+        uint32_t sym[4];
+        lds_code4<CT>(sc, k0 + j, sym);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          const bool real = k0 + j + k < cnt;
+          b += real ? (code_entry<LT>(sym[k], s_tab, len, nullptr) >> 27) : 0u;
+          if (real && sym[k] == 0) {
+            z++;
+            tb += (uint32_t)kept_bits<T>(x[c * C + k0 + j + k], ebb);
+          }
         }
       }
     }
