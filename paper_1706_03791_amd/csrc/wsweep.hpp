@@ -33,8 +33,8 @@ namespace szh {
 constexpr int kWG = 8;       // steps per group (also the chunk length in elements)
 constexpr int kWRing = 16;   // ring slots per row: two chunks
 constexpr int kWLanes = 64;  // y-rows per tile
-constexpr int kHaloStep = 6; // steps of a group before it waits for the next group's halo
-constexpr int kPollStep = 2; // step of a group after which each wave reads its predecessors' progress
+constexpr int kHaloStep = 7; // steps of a group before it waits for the next group's halo
+constexpr int kPollStep = 4; // step of a group after which each wave reads its predecessors' progress
 static_assert(kPollStep < kHaloStep, "progress is read before it is checked");
 
 struct WArgs {
