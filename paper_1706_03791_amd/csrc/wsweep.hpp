@@ -33,9 +33,15 @@ namespace szh {
 constexpr int kWG = 8;       // steps per group (also the chunk length in elements)
 constexpr int kWRing = 16;   // ring slots per row: two chunks
 constexpr int kWLanes = 64;  // y-rows per tile
-constexpr int kHaloStep = 7; // steps of a group before it waits for the next group's halo
-constexpr int kPollStep = 4; // step of a group after which each wave reads its predecessors' progress
-static_assert(kPollStep < kHaloStep, "progress is read before it is checked");
+// Steps of a group before a tile checks its predecessors' progress and
+// loads the next group's halo, and the step after which it reads that
+// progress (measured per direction: compression checks after the last step).
+template <bool COMP>
+struct HaloSteps {
+  static constexpr int kHalo = COMP ? 8 : 7;
+  static constexpr int kPoll = COMP ? 7 : 4;
+  static_assert(kPoll < kHalo && kHalo <= kWG, "progress is read before it is checked, inside the group");
+};
 
 struct WArgs {
   int64_t dims[3];   // Z, Y, X
@@ -192,6 +198,7 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   using CW = CWord<CT>;
   constexpr int G = kWG;
   constexpr int TZ = NW * AZ;
+  constexpr int kHaloStep = HaloSteps<COMP>::kHalo, kPollStep = HaloSteps<COMP>::kPoll;
   constexpr int SB = 8 * sizeof(CT);
   constexpr int XPC = (G * (int)sizeof(T)) / 16;  // 16-byte pieces per chunk of values
   constexpr int EPP = 16 / (int)sizeof(T);        // values per piece
@@ -316,7 +323,7 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   };
   // In the loop every wave reads its predecessors' progress itself: the
   // reads go out after step kPollStep - 1 and are checked after step
-  // kHaloStep - 1, so a predecessor that is already far enough costs no
+  // kHaloStep - 1 (HaloSteps), so a predecessor that is already far enough costs no
   // round trip and no workgroup barrier.  Otherwise the wave polls.
   const uint32_t* prog_z = &A.progress[pred_z >= 0 ? pred_z : tile];
   const uint32_t* prog_y = &A.progress[pred_y >= 0 ? pred_y : tile];
