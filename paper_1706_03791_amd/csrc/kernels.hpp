@@ -1444,18 +1444,27 @@ __global__ void __launch_bounds__(1024) dectab_kernel(const uint8_t* comp, uint6
       bitonic_sort<1024>(K, np2);
     else
       bitonic_sort_big<1024>(K, np2, s_keys, 4096);
-    for (uint32_t v = tid; v < n_used; v += 1024) {
-      const uint32_t sym = (uint32_t)(K[v] & 0xFFFF);
-      const uint32_t l = (uint32_t)(K[v] >> 16);
-      sorted_syms[v] = sym;
-      if (l <= (uint32_t)kLutBits) {
-        const uint32_t code = s_first[l] + (v - s_start[l]);
-        const uint32_t a = code << (kLutBits - l), b = (code + 1) << (kLutBits - l);
-        for (uint32_t q = a; q < b; q++) s_lut[q] = (l << 16) | sym;
+    for (uint32_t v = tid; v < n_used; v += 1024) sorted_syms[v] = (uint32_t)(K[v] & 0xFFFF);
+    // Codes of length l <= kLutBits own the windows [end_{l-1}, end_l), with
+    // end_l = (first_l + count_l) << (kLutBits - l): a canonical code's ranges
+    // follow each other as l grows.  Each window takes the smallest l whose
+    // range ends past it and the symbol of rank (window >> (kLutBits - l)) -
+    // first_l among the codes of that length; windows past end_kLutBits start
+    // longer codes and stay 0.
+    for (uint32_t q = tid; q < (1u << kLutBits); q += 1024) {
+      uint32_t L = 0;
+#pragma unroll
+      for (int l = kLutBits; l >= 1; l--)
+        if (q < ((s_first[l] + s_cnt[l]) << (kLutBits - l))) L = (uint32_t)l;
+      uint32_t e = 0;
+      if (L) {
+        const uint32_t v = s_start[L] + (q >> (kLutBits - L)) - s_first[L];
+        e = (L << 16) | (uint32_t)(K[v] & 0xFFFF);
       }
+      s_lut[q] = e;
+      D->lut[q] = e;
     }
     __syncthreads();  // the single-code table is complete
-    for (int i = tid; i < 4096; i += 1024) D->lut[i] = s_lut[i];
     if (nsym > 256) return;
     // greedy decode of each 12-bit window: the codes after the first are read
     // from the window shifted left, and one that reaches past bit 12 ends it
