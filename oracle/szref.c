@@ -56,10 +56,10 @@ static int make_layout(const szref_params* p, struct layout* L) {
   for (int d = 0; d < 3; d++) { L->dims[d] = 1; L->block[d] = 1; }
   uint64_t n = 1;
   for (uint32_t d = 0; d < p->ndim; d++) {
-    if (p->dims[d] == 0) return SZREF_EINVAL;
+    /* N < 2^40, tested before the product so that it cannot wrap */
+    if (p->dims[d] == 0 || p->dims[d] > ((1ull << 40) - 1) / n) return SZREF_EINVAL;
     L->dims[pad + d] = p->dims[d];
     n *= p->dims[d];
-    if (n >= (1ull << 40)) return SZREF_EINVAL;
   }
   for (uint32_t d = 0; d < p->ndim; d++) {
     uint64_t b = p->block[d];
@@ -633,6 +633,11 @@ int szref_inspect(const uint8_t* comp, size_t size, szref_params* p, szref_stats
   return SZREF_OK;
 }
 
+/* Does a section of len bytes at offset off lie within the first total bytes? */
+static int section_fits(uint64_t off, uint64_t len, uint64_t total) {
+  return off <= total && len <= total - off;
+}
+
 int szref_decompress(const uint8_t* comp, size_t size, void* out, size_t cap) {
   struct hdr h;
   int rc = read_hdr(comp, size, &h);
@@ -657,11 +662,16 @@ int szref_decompress(const uint8_t* comp, size_t size, void* out, size_t cap) {
   const uint32_t nsym = 1u << h.m;
   const uint64_t n = L.n;
   if (h.n_chunks != (n + h.chunk - 1) / h.chunk) return SZREF_ECORRUPT;
-  /* section bounds */
-  if (h.off_cb + 3ull * h.n_used > h.total || h.off_ch + 4ull * h.n_chunks > h.total ||
-      h.off_bs + 4ull * ((h.huff_bits + 31) / 32) > h.total ||
-      h.off_hd + 4ull * ((h.n_unpred * (h.dtype ? 12 : 9) + 31) / 32) > h.total ||
-      h.off_tl + 4ull * ((h.tail_bits + 31) / 32) > h.total)
+  /* Section bounds.  The counts are bounded first so that no section
+   * length below can wrap around, and each check is written so that a huge
+   * offset cannot wrap either. */
+  if (h.n_used > nsym || h.n_unpred > n || h.huff_bits > n * LMAX ||
+      h.tail_bits > h.n_unpred * (h.dtype ? 52 : 23))
+    return SZREF_ECORRUPT;
+  if (!section_fits(h.off_cb, 3ull * h.n_used, h.total) || !section_fits(h.off_ch, 4ull * h.n_chunks, h.total) ||
+      !section_fits(h.off_bs, 4ull * ((h.huff_bits + 31) / 32), h.total) ||
+      !section_fits(h.off_hd, 4ull * ((h.n_unpred * (h.dtype ? 12 : 9) + 31) / 32), h.total) ||
+      !section_fits(h.off_tl, 4ull * ((h.tail_bits + 31) / 32), h.total))
     return SZREF_ECORRUPT;
 
   uint8_t* len = (uint8_t*)calloc(nsym, 1);

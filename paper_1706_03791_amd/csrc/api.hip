@@ -145,6 +145,7 @@ int sz_inspect(const void* h_hdr, size_t n, sz_params* p, sz_stats* s) {
   Hdr h;
   if (n < kHdr) return SZ_ECORRUPT;
   int rc = parse_header((const uint8_t*)h_hdr, n, h, false);
+  if (!rc) rc = check_sections(h);
   if (rc) return rc;
   if (p) hdr_params(h, p);
   if (s) {

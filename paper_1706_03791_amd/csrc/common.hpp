@@ -8,32 +8,13 @@
 #include <stdint.h>
 
 #include "../../include/szhip.h"
+#include "container.hpp"
 
 namespace szh {
 
 
 // ------------------------------------------------------------- container
-// Byte layout (little endian), 192-byte header then 64-byte aligned sections:
-//   0 u32 magic "SZH1"        4 u16 version      6 u16 flags (bit0 raw copy)
-//   8 u8 dtype  9 u8 ndim  10 u8 layers  11 u8 m (bits per code in use)
-//  12 u8 eb_mode  13 u8 m requested (0 adaptive)  14 u16 reserved
-//  16 u64 dims[3]   40 u64 block[3]   64 f64 eb_abs   72 f64 eb_rel
-//  80 u64 bit pattern of the element-type bound   88 u64 points
-//  96 u64 unpredictable points  104 u64 Huffman bits  112 u64 tail bits
-// 120 u32 symbols per chunk    124 u32 codebook entries  128 u64 chunks
-// 136..176 u64 offsets: codebook, chunk table, bitstream, heads, tails, total
-// Sections: codebook (u16 symbol, u8 length) sorted by symbol; chunk table
-// (u32 bits per chunk); Huffman bitstream; heads (sign+exponent, 9 or 12
-// bits each); tails (kept mantissa bits).  Bit streams are MSB-first in
-// little-endian u32 words.
-constexpr uint32_t kMagic = 0x31485A53u;
-constexpr uint32_t kVersion = 1;
-constexpr uint32_t kHdr = 192;
-constexpr uint32_t kAlign = 64;
-constexpr uint32_t kDefaultChunk = 1024;
-constexpr uint32_t kMaxChunk = 4096;
-constexpr uint32_t kDefaultBlock1D = 2048;
-constexpr int kLmax = 27;
+// The format and its constants are in container.hpp.
 
 // Steps per synchronisation group in the wavefront sweep; also the element
 // count of the aligned chunks staged through LDS rings.

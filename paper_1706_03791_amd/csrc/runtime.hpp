@@ -41,6 +41,7 @@ struct sz_ctx {
   uint64_t prof_calls[ST_COUNT] = {};
   void* arena = nullptr;
   size_t arena_size = 0;
+  bool fixed_arena = false;        // arena memory lent by someone else: never (re)allocated here
   szh::DevPlan* plan = nullptr;    // device
   szh::DevPlan* h_plan = nullptr;  // pinned host mirror
   uint8_t* h_hdr = nullptr;   // pinned host header staging
@@ -148,9 +149,9 @@ int resolve(const sz_params* p, Layout& L, const Sched* sched_override = nullptr
     L.out_block[d] = 1;
   }
   for (int d = 0; d < L.ndim; d++) {
-    if (p->dims[d] == 0 || p->dims[d] >= (1ull << 31)) return SZ_EINVAL;
+    // n stays below 2^40; the test comes before the product, which cannot wrap
+    if (p->dims[d] == 0 || p->dims[d] >= (1ull << 31) || n > ((1ull << 40) - 1) / p->dims[d]) return SZ_EINVAL;
     n *= p->dims[d];
-    if (n >= (1ull << 40)) return SZ_EINVAL;
     L.dims3[pad + d] = (int64_t)p->dims[d];
     uint64_t b = p->block[d];
     if (b == 0) b = (L.ndim == 1) ? kDefaultBlock1D : p->dims[d];
@@ -299,6 +300,7 @@ size_t carve_comp(const Layout& L, uint8_t* base, CompWs* W, bool keep_values = 
 
 int ensure_arena(sz_ctx* ctx, size_t bytes) {
   if (bytes <= ctx->arena_size) return SZ_OK;
+  if (ctx->fixed_arena) return SZ_ENOMEM;
   if (ctx->arena) {
     if (hipDeviceSynchronize() != hipSuccess) return SZ_EHIP;
     (void)hipFree(ctx->arena);
@@ -604,58 +606,6 @@ void fill_stats(const DevPlan& P, const Layout& L, sz_stats* s) {
 }
 
 // -------------------------------------------------------------- decompress
-struct Hdr {
-  uint32_t flags, dtype, ndim, layers, m, eb_mode, m_req;
-  uint64_t dims[3], block[3];
-  double eb_abs, eb_rel;
-  uint64_t ebT_bits, n, n_unpred, huff_bits, tail_bits;
-  uint32_t chunk, n_used;
-  uint64_t n_chunks, off_cb, off_ch, off_bs, off_hd, off_tl, total;
-};
-
-uint64_t g64(const uint8_t* b) {
-  uint64_t v = 0;
-  for (int i = 7; i >= 0; i--) v = (v << 8) | b[i];
-  return v;
-}
-uint32_t g32(const uint8_t* b) { return (uint32_t)(b[0] | (b[1] << 8) | (b[2] << 16) | ((uint32_t)b[3] << 24)); }
-
-int parse_header(const uint8_t* b, size_t size, Hdr& h, bool check_total = true) {
-  if (size < kHdr) return SZ_ECORRUPT;
-  if (g32(b) != kMagic || (b[4] | (b[5] << 8)) != (int)kVersion) return SZ_ECORRUPT;
-  h.flags = b[6] | (b[7] << 8);
-  h.dtype = b[8];
-  h.ndim = b[9];
-  h.layers = b[10];
-  h.m = b[11];
-  h.eb_mode = b[12];
-  h.m_req = b[13];
-  for (int d = 0; d < 3; d++) h.dims[d] = g64(b + 16 + 8 * d);
-  for (int d = 0; d < 3; d++) h.block[d] = g64(b + 40 + 8 * d);
-  uint64_t u;
-  u = g64(b + 64);
-  std::memcpy(&h.eb_abs, &u, 8);
-  u = g64(b + 72);
-  std::memcpy(&h.eb_rel, &u, 8);
-  h.ebT_bits = g64(b + 80);
-  h.n = g64(b + 88);
-  h.n_unpred = g64(b + 96);
-  h.huff_bits = g64(b + 104);
-  h.tail_bits = g64(b + 112);
-  h.chunk = g32(b + 120);
-  h.n_used = g32(b + 124);
-  h.n_chunks = g64(b + 128);
-  h.off_cb = g64(b + 136);
-  h.off_ch = g64(b + 144);
-  h.off_bs = g64(b + 152);
-  h.off_hd = g64(b + 160);
-  h.off_tl = g64(b + 168);
-  h.total = g64(b + 176);
-  if (h.dtype > 1 || h.ndim < 1 || h.ndim > 3 || h.layers < 1 || h.layers > 4) return SZ_ECORRUPT;
-  if (check_total && h.total > size) return SZ_ECORRUPT;
-  return SZ_OK;
-}
-
 void hdr_params(const Hdr& h, sz_params* p) {
   std::memset(p, 0, sizeof *p);
   p->dtype = h.dtype;
@@ -826,24 +776,18 @@ __global__ void raw_unpack_kernel(const uint8_t* comp, uint8_t* out, uint64_t by
 int prepare_decompress(const uint8_t* hdr, size_t comp_size, size_t cap, Hdr& h, Layout& L) {
   int rc = parse_header(hdr, comp_size, h);
   if (rc) return rc;
+  if ((rc = check_sections(h))) return rc;
   sz_params p;
   hdr_params(h, &p);
-  p.quant_bits = h.m;  // intermediate code width follows the stored m
+  p.quant_bits = (h.flags & 1) ? 0 : h.m;  // intermediate code width follows the stored m
   if (resolve(&p, L)) return SZ_ECORRUPT;
   for (uint32_t d = 0; d < h.ndim; d++)
     if (h.block[d] != L.out_block[d]) return SZ_ECORRUPT;
   if ((uint64_t)L.n != h.n) return SZ_ECORRUPT;
   const uint64_t bytes = (uint64_t)L.n * L.ts;
   if (cap < bytes) return SZ_ECAPACITY;
-  if (h.flags & 1) return h.total == kHdr + bytes ? SZ_OK : SZ_ECORRUPT;
-  if (h.m < 1 || h.m > 16 || h.chunk != L.chunk || h.n_chunks != L.n_chunks) return SZ_ECORRUPT;
-  if (h.m_req != 0 && h.m_req != h.m) return SZ_ECORRUPT;
-  const int HB = h.dtype ? 12 : 9;
-  if (h.off_cb != kHdr || h.off_cb + 3ull * h.n_used > h.total || h.off_ch + 4ull * h.n_chunks > h.total ||
-      h.off_bs + 4ull * ((h.huff_bits + 31) / 32) > h.total ||
-      h.off_hd + 4ull * ((h.n_unpred * HB + 31) / 32) > h.total || h.off_tl + 4ull * ((h.tail_bits + 31) / 32) > h.total ||
-      (h.off_ch & 3) || (h.off_bs & 3) || (h.off_hd & 3) || (h.off_tl & 3) || h.n_unpred > h.n)
-    return SZ_ECORRUPT;
+  if (h.flags & 1) return SZ_OK;
+  if (h.chunk != L.chunk || h.n_chunks != L.n_chunks) return SZ_ECORRUPT;
   if (L.cw == 1 && h.m > 8) return SZ_ECORRUPT;
   return SZ_OK;
 }

@@ -164,6 +164,7 @@ int launch(sz_server* s, Slot& sl, Req* q) {
   sz_ctx& c = sl.ctx;
   c.arena = (uint8_t*)s->pool_mem + q->off;
   c.arena_size = q->fp ? q->fp : 0;
+  c.fixed_arena = true;  // the carve from the pool is all this request may use
   const sz_request& r = q->r;
   int rc;
   if (r.op == SZ_REQ_COMPRESS)

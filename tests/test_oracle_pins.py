@@ -465,3 +465,30 @@ def test_canonical_codes_prefix_free_roundtrip(oracle):
     assert st["n_used_syms"] > 200
     out = oracle.decompress(buf)
     assert np.all(np.abs(out - x) < 1e-4)
+
+
+def test_fibonacci_field_forces_the_length_limit(oracle):
+    """The full-size GPU case of the A14 rebuild: its 1D field has exact
+    codes k_i + 2^(m-1) with Fibonacci counts, a textbook Huffman tree of
+    those counts is 28 levels deep (beyond the 27-bit limit), and the
+    oracle's codebook comes out within the limit after the rebuild."""
+    import heapq
+    from test_gpu_fullsize import fibonacci_field
+    x, fib = fibonacci_field(29, np.float32, 20170662)
+    # textbook Huffman depth by a heap of (weight, depth) pairs
+    heap = [(f, 0) for f in fib]
+    heapq.heapify(heap)
+    while len(heap) > 1:
+        a, b = heapq.heappop(heap), heapq.heappop(heap)
+        heapq.heappush(heap, (a[0] + b[0], max(a[1], b[1]) + 1))
+    assert heap[0][1] == 28
+    codes, xp, nu = oracle.quantize(x, m=8, layers=1, eb_mode="abs", eb_abs=0.5)
+    assert nu == 0 and np.array_equal(xp, x)
+    counts = np.bincount(codes.ravel(), minlength=256)
+    assert sorted(counts[counts > 0].tolist()) == sorted(fib)
+    buf, st = oracle.compress(x, layers=1, m=8, eb_mode="abs", eb_abs=0.5)
+    off_cb = int.from_bytes(buf[136:144], "little")
+    cb = np.frombuffer(buf[off_cb:off_cb + 3 * st["n_used_syms"]], np.uint8).reshape(-1, 3)
+    lens = cb[:, 2].astype(np.int64)
+    assert lens.max() <= 27 and np.sum(2.0 ** -lens) <= 1.0
+    assert np.array_equal(oracle.decompress(buf), x)

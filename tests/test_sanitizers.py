@@ -1,0 +1,194 @@
+"""Host code under the address and undefined-behaviour sanitizers (CPU).
+
+Two small drivers are built with gcc/g++ ``-fsanitize=address,undefined``:
+
+* ``native/header_check.cpp`` runs the library's container header checks
+  (``parse_header`` and ``check_sections`` of ``csrc/container.hpp``, the
+  code ``sz_inspect``, ``sz_decompress`` and the request server use before
+  any kernel touches a container);
+* ``native/oracle_decompress.c`` runs the oracle's decompressor on whole
+  containers held in exact-size heap buffers.
+
+Both are fed good containers made by the oracle and corrupted copies:
+every header bit flipped, offsets and counts set to values whose sums wrap
+around 2^64, truncations and random body flips.  Every run must end cleanly
+(the sanitizers abort on the first error) with a defined return code, and
+every header whose offsets disagree with the layout must be rejected.
+"""
+import os
+import shutil
+import struct
+import subprocess
+
+import numpy as np
+import pytest
+
+import fieldgen as F
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+NATIVE = os.path.join(ROOT, "tests", "native")
+SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g", "-O1"]
+ECAPACITY, ECORRUPT = -2, -3
+OFFSET_FIELDS = {"off_cb": 136, "off_ch": 144, "off_bs": 152, "off_hd": 160, "off_tl": 168, "total": 176}
+COUNT_FIELDS = {"n": 88, "n_unpred": 96, "huff_bits": 104, "tail_bits": 112, "n_chunks": 128}
+
+
+def _need(tool):
+    if shutil.which(tool) is None:
+        pytest.skip(f"{tool} not available")
+
+
+@pytest.fixture(scope="module")
+def drivers(tmp_path_factory):
+    _need("gcc")
+    _need("g++")
+    d = tmp_path_factory.mktemp("san")
+    hc = str(d / "header_check")
+    subprocess.run(["g++", "-std=c++17", *SAN, "-I", os.path.join(ROOT, "include"),
+                    os.path.join(NATIVE, "header_check.cpp"), "-o", hc], check=True)
+    od = str(d / "oracle_decompress")
+    subprocess.run(["gcc", "-std=c11", *SAN, "-ffp-contract=off", os.path.join(ROOT, "oracle", "szref.c"),
+                    os.path.join(NATIVE, "oracle_decompress.c"), "-o", od, "-lm"], check=True)
+    return d, hc, od
+
+
+def _run(exe, path):
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:exitcode=86",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1:exitcode=87")
+    env.pop("LD_PRELOAD", None)
+    r = subprocess.run([exe, path], capture_output=True, text=True, env=env, timeout=600)
+    assert r.returncode == 0, f"{os.path.basename(exe)} exited {r.returncode}:\n{r.stderr[-4000:]}"
+    assert "runtime error" not in r.stderr and "Sanitizer" not in r.stderr, r.stderr[-4000:]
+    return r.stdout.split("\n")
+
+
+def _containers(oracle):
+    """Small containers: the oracle decodes one bit at a time against every
+    symbol of the alphabet, so a corrupted header that passes its checks
+    costs a full decode."""
+    rng = np.random.default_rng(11)
+    x3 = F.smooth3d((8, 9, 10))
+    x3[3, 4, 5] = 40.0  # a few unpredictable values
+    x1 = np.cumsum(rng.normal(0, 1, 300)).astype(np.float64)
+    x1[::37] += 300.0
+    raw = rng.normal(0, 1, 300).astype(np.float32)
+    out = {
+        "3d_f32": oracle.compress(x3, layers=1, m=8, eb_mode="rel", eb_rel=1e-4)[0],
+        "2d_f32_l2": oracle.compress(F.climate2d((20, 30)), layers=2, m=0, eb_mode="rel", eb_rel=1e-3,
+                                     chunk=256)[0],
+        "1d_f64_m12": oracle.compress(x1, layers=3, m=12, eb_mode="abs", eb_abs=1e-3)[0],
+        "raw_f32": oracle.compress(raw, layers=1, m=8, eb_mode="abs", eb_abs=1e-30)[0],
+    }
+    assert out["raw_f32"][6] & 1  # raw fallback
+    assert not any(out[k][6] & 1 for k in ("3d_f32", "2d_f32_l2", "1d_f64_m12"))
+    return out
+
+
+def _put(hdr: bytearray, off: int, v: int):
+    hdr[off:off + 8] = struct.pack("<Q", v & (2 ** 64 - 1))
+
+
+def _header_cases(containers):
+    """(name, claimed size, header bytes, expected check code or None)."""
+    cases = []
+    for cname, buf in containers.items():
+        good = bytearray(buf[:192])
+        size = len(buf)
+        cases.append((f"{cname}:good", size, bytes(good), 0))
+        cases.append((f"{cname}:short", size - 1, bytes(good), ECORRUPT))
+        cases.append((f"{cname}:tiny", 100, bytes(good), ECORRUPT))
+        raw = bool(good[6] & 1)
+        fields = dict(OFFSET_FIELDS)
+        if not raw:
+            fields.update(COUNT_FIELDS)
+        for fname, off in fields.items():
+            if raw and fname != "total":
+                continue
+            v = struct.unpack("<Q", bytes(good[off:off + 8]))[0]
+            small = (v + 64, v - 4 if v >= 4 else v + 4)
+            for bad in (2 ** 64 - 1, 2 ** 64 - 8, 2 ** 64 - 64 + v % 64, 2 ** 63, v + 2 ** 62) + small:
+                h = bytearray(good)
+                _put(h, off, bad)
+                # a count may move within the alignment slack of its section
+                # (the kernels then reject the mismatch); offsets may not move
+                want = None if (fname in COUNT_FIELDS and bad in small) else ECORRUPT
+                cases.append((f"{cname}:{fname}={bad:#x}", size, bytes(h), want))
+        # one offset wrapped so that offset + section length lands inside the buffer
+        if not raw:
+            for fname in ("off_ch", "off_bs", "off_hd", "off_tl"):
+                h = bytearray(good)
+                _put(h, OFFSET_FIELDS[fname], 2 ** 64 - 256)
+                cases.append((f"{cname}:{fname}-wrapped", size, bytes(h), ECORRUPT))
+        # every single-bit flip of the header: any outcome but a crash
+        for pos in range(192):
+            for bit in range(8):
+                h = bytearray(good)
+                h[pos] ^= 1 << bit
+                cases.append((f"{cname}:flip{pos}.{bit}", size, bytes(h), None))
+    return cases
+
+
+def test_header_checks_under_sanitizers(drivers, oracle):
+    d, hc, _ = drivers
+    cases = _header_cases(_containers(oracle))
+    path = str(d / "headers.bin")
+    with open(path, "wb") as f:
+        for _, size, hdr, _ in cases:
+            f.write(struct.pack("<Q", size) + hdr)
+    lines = _run(hc, path)
+    assert len([ln for ln in lines if ln]) == len(cases)
+    for (name, _, _, want), line in zip(cases, lines):
+        a, b = map(int, line.split())
+        assert b in (0, ECORRUPT), (name, a, b)
+        if want is not None:
+            assert b == want, (name, a, b)
+        if name.split(":")[1].startswith("flip") and 136 <= int(name.split("flip")[1].split(".")[0]) < 184:
+            assert b == ECORRUPT, name  # offsets are fully determined by the counts
+
+
+def test_oracle_decompress_under_sanitizers(drivers, oracle):
+    d, _, od = drivers
+    containers = _containers(oracle)
+    rng = np.random.default_rng(5)
+    recs = []
+    for cname, buf in containers.items():
+        info = oracle.inspect(buf)
+        cap = int(np.prod(info["dims"])) * (4 if info["dtype"] == 0 else 8)
+        recs.append((f"{cname}:good", buf, cap, 0))
+        recs.append((f"{cname}:cap-1", buf, cap - 1, ECAPACITY))
+        for cut in (0, 100, 191, 192, len(buf) // 2, len(buf) - 1):
+            recs.append((f"{cname}:cut{cut}", buf[:cut], cap, ECORRUPT))
+        for _, _, hdr, want in _header_cases({cname: buf}):
+            recs.append((f"{cname}:hdr", hdr + buf[192:], cap, None))
+        for _ in range(200):
+            b = bytearray(buf)
+            pos = int(rng.integers(192, len(b)))
+            b[pos] ^= 1 << int(rng.integers(0, 8))
+            recs.append((f"{cname}:body{pos}", bytes(b), cap, None))
+    path = str(d / "containers.bin")
+    with open(path, "wb") as f:
+        for _, buf, cap, _ in recs:
+            f.write(struct.pack("<QQ", len(buf), cap) + buf)
+    lines = _run(od, path)
+    assert len([ln for ln in lines if ln]) == len(recs)
+    for (name, _, _, want), line in zip(recs, lines):
+        rc = int(line)
+        assert rc in (0, ECORRUPT, ECAPACITY), (name, rc)
+        if want is not None:
+            assert rc == want, (name, rc)
+
+
+def test_inspect_rejects_wrapped_offsets(oracle):
+    """The library's own sz_inspect applies the same checks (no GPU needed)."""
+    import paper_1706_03791_amd as Z
+    if not os.path.exists(Z.LIB_PATH):
+        pytest.skip("library not built")
+    buf = _containers(oracle)["3d_f32"]
+    rc, _, _ = Z.sz_inspect(buf[:192])
+    assert rc == 0
+    for fname, off in OFFSET_FIELDS.items():
+        for bad in (2 ** 64 - 256, 2 ** 64 - 1, 2 ** 63):
+            h = bytearray(buf[:192])
+            _put(h, off, bad)
+            rc, _, _ = Z.sz_inspect(bytes(h))
+            assert rc == Z.SZ_ECORRUPT, (fname, hex(bad))
