@@ -48,6 +48,7 @@ extern "C" {
 #define SZ_EHIP (-6)
 #define SZ_ESTALL (-7) /* internal dataflow wait exceeded its bound (a bug) */
 #define SZ_ETIMEDOUT (-8) /* sz_server_wait: the request did not finish in time */
+#define SZ_ESCRATCH (-9)  /* sz_compress_async_noalloc: workspace beyond its static scratch */
 
 typedef enum { SZ_F32 = 0, SZ_F64 = 1 } sz_dtype;
 
@@ -103,6 +104,24 @@ int sz_compress(sz_ctx* ctx, const sz_params* p, const void* d_in, void* d_out,
  * (int32).  `cap` must be >= sz_compress_bound(p). */
 int sz_compress_async(sz_ctx* ctx, const sz_params* p, const void* d_in, void* d_out,
                       size_t cap, uint64_t* d_out_size, int32_t* d_status, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * pipeline and the same bytes as sz_compress_async, with every piece of
+ * workspace (codes, tile boundary records, histograms, chunk tables, the
+ * device plan) taken from a static device array of
+ * SZ_NOALLOC_SCRATCH_BYTES that the library holds on each GPU until the
+ * process ends.  Nothing is allocated: no hipMalloc, hipFree or allocating
+ * library call.  The context only names the device (its own scratch is not
+ * used).  Fields whose workspace exceeds the static array fail with
+ * SZ_ESCRATCH before anything is enqueued; the 512^3 f32 field at m <= 8
+ * fits.  Every call on one GPU shares that GPU's array, and the array keeps
+ * the last call's contents (each call clears what it needs cleared), so
+ * calls whose executions overlap on one GPU race and must be serialised by
+ * the caller (one stream, or events). */
+#define SZ_NOALLOC_SCRATCH_BYTES (256u << 20)
+int sz_compress_async_noalloc(sz_ctx* ctx, const sz_params* p, const void* d_in, void* d_out,
+                              size_t cap, uint64_t* d_out_size, int32_t* d_status, void* stream);
 
 /* Read the parameters and statistics stored in a container header (host
  * memory, at least 192 bytes). */

@@ -17,12 +17,15 @@ LIB_PATH = os.path.join(HERE, "libszhip.so")
 
 SZ_OK, SZ_EINVAL, SZ_ECAPACITY, SZ_ECORRUPT, SZ_ENONFINITE, SZ_ENOMEM, SZ_EHIP, SZ_ESTALL = 0, -1, -2, -3, -4, -5, -6, -7
 SZ_ETIMEDOUT = -8
+SZ_ESCRATCH = -9
+SZ_NOALLOC_SCRATCH_BYTES = 256 << 20
 SZ_REQ_COMPRESS, SZ_REQ_DECOMPRESS = 0, 1
 SZ_F32, SZ_F64 = 0, 1
 SZ_EB_ABS, SZ_EB_REL, SZ_EB_ABS_AND_REL = 0, 1, 2
 HEADER_BYTES = 192
 
 EXPORTS = ("sz_ctx_create", "sz_ctx_destroy", "sz_compress_bound", "sz_compress", "sz_compress_async",
+           "sz_compress_async_noalloc",
            "sz_inspect", "sz_decompress", "sz_quantize", "sz_strerror", "sz_ctx_profile",
            "sz_ctx_profile_read", "sz_batch_create", "sz_batch_compress", "sz_batch_info",
            "sz_batch_destroy", "sz_server_create", "sz_server_submit", "sz_server_wait", "sz_server_stats",
@@ -107,6 +110,7 @@ def lib():
             L.sz_compress_bound.restype = C.c_size_t
             L.sz_compress.argtypes = [vp, P(SzParams), vp, vp, C.c_size_t, P(C.c_size_t), P(SzStats), vp]
             L.sz_compress_async.argtypes = [vp, P(SzParams), vp, vp, C.c_size_t, vp, vp, vp]
+            L.sz_compress_async_noalloc.argtypes = [vp, P(SzParams), vp, vp, C.c_size_t, vp, vp, vp]
             L.sz_inspect.argtypes = [vp, C.c_size_t, P(SzParams), P(SzStats)]
             L.sz_decompress.argtypes = [vp, vp, C.c_size_t, vp, C.c_size_t, vp]
             L.sz_quantize.argtypes = [vp, P(SzParams), vp, vp, vp, P(SzStats), vp]
@@ -172,6 +176,12 @@ def sz_compress_async(ctx, p: SzParams, d_in: int, d_out: int, cap: int, d_out_s
                       stream: int = 0) -> int:
     return lib().sz_compress_async(C.c_void_p(ctx), C.byref(p), C.c_void_p(d_in), C.c_void_p(d_out), cap,
                                    C.c_void_p(d_out_size), C.c_void_p(d_status), C.c_void_p(stream))
+
+
+def sz_compress_async_noalloc(ctx, p: SzParams, d_in: int, d_out: int, cap: int, d_out_size: int,
+                              d_status: int, stream: int = 0) -> int:
+    return lib().sz_compress_async_noalloc(C.c_void_p(ctx), C.byref(p), C.c_void_p(d_in), C.c_void_p(d_out), cap,
+                                           C.c_void_p(d_out_size), C.c_void_p(d_status), C.c_void_p(stream))
 
 
 def sz_inspect(header: bytes):

@@ -5,6 +5,38 @@
 
 using namespace szh;
 
+// ------------------------------------------------- static no-allocation scratch
+// Workspace of sz_compress_async_noalloc: a device array of fixed size in
+// the library's code object, so that entry point never allocates.  Every GPU
+// the library runs on holds its own copy until the process ends.  In host
+// code the name `scratch` is only a stand-in for the symbol: its device
+// address on each GPU comes from hipGetSymbolAddress, taken once per device
+// when the first context on that device is created, and only that address is
+// passed to kernels.
+constexpr size_t kPlanBytes = 256;
+static_assert(sizeof(DevPlan) <= kPlanBytes, "the plan must fit its slot of the static scratch");
+constexpr size_t kStaticScratch = (size_t)SZ_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kStaticScratch];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// With `device` current: the device address of its static scratch, looked up
+// once per device.
+void* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch[device] = ptr;
+  }
+  return g_scratch[device];
+}
+}  // namespace
+
 
 // =================================================================== C ABI
 extern "C" {
@@ -24,6 +56,14 @@ int sz_ctx_create(sz_ctx** out, int device) {
     (void)hipFree(c->plan);
     delete c;
     return SZ_ENOMEM;
+  }
+  c->scratch = scratch_address(device);
+  if (!c->scratch) {
+    (void)hipFree(c->plan);
+    (void)hipHostFree(c->h_plan);
+    (void)hipHostFree(c->h_hdr);
+    delete c;
+    return SZ_EHIP;
   }
   *out = c;
   return SZ_OK;
@@ -111,6 +151,31 @@ int sz_compress_async(sz_ctx* ctx, const sz_params* p, const void* d_in, void* d
   return hipGetLastError() == hipSuccess ? SZ_OK : SZ_EHIP;
 }
 
+int sz_compress_async_noalloc(sz_ctx* ctx, const sz_params* p, const void* d_in, void* d_out, size_t cap,
+                              uint64_t* d_out_size, int32_t* d_status, void* stream) {
+  if (!ctx || !ctx->scratch) return SZ_EINVAL;
+  Layout L;
+  int rc = resolve(p, L);
+  if (rc) return rc;
+  if (check_align(d_in) || check_align(d_out)) return SZ_EINVAL;
+  // the whole workspace comes from the static scratch, behind the plan
+  if (carve_comp(L, nullptr, nullptr) > kStaticScratch - kPlanBytes) return SZ_ESCRATCH;
+  if (hipSetDevice(ctx->device) != hipSuccess) return SZ_EHIP;
+  sz_ctx view;  // a context over the static scratch; owns nothing
+  view.device = ctx->device;
+  view.prof = false;
+  view.plan = (DevPlan*)ctx->scratch;
+  view.arena = (uint8_t*)ctx->scratch + kPlanBytes;
+  view.arena_size = kStaticScratch - kPlanBytes;
+  view.fixed_arena = true;
+  hipStream_t st = (hipStream_t)stream;
+  rc = L.dtype == SZ_F32 ? enqueue_compress_t<float>(&view, L, p, d_in, d_out, cap, st, false)
+                         : enqueue_compress_t<double>(&view, L, p, d_in, d_out, cap, st, false);
+  if (rc) return rc;
+  hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(64), 0, st, (const DevPlan*)view.plan, d_out_size, d_status);
+  return hipGetLastError() == hipSuccess ? SZ_OK : SZ_EHIP;
+}
+
 int sz_quantize(sz_ctx* ctx, const sz_params* p, const void* d_in, uint16_t* d_codes, void* d_xprime,
                 sz_stats* stats, void* stream) {
   if (!p || p->quant_bits < 1 || p->quant_bits > 16) return SZ_EINVAL;
@@ -193,6 +258,7 @@ const char* sz_strerror(int code) {
     case SZ_EHIP: return "HIP runtime error";
     case SZ_ESTALL: return "internal wavefront wait exceeded its bound";
     case SZ_ETIMEDOUT: return "request not finished within the timeout";
+    case SZ_ESCRATCH: return "field needs more workspace than the static no-allocation scratch holds";
   }
   return "unknown error";
 }

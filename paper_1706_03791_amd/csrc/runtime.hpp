@@ -42,6 +42,7 @@ struct sz_ctx {
   void* arena = nullptr;
   size_t arena_size = 0;
   bool fixed_arena = false;        // arena memory lent by someone else: never (re)allocated here
+  void* scratch = nullptr;         // this device's static scratch (no-allocation entry point)
   szh::DevPlan* plan = nullptr;    // device
   szh::DevPlan* h_plan = nullptr;  // pinned host mirror
   uint8_t* h_hdr = nullptr;   // pinned host header staging
