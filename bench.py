@@ -143,6 +143,8 @@ def roundtrip(Z, torch, x, kw, steps=3, warmup=1):
     S = x.numel() * x.element_size()
     tc, td = [], []
     for i in range(warmup + steps):
+        if i == warmup:
+            Z.sz_ctx_profile(ctx, True)
         t0 = time.perf_counter()
         rc, size, st = Z.sz_compress(ctx, p, x.data_ptr(), comp.data_ptr(), cap, st_)
         t1 = time.perf_counter()
@@ -155,11 +157,14 @@ def roundtrip(Z, torch, x, kw, steps=3, warmup=1):
         if i >= warmup:
             tc.append(t1 - t0)
             td.append(t2 - t1)
-    t_c, t_d = float(np.mean(tc)), float(np.mean(td))
+    prof = Z.sz_ctx_profile_read(ctx)
+    Z.sz_ctx_profile(ctx, False)
+    t_c, t_d = float(np.median(tc)), float(np.median(td))
     row = {"GBps": round(2 * S / (t_c + t_d) / 1e9, 3), "compress_GBps": round(S / t_c / 1e9, 3),
            "decompress_GBps": round(S / t_d / 1e9, 3), "compression_factor": round(S / size, 3),
            "bits_per_value": round(8.0 * size / x.numel(), 4), "hit_rate": round(st.hit_rate, 6),
-           "m_used": int(st.m_used)}
+           "m_used": int(st.m_used),
+           "stage_ms": {k: round(ms / calls, 4) for k, (ms, calls) in prof.items() if calls}}
     del comp
     return row, out, st
 

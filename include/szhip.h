@@ -56,7 +56,13 @@ typedef enum { SZ_F32 = 0, SZ_F64 = 1 } sz_dtype;
  * (eb_rel * (max - min)), or both (the smaller of the two applies). */
 typedef enum { SZ_EB_ABS = 0, SZ_EB_REL = 1, SZ_EB_ABS_AND_REL = 2 } sz_eb_mode;
 
+/* Parameters of one field (Sec. II states the problem: a d-dimensional
+ * floating-point array compressed under a user bound; Sec. III-A the layer
+ * count n; Sec. IV-A/IV-B the interval count 2^m and its adaptive choice). */
 typedef struct {
+  uint32_t struct_size; /* sizeof(sz_params), checked by every entry point that
+                           takes parameters (SZ_EINVAL on a mismatch): the ABI
+                           version of the caller's struct */
   uint32_t dtype;      /* sz_dtype */
   uint32_t ndim;       /* 1..3 */
   uint64_t dims[3];    /* C order, slowest first; dims[ndim-1] is contiguous
@@ -84,24 +90,45 @@ typedef struct {
 
 typedef struct sz_ctx sz_ctx;
 
-/* Create a context on HIP device `device`.  Returns SZ_OK and *ctx. */
+/* Create a context on HIP device `device`.  Returns SZ_OK and *ctx
+ * (SZ_EHIP for a bad device, SZ_ENOMEM if its small device plan cannot be
+ * allocated).  The context owns its scratch arena and device plan; it holds
+ * no caller memory.  Not a method of the paper: the state of the library. */
 int sz_ctx_create(sz_ctx** ctx, int device);
+/* Wait for the context's device, then free everything the context owns.
+ * NULL is a no-op.  The context must not be used afterwards. */
 void sz_ctx_destroy(sz_ctx* ctx);
 
-/* Worst-case container size: the 192-byte header plus the raw field (a
- * container never exceeds it: compression falls back to a raw copy). */
+/* Worst-case container size: the 192-byte header plus the raw field.  The
+ * paper does not say what happens when coding expands the data; here a
+ * container never exceeds the raw field plus its header, because
+ * compression falls back to a raw copy (a lossless verbatim store).  Returns
+ * 0 for invalid parameters. */
 size_t sz_compress_bound(const sz_params* p);
 
-/* Compress d_in (dims of p, dtype of p) into d_out (capacity `cap` bytes).
- * Synchronises `stream`; writes the container size to *out_size and, if
- * non-NULL, statistics to *stats.  SZ_ECAPACITY if cap < needed. */
+/* Compress d_in (dims of p, dtype of p, row-major with dims[ndim-1]
+ * contiguous) into the container d_out (capacity `cap` bytes), so that every
+ * decompressed value lies strictly within the bound of the original (Sec. II,
+ * Metric 1): range and bound resolution, then Algorithm 1 -- multilayer
+ * prediction from decompressed neighbours (Sec. III-A, Eq. predmodel),
+ * error-controlled quantization into 2^m codes (Sec. IV-A) with the adaptive
+ * choice of m when quant_bits is 0 (Sec. IV-B), unpredictable values by
+ * binary-representation reduction (Sec. IV-B), Huffman coding of the codes
+ * (Sec. IV-A).  Synchronises `stream`; writes the container size to
+ * *out_size and, if non-NULL, statistics to *stats.  Errors: SZ_EINVAL
+ * (parameters, alignment), SZ_ENONFINITE (relative bound on NaN/Inf),
+ * SZ_ECAPACITY (cap < container size; d_out contents undefined), SZ_ENOMEM,
+ * SZ_EHIP. */
 int sz_compress(sz_ctx* ctx, const sz_params* p, const void* d_in, void* d_out,
                 size_t cap, size_t* out_size, sz_stats* stats, void* stream);
 
-/* Same pipeline without any host synchronisation (capturable into a HIP
- * graph): the container size is written to device memory *d_out_size
- * (uint64), and a status word (SZ_OK or a negative code) to *d_status
- * (int32).  `cap` must be >= sz_compress_bound(p). */
+/* The pipeline of sz_compress (Sec. II, Algorithm 1) without any host
+ * synchronisation, so it can be captured into a HIP graph: the container size
+ * is written to device memory *d_out_size (uint64) and a status word (SZ_OK
+ * or a negative code: SZ_ECAPACITY, SZ_ENONFINITE) to *d_status (int32) when
+ * the stream reaches them.  The return value reports only what the host can
+ * see (parameters, alignment, allocation of the context's scratch, which
+ * happens on the first call of a size and must not happen under capture). */
 int sz_compress_async(sz_ctx* ctx, const sz_params* p, const void* d_in, void* d_out,
                       size_t cap, uint64_t* d_out_size, int32_t* d_status, void* stream);
 
@@ -124,11 +151,20 @@ int sz_compress_async_noalloc(sz_ctx* ctx, const sz_params* p, const void* d_in,
                               size_t cap, uint64_t* d_out_size, int32_t* d_status, void* stream);
 
 /* Read the parameters and statistics stored in a container header (host
- * memory, at least 192 bytes). */
+ * memory, n >= 192 bytes; the container format is this library's, not the
+ * paper's).  The header is fully checked first: every count within its
+ * bounds and every section offset equal to the layout the compressor writes;
+ * SZ_ECORRUPT otherwise.  No device work. */
 int sz_inspect(const void* h_hdr, size_t n, sz_params* p, sz_stats* stats);
 
 /* Decompress the container d_comp (comp_size bytes) into d_out (capacity
- * cap bytes).  Synchronises `stream` (it reads the header first). */
+ * cap bytes): Huffman decoding of the codes (Sec. IV-A), the stored
+ * unpredictable values (Sec. IV-B), and the reconstruction of every point
+ * from the same prediction the compressor made from decompressed neighbours
+ * (Sec. III-A, Eq. predmodel): x' = prediction + (code - 2^(m-1)) * 2eb.
+ * Synchronises `stream` (it reads and checks the header first).  Errors:
+ * SZ_ECORRUPT (header or content inconsistent), SZ_ECAPACITY (cap smaller
+ * than the field), SZ_EINVAL, SZ_ENOMEM, SZ_EHIP. */
 int sz_decompress(sz_ctx* ctx, const void* d_comp, size_t comp_size, void* d_out,
                   size_t cap, void* stream);
 
@@ -150,6 +186,15 @@ const char* sz_strerror(int code);
  * reconstruction sweep, code histogram (when it is a kernel of its own).
  * Returns the number of stages. */
 int sz_ctx_profile(sz_ctx* ctx, int enable);
+/* Schedule-invariance check (for tests; not needed by callers of the codec).
+ * Later calls on the context run their prediction and reconstruction sweeps
+ * (Algorithm 1's traversal, kept in the dependence order Sec. III-A fixes)
+ * with another schedule: `schedule` 0 = default tiles, 1 = row-per-thread
+ * tiles for every field; `claim_order` 0..2 = the order in which workgroups
+ * claim the tiles (0 = default; 1 = another dependence order within each
+ * block; 2 = that, with the independent blocks in reverse).  Every schedule
+ * must produce the same bytes.  SZ_EINVAL for values out of range. */
+int sz_ctx_debug_sweep(sz_ctx* ctx, int schedule, int claim_order);
 int sz_ctx_profile_read(sz_ctx* ctx, double* ms, uint64_t* calls, int n);
 
 /* ---------------------------------------------------------------- analysis
@@ -227,11 +272,13 @@ void sz_batch_destroy(sz_batch* batch);
  * admits submitted requests, in arrival order, as execution slots (one HIP
  * stream each) and HBM free up, so requests arriving while others run
  * overlap with them on the device.  Every request's workspace is carved from
- * one device pool of `hbm_budget` bytes allocated by sz_server_create:
- * admission is by workspace footprint and nothing is allocated while
- * serving.  A request that does not fit in the free pool lets later requests
- * pass for at most 50 ms, then admission waits for it; a request larger than
- * the whole pool fails with SZ_ENOMEM.  Results equal those of sz_compress /
+ * one device pool of `hbm_budget` bytes allocated by sz_server_create, and
+ * nothing is allocated while serving.  Admission is by HBM footprint: the
+ * request's input, its output capacity and its workspace all count against
+ * `hbm_budget` while it is in flight.  A request that does not fit in what is
+ * left lets later requests pass for at most 50 ms, then admission waits for
+ * it; a request whose footprint exceeds the whole budget fails with
+ * SZ_ENOMEM.  Results equal those of sz_compress /
  * sz_decompress on the same input.  Input and output buffers belong to the
  * client and must stay valid until sz_server_wait returns for the request. */
 #define SZ_REQ_COMPRESS 0
@@ -260,7 +307,7 @@ typedef struct {
 typedef struct {
   uint64_t submitted, admitted, completed;
   uint32_t in_flight, max_in_flight;
-  uint64_t pool_bytes, pool_peak_bytes;
+  uint64_t pool_bytes, pool_peak_bytes; /* the budget, and the peak footprint in flight */
   double clock_s;       /* the server clock now */
 } sz_server_stats_t;
 

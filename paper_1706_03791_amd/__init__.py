@@ -27,7 +27,7 @@ HEADER_BYTES = 192
 EXPORTS = ("sz_ctx_create", "sz_ctx_destroy", "sz_compress_bound", "sz_compress", "sz_compress_async",
            "sz_compress_async_noalloc",
            "sz_inspect", "sz_decompress", "sz_quantize", "sz_strerror", "sz_ctx_profile",
-           "sz_ctx_profile_read", "sz_batch_create", "sz_batch_compress", "sz_batch_info",
+           "sz_ctx_profile_read", "sz_ctx_debug_sweep", "sz_batch_create", "sz_batch_compress", "sz_batch_info",
            "sz_batch_destroy", "sz_server_create", "sz_server_submit", "sz_server_wait", "sz_server_stats",
            "sz_server_destroy", "sz_quality", "sz_layer_survey")
 STAGES = ("range", "sweep_compress", "codebook", "encode", "dectab", "decode", "unpred", "sweep_decompress",
@@ -35,7 +35,7 @@ STAGES = ("range", "sweep_compress", "codebook", "encode", "dectab", "decode", "
 
 
 class SzParams(C.Structure):
-    _fields_ = [("dtype", C.c_uint32), ("ndim", C.c_uint32), ("dims", C.c_uint64 * 3),
+    _fields_ = [("struct_size", C.c_uint32), ("dtype", C.c_uint32), ("ndim", C.c_uint32), ("dims", C.c_uint64 * 3),
                 ("block", C.c_uint64 * 3), ("layers", C.c_uint32), ("quant_bits", C.c_uint32),
                 ("eb_mode", C.c_uint32), ("chunk", C.c_uint32), ("eb_abs", C.c_double),
                 ("eb_rel", C.c_double), ("theta", C.c_double)]
@@ -118,6 +118,7 @@ def lib():
             L.sz_strerror.restype = C.c_char_p
             L.sz_ctx_profile.argtypes = [vp, C.c_int]
             L.sz_ctx_profile_read.argtypes = [vp, vp, vp, C.c_int]
+            L.sz_ctx_debug_sweep.argtypes = [vp, C.c_int, C.c_int]
             L.sz_batch_create.argtypes = [vp, C.c_uint32, P(SzParams), C.c_int, P(vp)]
             L.sz_batch_compress.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int, vp]
             L.sz_batch_info.argtypes = [vp, P(C.c_int), P(C.c_uint32), P(C.c_int), vp, C.c_int]
@@ -206,6 +207,10 @@ def sz_quantize(ctx, p: SzParams, d_in: int, d_codes: int, d_xprime: int = 0, st
 
 def sz_ctx_profile(ctx, enable: bool = True) -> int:
     return lib().sz_ctx_profile(C.c_void_p(ctx), int(enable))
+
+
+def sz_ctx_debug_sweep(ctx, schedule: int, claim_order: int) -> int:
+    return lib().sz_ctx_debug_sweep(C.c_void_p(ctx), int(schedule), int(claim_order))
 
 
 def sz_ctx_profile_read(ctx):
@@ -319,6 +324,7 @@ def context(device: int = 0) -> int:
 def make_params(shape, dtype="float32", layers=1, m=8, eb_mode="rel", eb_abs=0.0, eb_rel=0.0,
                 block=None, chunk=0, theta=0.0) -> SzParams:
     p = SzParams()
+    p.struct_size = C.sizeof(SzParams)
     p.dtype = SZ_F32 if str(dtype).endswith("float32") else SZ_F64
     p.ndim = len(shape)
     for d, s in enumerate(shape):

@@ -96,6 +96,13 @@ int sz_ctx_profile(sz_ctx* c, int enable) {
   return SZ_OK;
 }
 
+int sz_ctx_debug_sweep(sz_ctx* c, int schedule, int claim_order) {
+  if (!c || schedule < 0 || schedule > 1 || claim_order < 0 || claim_order > 2) return SZ_EINVAL;
+  c->dbg_sched = schedule;
+  c->dbg_claim = (uint32_t)claim_order;
+  return SZ_OK;
+}
+
 int sz_ctx_profile_read(sz_ctx* c, double* ms, uint64_t* calls, int n) {
   if (!c) return SZ_EINVAL;
   for (int i = 0; i < n && i < ST_COUNT; i++) {
@@ -114,7 +121,8 @@ size_t sz_compress_bound(const sz_params* p) {
 static int compress_common(sz_ctx* ctx, const sz_params* p, const void* d_in, void* d_out, size_t cap,
                            hipStream_t st, Layout& L, bool codes_only) {
   if (!ctx) return SZ_EINVAL;
-  int rc = resolve(p, L);
+  const Sched legacy = p ? default_sched((int)p->dtype, (int)p->ndim, (int)p->layers, true) : Sched{};
+  int rc = resolve(p, L, ctx->dbg_sched == 1 ? &legacy : nullptr);
   if (rc) return rc;
   if (check_align(d_in) || (!codes_only && check_align(d_out))) return SZ_EINVAL;
   if (hipSetDevice(ctx->device) != hipSuccess) return SZ_EHIP;
@@ -183,7 +191,9 @@ int sz_quantize(sz_ctx* ctx, const sz_params* p, const void* d_in, uint16_t* d_c
   q.quant_bits = 16;  // keep 16-bit codes in the intermediate array
   hipStream_t st = (hipStream_t)stream;
   Layout L;
-  int rc = resolve(&q, L);
+  if (!ctx) return SZ_EINVAL;
+  const Sched legacy = default_sched((int)p->dtype, (int)p->ndim, (int)p->layers, true);
+  int rc = resolve(&q, L, ctx->dbg_sched == 1 ? &legacy : nullptr);
   if (rc) return rc;
   if (!ctx || check_align(d_in) || check_align(d_codes)) return SZ_EINVAL;
   if (hipSetDevice(ctx->device) != hipSuccess) return SZ_EHIP;
@@ -238,7 +248,7 @@ int sz_decompress(sz_ctx* ctx, const void* d_comp, size_t comp_size, void* d_out
   HIPCHK(hipStreamSynchronize(st));
   Hdr h;
   Layout L;
-  int rc = prepare_decompress(ctx->h_hdr, comp_size, cap, h, L);
+  int rc = prepare_decompress(ctx->h_hdr, comp_size, cap, h, L, ctx->dbg_sched == 1);
   if (rc) return rc;
   if ((rc = enqueue_decompress_any(ctx, L, h, d_comp, d_out, st))) return rc;
   HIPCHK(hipMemcpyAsync(ctx->h_plan, ctx->plan, sizeof(DevPlan), hipMemcpyDeviceToHost, st));

@@ -58,4 +58,21 @@ struct Geom {
   int64_t n;
 };
 
+// Tile claimed with a ticket of a single-field sweep.  Tickets are taken in
+// a dependence order of the tiles, so every predecessor of a tile (the tiles
+// before it along z and y in its block) holds a smaller ticket.  Order 0 is
+// the tile numbering itself (blocks in order; z-tiles outer, y-tiles inner);
+// order 1 numbers the tiles of a block y-tiles outer, another dependence
+// order; order 2 also takes the blocks, which are independent, in reverse.
+// All orders give the same bytes (the schedule-invariance check of the tests).
+__device__ __forceinline__ int claim_tile(int ticket, uint32_t order, int tz_per_blk, int ty_per_blk, int ntiles) {
+  if (order == 0) return ticket;
+  const int per = tz_per_blk * ty_per_blk;
+  int bi = ticket / per;
+  const int q = ticket % per;
+  if (order == 2) bi = ntiles / per - 1 - bi;
+  const int tyt = q / tz_per_blk, tzt = q % tz_per_blk;
+  return bi * per + tzt * ty_per_blk + tyt;
+}
+
 }  // namespace szh

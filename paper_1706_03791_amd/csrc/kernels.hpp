@@ -384,29 +384,186 @@ __device__ void bitonic_sort_big(uint64_t* k, uint32_t n, uint64_t* buf, uint32_
   }
 }
 
+constexpr int kCbNT = 1024;
+constexpr int kCbNW = kCbNT / 64;
+constexpr uint32_t kCbLdsSyms = 2048;
+// Rounds of the parallel construction: the lightest available weight at
+// least doubles per round and all weights sum to N < 2^40, so 41 suffice.
+constexpr int kCbMaxRounds = 96;
+
+// Entries of the nondecreasing sequence get(lo .. hi-1) below x (LE: not
+// above x), by binary search.
+template <bool LE, typename G>
+__device__ __forceinline__ uint32_t cb_count(const G& get, uint32_t lo, uint32_t hi, uint64_t x) {
+  uint32_t l = lo, h = hi;
+  while (l < h) {
+    const uint32_t mid = (l + h) >> 1;
+    const uint64_t v = get(mid);
+    if (LE ? (v <= x) : (v < x))
+      l = mid + 1;
+    else
+      h = mid;
+  }
+  return l - lo;
+}
+
+// Stable LSD radix sort, by the frequency field, of n keys (frequency << 16
+// | symbol) given in symbol order, so they end in (frequency, symbol) order
+// in k.  One workgroup, 8-bit digits, as many passes as the largest
+// frequency needs.  Each wave owns a contiguous segment of the keys and
+// places them in order: a key's rank among the keys of its 64-key batch
+// with the same digit comes from eight ballots, and the last of them moves
+// the wave's offset for that digit on, so every pass keeps the order of
+// equal digits.
+__device__ void cb_radix_sort(uint64_t* k, uint64_t* tmp, uint32_t n, uint32_t* cnt, uint32_t* off,
+                              uint32_t* red, uint32_t* s_max) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  uint32_t mx = 0;
+  for (uint32_t i = tid; i < n; i += kCbNT) mx = max(mx, (uint32_t)(k[i] >> 16));
+  for (int o = 32; o >= 1; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
+  if (tid == 0) *s_max = 0;
+  __syncthreads();
+  if (lane == 0) atomicMax(s_max, mx);
+  __syncthreads();
+  const int nbits = 32 - __clz(*s_max | 1u);
+  const uint32_t seg = (n + kCbNW - 1) / kCbNW;
+  const uint32_t s0 = min(n, (uint32_t)w * seg), s1 = min(n, s0 + seg);
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  uint64_t* src = k;
+  uint64_t* dst = tmp;
+  for (int shift = 16; shift < 16 + nbits; shift += 8) {
+    for (int e = tid; e < kCbNW * 256; e += kCbNT) cnt[e] = 0;
+    __syncthreads();
+    for (uint32_t i = s0 + lane; i < s1; i += 64) atomicAdd(&cnt[w * 256 + ((src[i] >> shift) & 255)], 1u);
+    __syncthreads();
+    // exclusive scan in (digit, wave) order: element e = digit * kCbNW + wave
+    static_assert(kCbNW * 256 == 4 * kCbNT, "four scan elements per thread");
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int e = 4 * tid + q;
+      v[q] = cnt[(e % kCbNW) * 256 + e / kCbNW];
+      sum += v[q];
+    }
+    uint32_t base = block_exscan<kCbNT, uint32_t>(sum, red, nullptr);
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int e = 4 * tid + q;
+      off[(e % kCbNW) * 256 + e / kCbNW] = base;
+      base += v[q];
+    }
+    __syncthreads();
+    for (uint32_t i0 = s0; i0 < s1; i0 += 64) {
+      const uint32_t i = i0 + lane;
+      const bool ok = i < s1;
+      const uint64_t key = ok ? src[i] : 0ull;
+      const uint32_t d = (uint32_t)((key >> shift) & 255);
+      uint64_t peers = __ballot(ok);
+#pragma unroll
+      for (int b = 0; b < 8; b++) {
+        const uint64_t bb = __ballot(ok && ((d >> b) & 1u));
+        peers &= ((d >> b) & 1u) ? bb : ~bb;
+      }
+      if (ok) {
+        const uint32_t pos = off[w * 256 + d] + (uint32_t)__popcll(peers & below);
+        dst[pos] = key;
+        // the highest lane of each digit group moves the offset on
+        if ((peers >> lane) == 1ull) off[w * 256 + d] = pos + 1;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    uint64_t* t = src;
+    src = dst;
+    dst = t;
+  }
+  if (src != k) {
+    for (uint32_t i = tid; i < n; i += kCbNT) k[i] = src[i];
+    __syncthreads();
+  }
+}
+
+// Stable counting of items 0..n-1 by a code length (1..27; 0 = no item):
+// emit(i, base[len] + the number of earlier items of the same length).  One
+// workgroup of NT threads; each wave takes a contiguous segment of the
+// items, counts its lengths, and after a prefix over the waves ranks the
+// items of each 64-item batch among their equal lengths with five ballots.
+// `lc` is NT/64 x 32 words of LDS.
+template <int NT, typename G, typename E>
+__device__ __forceinline__ void rank_by_length(uint32_t n, const G& get_len, const uint32_t* base,
+                                               uint32_t (*lc)[32], const E& emit) {
+  constexpr int NWV = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int e = tid; e < NWV * 32; e += NT) (&lc[0][0])[e] = 0;
+  __syncthreads();
+  const uint32_t sg = (n + NWV - 1) / NWV;
+  const uint32_t g0 = min(n, (uint32_t)wv * sg), g1 = min(n, g0 + sg);
+  for (uint32_t q = g0 + lane; q < g1; q += 64) {
+    const uint32_t l = get_len(q);
+    if (l) atomicAdd(&lc[wv][l], 1u);
+  }
+  __syncthreads();
+  if (tid >= 1 && tid < 32) {
+    uint32_t c0 = base[tid];
+    for (int ww = 0; ww < NWV; ww++) {
+      const uint32_t cl = lc[ww][tid];
+      lc[ww][tid] = c0;
+      c0 += cl;
+    }
+  }
+  __syncthreads();
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (uint32_t q0 = g0; q0 < g1; q0 += 64) {
+    const uint32_t q = q0 + lane;
+    const uint32_t l = q < g1 ? get_len(q) : 0u;
+    uint64_t peers = __ballot(l != 0);
+#pragma unroll
+    for (int b = 0; b < 5; b++) {
+      const uint64_t bb = __ballot(l != 0 && ((l >> b) & 1u));
+      peers &= ((l >> b) & 1u) ? bb : ~bb;
+    }
+    if (l) {
+      const uint32_t r = lc[wv][l] + (uint32_t)__popcll(peers & below);
+      emit(q, r);
+      if ((peers >> lane) == 1ull) lc[wv][l] = r + 1;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+}
+
 // --------------------------------------------------- K4: Huffman codebook
 struct CodebookArgs {
   const uint32_t* hist;
   uint8_t* len;        // 2^m
   uint32_t* cw;        // 2^m
-  uint64_t* gkeys;     // 65536 (global sort scratch)
-  uint64_t* gw;        // 131072 (global merge scratch)
-  uint32_t* gpar;      // 131072
-  uint32_t* ganc;      // 2 x 131072
-  uint32_t* gdep;      // 2 x 131072
+  uint64_t* gkeys;     // 65536 (leaves)
+  uint64_t* gw;        // 131072 (sort buffer, then internal-node weights)
+  uint32_t* gpar;      // 131072 (parent of every node)
+  uint32_t* ganc;      // 262144 (merge-order weights of a round, as 131072 u64)
+  uint32_t* gdep;      // 262144 (merge-order node ids of a round; node depths)
   DevPlan* plan;
   uint64_t n;
   double theta;
 };
 
-constexpr int kCbNT = 1024;
-constexpr uint32_t kCbLdsSyms = 2048;
-
-// Code lengths by the two-queue construction over leaves sorted by
-// (frequency, symbol), the leaf queue winning ties; depths by pointer
-// jumping over the parent links; lengths above 27 are repaired by halving
-// every frequency (keeping it >= 1) and rebuilding.  Canonical codes follow
-// in (length, symbol) order.
+// Code lengths of the two-queue construction over the leaves sorted by
+// (frequency, symbol), the leaf queue winning ties (the oracle's definition),
+// computed in rounds rather than one merge at a time.  Both queues are
+// sorted and an internal node outweighs what it joins, so the order in
+// which the construction consumes nodes is the merge of the two queues, and
+// internal node c joins the nodes at places 2c and 2c + 1 of that order.
+// A round starts from the two lightest available nodes, whose sum t is the
+// weight of the next internal node; every node made from then on weighs at
+// least t and every available internal node weighs at most t, so all
+// available internal nodes and all leaves not heavier than t are consumed
+// first, in merge order (a leaf before an internal node of equal weight, an
+// older internal node before a newer one).  The round places those K nodes
+// by binary searches in the other queue, joins them pairwise into new
+// internal nodes and, when K is odd, joins the last with the first new node.
+// Depths follow top-down, round by round in reverse.  Lengths above 27 are
+// repaired by halving every frequency (keeping it >= 1) and rebuilding, as
+// the oracle does.  Canonical codes follow in (length, symbol) order.
 __device__ __forceinline__ void codebook_kernel_dev(CodebookArgs A) {
   DevPlan* P = A.plan;
   if (P->status) return;
@@ -414,204 +571,200 @@ __device__ __forceinline__ void codebook_kernel_dev(CodebookArgs A) {
   __shared__ uint64_t s_w[2 * kCbLdsSyms];
   __shared__ uint32_t s_par[2 * kCbLdsSyms];
   __shared__ uint32_t s_dep[2 * kCbLdsSyms];
-  __shared__ uint32_t s_par2[2 * kCbLdsSyms];
+  __shared__ uint32_t s_mid[2 * kCbLdsSyms];
   __shared__ uint32_t s_red[64];
-  __shared__ uint32_t s_cnt[32], s_first[32], s_start[32];
-  __shared__ uint32_t s_s, s_maxd;
+  __shared__ uint32_t s_rs[kCbMaxRounds + 1];
+  __shared__ uint32_t s_lc[kCbNW][32];
+  __shared__ uint64_t s_t;
+  __shared__ uint32_t s_a, s_b, s_c, s_nr, s_maxd, s_first[32];
 
   const uint32_t m = P->m;
   const uint32_t nsym = 1u << m;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 
-  // used symbols, compacted in symbol order
+  // used symbols, in symbol order
   const uint32_t per = (nsym + kCbNT - 1) / kCbNT;
   const uint32_t lo = min(nsym, tid * per), hi = min(nsym, lo + per);
   uint32_t cnt = 0;
   for (uint32_t q = lo; q < hi; q++) cnt += A.hist[q] != 0;
   uint32_t total;
-  uint32_t pos = block_exscan<kCbNT, uint32_t>(cnt, s_red, &total);
+  const uint32_t pos0 = block_exscan<kCbNT, uint32_t>(cnt, s_red, &total);
   const uint32_t s = total;
-  const bool in_lds = s <= kCbLdsSyms;
-  uint64_t* K = in_lds ? s_keys : A.gkeys;
-  uint64_t* W = in_lds ? s_w : A.gw;
-  uint32_t* PAR = in_lds ? s_par : A.gpar;
-  uint32_t np2 = 1;
-  while (np2 < s) np2 <<= 1;
-  for (uint32_t q = lo; q < hi; q++) {
-    const uint32_t f = A.hist[q];
-    if (f) K[pos++] = ((uint64_t)f << 16) | q;
-  }
-  for (uint32_t i = s + tid; i < np2; i += kCbNT) K[i] = ~0ull;
   for (uint32_t q = lo; q < hi; q++) A.len[q] = 0;
-  __syncthreads();
 
   if (s == 1) {
+    __syncthreads();
+    for (uint32_t q = lo; q < hi; q++)
+      if (A.hist[q]) {
+        A.len[q] = 1;
+        A.cw[q] = 1u << 27;
+      }
     if (tid == 0) {
-      const uint32_t sym = (uint32_t)(K[0] & 0xFFFF);
-      A.len[sym] = 1;
-      A.cw[sym] = 0;
       P->n_used = 1;
       P->max_len = 1;
     }
-  } else {
+  } else if (s > 1) {
     // The construction takes its arrays as arguments so that, called with
-    // the LDS arrays, every access compiles to LDS instructions (a pointer
-    // that may address LDS or global memory compiles to slower generic ones).
-    auto build = [&](uint64_t* K, uint64_t* W, uint32_t* PAR, uint32_t* ANC_a, uint32_t* ANC_b, uint32_t* DEP_a,
-                     uint32_t* DEP_b, bool lds) {
-      for (int attempt = 0; attempt < 64; attempt++) {
+    // the LDS arrays, every access compiles to LDS instructions.
+    auto build = [&](uint64_t* K, uint64_t* IW, uint64_t* MW, uint32_t* MID, uint32_t* PAR, uint32_t* DEP,
+                     bool lds) {
+      uint32_t np2 = 1;
+      while (np2 < s) np2 <<= 1;
+      for (int halvings = 0; halvings < 64; halvings++) {
+        // leaves with frequencies max(1, f >> halvings), in symbol order
+        {
+          uint32_t pos = pos0;
+          for (uint32_t q = lo; q < hi; q++) {
+            const uint32_t f = A.hist[q];
+            if (f) K[pos++] = ((uint64_t)max(1u, f >> min(halvings, 31)) << 16) | q;
+          }
+          if (lds)
+            for (uint32_t i = s + tid; i < np2; i += kCbNT) K[i] = ~0ull;
+          __syncthreads();
+        }
         if (lds)
           bitonic_sort<kCbNT>(K, np2);
         else
-          bitonic_sort_big<kCbNT>(K, np2, s_w, 2 * kCbLdsSyms);
+          cb_radix_sort(K, IW, s, s_mid, s_dep, s_red, &s_maxd);
+        // rounds
         if (tid == 0) {
-          // two-queue merge: leaves 0..s-1, internal nodes s..2s-2.  The next
-          // kLA weights of each queue live in registers and a weight is read
-          // kLA - 1 picks before it can be needed, so picks do not wait on
-          // memory.
-          constexpr uint64_t kInf = ~0ull;
-          constexpr uint32_t kLA = 4;
-          uint32_t i = 0, j = s, next = s;
-          uint64_t lw[kLA];  // leaves i .. i + kLA - 1 (kInf past s)
-          uint64_t nw[kLA];  // internal nodes j .. j + kLA - 1 (kInf at or past next)
-#pragma unroll
-          for (uint32_t q = 0; q < kLA; q++) {
-            lw[q] = q < s ? (K[q] >> 16) : kInf;
-            nw[q] = kInf;
-          }
-          for (uint32_t step = 0; step + 1 < s; step++) {
-            uint32_t pk[2];
-            uint64_t wk[2];
-#pragma unroll
+          s_a = 0;
+          s_b = 0;
+          s_c = 0;
+          s_nr = 0;
+        }
+        __syncthreads();
+        for (;;) {
+          const uint32_t a = s_a, b = s_b, c = s_c, nr = s_nr;
+          if ((s - a) + (c - b) <= 1 || nr >= (uint32_t)kCbMaxRounds) break;
+          if (tid == 0) {
+            // the two lightest available nodes, in merge order
+            uint32_t i = a, j = b;
+            uint64_t t = 0;
             for (int q = 0; q < 2; q++) {
-              if (i < s && (j >= next || lw[0] <= nw[0])) {
-                pk[q] = i;
-                wk[q] = lw[0];
-                i++;
-#pragma unroll
-                for (uint32_t r = 0; r + 1 < kLA; r++) lw[r] = lw[r + 1];
-                lw[kLA - 1] = (i + kLA - 1 < s) ? (K[i + kLA - 1] >> 16) : kInf;
-              } else {
-                pk[q] = j;
-                wk[q] = nw[0];
-                j++;
-#pragma unroll
-                for (uint32_t r = 0; r + 1 < kLA; r++) nw[r] = nw[r + 1];
-                nw[kLA - 1] = (j + kLA - 1 < next) ? W[j + kLA - 1] : kInf;
-              }
+              if (i < s && (j >= c || (K[i] >> 16) <= IW[j]))
+                t += K[i++] >> 16;
+              else
+                t += IW[j++];
             }
-            const uint64_t wsum = wk[0] + wk[1];
-            W[next] = wsum;
-            PAR[pk[0]] = next;
-            PAR[pk[1]] = next;
-            // the new node enters the register window when it is one of the
-            // next kLA internal nodes
-            const uint32_t d = next - j;
-#pragma unroll
-            for (uint32_t r = 0; r < kLA; r++)
-              if (d == r) nw[r] = wsum;
-            next++;
-          }
-          PAR[2 * s - 2] = 2 * s - 2;
-        }
-        __syncthreads();
-        // depths by pointer jumping (double-buffered ancestor/depth arrays)
-        const uint32_t nn = 2 * s - 1;
-        uint32_t *ANC = ANC_a, *DEP = DEP_a, *ANC2 = ANC_b, *DEP2 = DEP_b;
-        for (uint32_t v = tid; v < nn; v += kCbNT) {
-          ANC[v] = PAR[v];
-          DEP[v] = (v == nn - 1) ? 0u : 1u;
-        }
-        __syncthreads();
-        for (uint32_t span = 1; span < nn; span <<= 1) {
-          // 4 nodes per thread at a time, so their loads overlap
-          for (uint32_t v0 = tid; v0 < nn; v0 += 4 * kCbNT) {
-            uint32_t a[4], d[4];
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-              const uint32_t v = v0 + u * kCbNT;
-              a[u] = v < nn ? ANC[v] : 0u;
-              d[u] = v < nn ? DEP[v] : 0u;
-            }
-            uint32_t da[4], aa[4];
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-              da[u] = DEP[a[u]];
-              aa[u] = ANC[a[u]];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-              const uint32_t v = v0 + u * kCbNT;
-              if (v < nn) {
-                DEP2[v] = d[u] + da[u];
-                ANC2[v] = aa[u];
-              }
-            }
+            s_t = t;
+            s_rs[nr] = c;
           }
           __syncthreads();
-          uint32_t* t0 = ANC; ANC = ANC2; ANC2 = t0;
-          uint32_t* t1 = DEP; DEP = DEP2; DEP2 = t1;
+          const uint64_t t = s_t;
+          // leaves of weight <= t (a prefix of the remaining leaves)
+          uint32_t kl = 0;
+          for (uint32_t base = a; base < s; base += kCbNT) {
+            const uint32_t i = base + tid;
+            const int cntc = __syncthreads_count(i < s && (K[i] >> 16) <= t);
+            kl += (uint32_t)cntc;
+            if (cntc < kCbNT) break;
+          }
+          const uint32_t kk = kl + (c - b);
+          // merge places: a leaf after the internal nodes lighter than it; an
+          // internal node after the leaves not heavier than it
+          for (uint32_t i = a + tid; i < a + kl; i += kCbNT) {
+            const uint64_t f = K[i] >> 16;
+            const uint32_t p = (i - a) + cb_count<false>([&](uint32_t x) { return IW[x]; }, b, c, f);
+            MW[p] = f;
+            MID[p] = i;
+          }
+          for (uint32_t j = b + tid; j < c; j += kCbNT) {
+            const uint64_t wj = IW[j];
+            const uint32_t p = (j - b) + cb_count<true>([&](uint32_t x) { return K[x] >> 16; }, a, a + kl, wj);
+            MW[p] = wj;
+            MID[p] = s + j;
+          }
+          __syncthreads();
+          const uint32_t npair = kk / 2;
+          for (uint32_t q = tid; q < npair; q += kCbNT) {
+            IW[c + q] = MW[2 * q] + MW[2 * q + 1];
+            PAR[MID[2 * q]] = s + c + q;
+            PAR[MID[2 * q + 1]] = s + c + q;
+          }
+          if ((kk & 1) && tid == 0) {
+            // the last node joins the first new one, the lightest left
+            IW[c + npair] = MW[kk - 1] + (MW[0] + MW[1]);
+            PAR[MID[kk - 1]] = s + c + npair;
+            PAR[s + c] = s + c + npair;
+          }
+          __syncthreads();
+          if (tid == 0) {
+            s_a = a + kl;
+            s_b = c + (kk & 1);
+            s_c = c + npair + (kk & 1);
+            s_nr = nr + 1;
+          }
+          __syncthreads();
+        }
+        const uint32_t nr = s_nr, cend = s_c;
+        if (nr >= (uint32_t)kCbMaxRounds) {
+          if (tid == 0) set_status(P, SZ_EINVAL);
+          return;
+        }
+        // depths, top-down: the root, then the rounds in reverse; within a
+        // round only its first node can hang below its last
+        if (tid == 0) {
+          s_rs[nr] = cend;
+          DEP[s + cend - 1] = 0;
+        }
+        __syncthreads();
+        for (int r = (int)nr - 1; r >= 0; r--) {
+          const uint32_t r0 = s_rs[r], r1 = s_rs[r + 1];
+          if (tid == 0 && r1 - 1 != cend - 1) DEP[s + r1 - 1] = DEP[PAR[s + r1 - 1]] + 1;
+          __syncthreads();
+          for (uint32_t v = r0 + tid; v + 1 < r1; v += kCbNT) DEP[s + v] = DEP[PAR[s + v]] + 1;
+          __syncthreads();
         }
         uint32_t md = 0;
-        for (uint32_t v = tid; v < s; v += kCbNT) md = max(md, DEP[v]);
+        for (uint32_t i = tid; i < s; i += kCbNT) {
+          const uint32_t d = DEP[PAR[i]] + 1;
+          DEP[i] = d;
+          md = max(md, d);
+        }
         for (int o = 32; o >= 1; o >>= 1) md = max(md, (uint32_t)__shfl_xor(md, o, 64));
         if (tid == 0) s_maxd = 0;
         __syncthreads();
-        if ((tid & 63) == 0) atomicMax(&s_maxd, md);
+        if (lane == 0) atomicMax(&s_maxd, md);
         __syncthreads();
         const uint32_t maxd = s_maxd;
         if (maxd <= (uint32_t)kLmax) {
-          for (uint32_t v = tid; v < s; v += kCbNT) A.len[K[v] & 0xFFFF] = (uint8_t)DEP[v];
+          for (uint32_t i = tid; i < s; i += kCbNT) A.len[K[i] & 0xFFFF] = (uint8_t)DEP[i];
           if (tid == 0) {
             P->n_used = s;
             P->max_len = maxd;
           }
-          __syncthreads();
           break;
-        }
-        // halve frequencies, keep >= 1
-        for (uint32_t v = tid; v < s; v += kCbNT) {
-          uint64_t f = K[v] >> 16;
-          f >>= 1;
-          if (!f) f = 1;
-          K[v] = (f << 16) | (K[v] & 0xFFFF);
         }
         __syncthreads();
       }
-      // canonical codes: sort used symbols by (length, symbol)
-      if (tid < 32) s_cnt[tid] = 0;
-      __syncthreads();
-      for (uint32_t v = tid; v < s; v += kCbNT) {
-        const uint32_t sym = (uint32_t)(K[v] & 0xFFFF);
-        const uint32_t l = A.len[sym];
-        K[v] = ((uint64_t)l << 16) | sym;
-        atomicAdd(&s_cnt[l], 1u);
-      }
-      __syncthreads();
-      if (tid == 0) {
-        uint32_t code = 0, start = 0;
-        for (int l = 1; l <= kLmax; l++) {
-          s_first[l] = code;
-          s_start[l] = start;
-          code = (code + s_cnt[l]) << 1;
-          start += s_cnt[l];
-        }
-      }
-      if (lds)
-        bitonic_sort<kCbNT>(K, np2);
-      else
-        bitonic_sort_big<kCbNT>(K, np2, s_w, 2 * kCbLdsSyms);
-      for (uint32_t v = tid; v < s; v += kCbNT) {
-        const uint32_t sym = (uint32_t)(K[v] & 0xFFFF);
-        const uint32_t l = (uint32_t)(K[v] >> 16);
-        A.cw[sym] = s_first[l] + (v - s_start[l]);
-      }
     };
-    if (in_lds)
-      // merge weights are no longer needed once the depths are computed
-      build(s_keys, s_w, s_par, (uint32_t*)s_w, (uint32_t*)s_w + 2 * kCbLdsSyms, s_dep, s_par2, true);
+    if (s <= kCbLdsSyms)
+      build(s_keys, s_w, s_w + kCbLdsSyms, s_mid, s_par, s_dep, true);
     else
-      build(A.gkeys, A.gw, A.gpar, A.ganc, A.ganc + 131072, A.gdep, A.gdep + 131072, false);
+      build(A.gkeys, A.gw, (uint64_t*)A.ganc, A.gdep, A.gpar, A.gdep + 131072, false);
+    __syncthreads();
+    // canonical codes in (length, symbol) order: the first code of each
+    // length, then each symbol's rank among the symbols of its length
+    if (tid < 32) s_first[tid] = 0;
+    __syncthreads();
+    for (uint32_t q = tid; q < nsym; q += kCbNT) {
+      const uint32_t l = A.len[q];
+      if (l) atomicAdd(&s_first[l], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t code = 0;
+      for (int l = 1; l <= kLmax; l++) {
+        const uint32_t cl = s_first[l];
+        s_first[l] = code;
+        code = (code + cl) << 1;
+      }
+    }
+    __syncthreads();
+    rank_by_length<kCbNT>(
+        nsym, [&](uint32_t q) { return (uint32_t)A.len[q]; }, s_first, s_lc,
+        [&](uint32_t q, uint32_t code) { A.cw[q] = ((uint32_t)A.len[q] << 27) | code; });
   }
   if (tid == 0) {
     const double hr = 1.0 - (double)A.hist[0] / (double)A.n;
@@ -809,6 +962,92 @@ __global__ void __launch_bounds__(1024) hist_kernel(const CT* __restrict__ codes
 }
 
 
+// Histogram of 2-byte codes (m > 8) without global atomics: the bins are
+// split into two halves of 32768, and each half is counted by blocks of its
+// own (blockIdx.y) holding the whole half in LDS (128 KiB, dynamic), so
+// every code lands in an LDS bin of exactly one block.  The zero and centre
+// codes, the most frequent ones, are counted in registers.  Each block
+// stores its row of counts with plain stores; hist2_reduce_kernel adds the
+// rows of every bin in a fixed order.
+constexpr uint32_t kHist2Half = 32768;
+constexpr uint32_t kHist2MaxBlocks = 256;  // blocks per half
+__host__ __device__ constexpr uint32_t hist2_blocks(uint64_t n) {
+  return (uint32_t)(n / 65536 + 1 < kHist2MaxBlocks ? n / 65536 + 1 : kHist2MaxBlocks);
+}
+__global__ void __launch_bounds__(1024) hist2_kernel(const uint16_t* __restrict__ codes, uint64_t n,
+                                                     uint32_t* __restrict__ hpart, const DevPlan* P,
+                                                     uint32_t pass2) {
+  extern __shared__ uint32_t h2[];
+  if (P->status) return;
+  if (pass2 && !P->rerun) return;
+  const uint32_t m = P->m;
+  const uint32_t nb = 1u << m, center = 1u << (m - 1);
+  const uint32_t lo = blockIdx.y * kHist2Half;
+  const uint32_t W = nb > lo ? min(nb - lo, kHist2Half) : 0u;
+  uint32_t* row = hpart + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * kHist2Half;
+  if (W == 0) return;  // this half holds no bins at this m
+  for (uint32_t i = threadIdx.x; i < W; i += 1024) h2[i] = 0;
+  __syncthreads();
+  uint32_t c_center = 0, c_zero = 0;
+  auto count = [&](uint32_t code) {
+    if (code == center) {
+      c_center++;
+    } else if (code == 0) {
+      c_zero++;
+    } else {
+      const uint32_t w = code - lo;
+      if (w < W) atomicAdd(&h2[w], 1u);
+    }
+  };
+  auto count_vec = [&](const uint4 raw) {
+    const uint32_t wd[4] = {raw.x, raw.y, raw.z, raw.w};
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      count(wd[e] & 0xFFFFu);
+      count(wd[e] >> 16);
+    }
+  };
+  constexpr int U = 4;  // 16-byte loads in flight per thread
+  const uint64_t nv = n / 8;
+  const uint64_t stride = (uint64_t)gridDim.x * 1024;
+  uint64_t v = (uint64_t)blockIdx.x * 1024 + threadIdx.x;
+  for (; v + (U - 1) * stride < nv; v += U * stride) {
+    uint4 raw[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) raw[u] = ((const uint4*)codes)[v + u * stride];
+#pragma unroll
+    for (int u = 0; u < U; u++) count_vec(raw[u]);
+  }
+  for (; v < nv; v += stride) count_vec(((const uint4*)codes)[v]);
+  for (uint64_t i = nv * 8 + (uint64_t)blockIdx.x * 1024 + threadIdx.x; i < n; i += stride) count(codes[i]);
+  c_center = wave_sum(c_center);
+  c_zero = wave_sum(c_zero);
+  if ((threadIdx.x & 63) == 0) {
+    if (c_center && center - lo < W) atomicAdd(&h2[center - lo], c_center);
+    if (c_zero && lo == 0) atomicAdd(&h2[0], c_zero);
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < W; i += 1024) row[i] = h2[i];
+}
+// Bin b of the 2-byte histogram: the rows of its half added in order.
+__global__ void __launch_bounds__(256) hist2_reduce_kernel(const uint32_t* __restrict__ hpart, uint32_t rows,
+                                                           uint32_t* hist, const DevPlan* P, uint32_t pass2) {
+  if (P->status) return;
+  if (pass2 && !P->rerun) return;
+  const uint32_t nb = 1u << P->m;
+  const uint32_t b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= 65536) return;
+  if (b >= nb) {
+    hist[b] = 0;
+    return;
+  }
+  const uint32_t half = b / kHist2Half, w = b % kHist2Half;
+  const uint32_t* col = hpart + (size_t)half * rows * kHist2Half + w;
+  uint32_t t = 0;
+  for (uint32_t r = 0; r < rows; r++) t += col[(size_t)r * kHist2Half];
+  hist[b] = t;
+}
+
 // Four consecutive codes starting at i (a multiple of 4), as one 4- or
 // 8-byte load; codes at or past n read as 0.
 template <typename CT>
@@ -885,7 +1124,63 @@ __device__ __forceinline__ uint32_t code_entry(uint32_t s, const uint32_t* s_tab
   if constexpr (LT)
     return s_tab[s];
   else
-    return ((uint32_t)len[s] << 27) | (cw ? cw[s] : 0u);
+    return cw ? cw[s] : ((uint32_t)len[s] << 27);  // cw holds len << 27 | code
+}
+
+// Bit fields appended MSB-first to a stream from bit `pos` on, gathered in a
+// 64-bit register: words wholly inside the writer's range get plain stores;
+// its first and last words, which it may share with the neighbouring ranges,
+// are ORed in (the stream starts zeroed).
+struct BitWriter {
+  uint32_t* words;
+  uint64_t aw, w_first;
+  int used;
+  bool any;  // a field was put: a writer that wrote nothing touches no word
+  uint64_t acc;
+  __device__ __forceinline__ BitWriter(uint32_t* w, uint64_t pos)
+      : words(w), aw(pos >> 5), w_first(pos >> 5), used((int)(pos & 31)), any(false), acc(0) {}
+  // nb <= 32 bits of val
+  __device__ __forceinline__ void put(uint32_t val, int nb) {
+    if (nb <= 0) return;
+    any = true;
+    acc |= (uint64_t)val << (64 - used - nb);  // used < 32, nb <= 32: inside 64 bits
+    used += nb;
+    if (used >= 32) {
+      const uint32_t word = (uint32_t)(acc >> 32);
+      if (aw == w_first)
+        atomicOr(&words[aw], word);
+      else
+        words[aw] = word;
+      aw++;
+      acc <<= 32;
+      used -= 32;
+    }
+  }
+  __device__ __forceinline__ void finish() {
+    if (any && used > 0) atomicOr(&words[aw], (uint32_t)(acc >> 32));
+  }
+};
+
+// Four consecutive values x[i .. i+3] (i a multiple of 4: 16-byte aligned);
+// at the end of the field (i + 4 > n) only the values below n are read.
+template <typename T>
+__device__ __forceinline__ void load4(const T* __restrict__ x, uint64_t i, uint64_t n, T (&v)[4]) {
+  if (i + 4 > n) {
+#pragma unroll
+    for (int k = 0; k < 4; k++) v[k] = i + k < n ? x[i + k] : T(0);
+  } else if constexpr (sizeof(T) == 4) {
+    const uint4 u = *(const uint4*)(x + i);
+    v[0] = __builtin_bit_cast(float, u.x);
+    v[1] = __builtin_bit_cast(float, u.y);
+    v[2] = __builtin_bit_cast(float, u.z);
+    v[3] = __builtin_bit_cast(float, u.w);
+  } else {
+    const uint4 a = *(const uint4*)(x + i), b = *(const uint4*)(x + i + 2);
+    v[0] = __builtin_bit_cast(double, ((uint64_t)a.y << 32) | a.x);
+    v[1] = __builtin_bit_cast(double, ((uint64_t)a.w << 32) | a.z);
+    v[2] = __builtin_bit_cast(double, ((uint64_t)b.y << 32) | b.x);
+    v[3] = __builtin_bit_cast(double, ((uint64_t)b.w << 32) | b.z);
+  }
 }
 
 template <typename T, typename CT, bool LT>
@@ -905,12 +1200,24 @@ __device__ __forceinline__ void chunk_stats_body(const CT* __restrict__ codes, c
       const uint4 v = ((const uint4*)(codes + c * C))[lane];
       const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-      for (int k = 0; k < 16; k++) {
-        const uint32_t sym = (wv[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-        b += code_entry<LT>(sym, s_tab, len, nullptr) >> 27;
-        if (sym == 0) {
-          z++;
-          tb += (uint32_t)kept_bits<T>(x[c * C + k0 + k], ebb);
+      for (int g = 0; g < 4; g++) {
+        bool anyz = false;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          const uint32_t sym = (wv[g] >> (8 * k)) & 0xFFu;
+          b += code_entry<LT>(sym, s_tab, len, nullptr) >> 27;
+          anyz |= sym == 0;
+        }
+        if (anyz) {
+          // unpredictable values come four at a time (16-byte aligned loads)
+          T xv[4];
+          load4<T>(x, c * C + k0 + 4 * g, n, xv);
+#pragma unroll
+          for (int k = 0; k < 4; k++)
+            if (((wv[g] >> (8 * k)) & 0xFFu) == 0) {
+              z++;
+              tb += (uint32_t)kept_bits<T>(xv[k], ebb);
+            }
         }
       }
     } else {
@@ -918,14 +1225,22 @@ __device__ __forceinline__ void chunk_stats_body(const CT* __restrict__ codes, c
       for (uint32_t j = 0; j < per; j += 4) {
         uint32_t sym[4];
         lds_code4<CT>(sc, k0 + j, sym);
+        bool anyz = false;
 #pragma unroll
         for (int k = 0; k < 4; k++) {
           const bool real = k0 + j + k < cnt;
           b += real ? (code_entry<LT>(sym[k], s_tab, len, nullptr) >> 27) : 0u;
-          if (real && sym[k] == 0) {
-            z++;
-            tb += (uint32_t)kept_bits<T>(x[c * C + k0 + j + k], ebb);
-          }
+          anyz |= real && sym[k] == 0;
+        }
+        if (anyz) {
+          T xv[4];
+          load4<T>(x, c * C + k0 + j, n, xv);
+#pragma unroll
+          for (int k = 0; k < 4; k++)
+            if (k0 + j + k < cnt && sym[k] == 0) {
+              z++;
+              tb += (uint32_t)kept_bits<T>(xv[k], ebb);
+            }
         }
       }
     }
@@ -1125,68 +1440,70 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
     for (uint32_t w = lane; w < nw; w += 64) words[w] = 0;
     const uint32_t cnt = stage_codes<CT>(codes, n, c, C, sc, lane);
     const uint32_t k0 = (uint32_t)lane * per;
-    const uint64_t i0 = c * C + k0;
+    const uint64_t i0 = c * C + k0;  // a multiple of 4
     uint32_t mybits = 0, myz = 0, mytb = 0;
     for (uint32_t j = 0; j < per; j += 4) {
       uint32_t sym[4];
       lds_code4<CT>(sc, k0 + j, sym);
+      bool anyz = false;
 #pragma unroll
       for (int k = 0; k < 4; k++) {
         const bool real = k0 + j + k < cnt;
         mybits += real ? (code_entry<LT>(sym[k], s_tab, len, cw) >> 27) : 0u;
-        if (real && sym[k] == 0) {
-          myz++;
-          mytb += (uint32_t)kept_bits<T>(x[i0 + j + k], ebb);
-        }
+        anyz |= real && sym[k] == 0;
+      }
+      if (anyz) {
+        // unpredictable values come four at a time (16-byte aligned loads)
+        T xv[4];
+        load4<T>(x, i0 + j, n, xv);
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+          if (k0 + j + k < cnt && sym[k] == 0) {
+            myz++;
+            mytb += (uint32_t)kept_bits<T>(xv[k], ebb);
+          }
       }
     }
-    uint64_t bpos = (b0 & 31) + wave_exscan(mybits);
-    uint64_t zpos = uoff[c] + wave_exscan(myz);
-    uint64_t tpos = toff[c] + wave_exscan(mytb);
+    const uint64_t bpos = (b0 & 31) + wave_exscan(mybits);
+    const uint64_t zpos = uoff[c] + wave_exscan(myz);
+    const uint64_t tpos = toff[c] + wave_exscan(mytb);
     __builtin_amdgcn_wave_barrier();
-    // The lane's bits gather left-aligned in a 64-bit register from bit
-    // (bpos % 32) of word bpos / 32 on.  Words wholly inside the lane's range
-    // get plain stores; its first and last words, which it may share with the
-    // neighbouring lanes, are ORed in.
-    uint32_t aw = (uint32_t)(bpos >> 5);  // word the accumulator starts at
-    const uint32_t w_first = aw;
-    int used = (int)(bpos & 31);          // bits of that word before the lane's own
-    uint64_t acc = 0;
+    // codes into the wave's LDS words; heads and tails of unpredictable
+    // values straight into their streams
+    BitWriter wb(words, bpos), wh(hd, zpos * HB), wt(tl, tpos);
     for (uint32_t j = 0; j < per; j += 4) {
       uint32_t sym[4];
       lds_code4<CT>(sc, k0 + j, sym);
+      bool anyz = false;
 #pragma unroll
       for (int k = 0; k < 4; k++) {
         if (k0 + j + k >= cnt) break;
-        const uint32_t code = sym[k];
-        const uint32_t e = code_entry<LT>(code, s_tab, len, cw);
-        const int l = (int)(e >> 27);
-        const uint32_t v = e & 0x07FFFFFFu;
-        acc |= (uint64_t)v << (64 - used - l);  // used < 32 and l <= 27: inside 64 bits
-        used += l;
-        if (used >= 32) {
-          const uint32_t word = (uint32_t)(acc >> 32);
-          if (aw == w_first)
-            atomicOr(&words[aw], word);
-          else
-            words[aw] = word;
-          aw++;
-          acc <<= 32;
-          used -= 32;
-        }
-        bpos += l;
-        if (code == 0) {
-          const T xi = x[i0 + j + k];
-          const U ub = to_bits<T>(truncate_unpred<T>(xi, ebb));
-          const int r = kept_bits<T>(xi, ebb);
-          or_bits(hd, zpos * HB, (uint64_t)(ub >> MANT), HB);
-          if (r > 0) or_bits(tl, tpos, (uint64_t)((ub & ((((U)1) << MANT) - 1)) >> (MANT - r)), r);
-          zpos++;
-          tpos += r;
+        const uint32_t e = code_entry<LT>(sym[k], s_tab, len, cw);
+        wb.put(e & 0x07FFFFFFu, (int)(e >> 27));
+        anyz |= sym[k] == 0;
+      }
+      if (anyz) {
+        T xv[4];
+        load4<T>(x, i0 + j, n, xv);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          if (k0 + j + k >= cnt || sym[k] != 0) continue;
+          const U ub = to_bits<T>(truncate_unpred<T>(xv[k], ebb));
+          const int r = kept_bits<T>(xv[k], ebb);
+          wh.put((uint32_t)(ub >> MANT), HB);
+          const U tail = (ub & ((((U)1) << MANT) - 1)) >> (MANT - r);  // the top r mantissa bits
+          if (r > 32) {
+            wt.put((uint32_t)((uint64_t)tail >> 32), r - 32);
+            wt.put((uint32_t)tail, 32);
+          } else {
+            wt.put((uint32_t)tail, r);
+          }
         }
       }
     }
-    if (used > 0) atomicOr(&words[aw], (uint32_t)(acc >> 32));
+    wb.finish();
+    wh.finish();
+    wt.finish();
     __builtin_amdgcn_wave_barrier();
     const uint64_t gw0 = b0 >> 5;
     const uint64_t bend = b0 + nb;
@@ -1219,7 +1536,7 @@ __device__ __forceinline__ void encode_kernel_dev(const CT* __restrict__ codes, 
   const uint32_t nsym = 1u << P->m;
   const bool lt = nsym <= kTab;
   if (lt)
-    for (uint32_t i = threadIdx.x; i < nsym; i += kEncNT) s_tab[i] = ((uint32_t)len[i] << 27) | cw[i];
+    for (uint32_t i = threadIdx.x; i < nsym; i += kEncNT) s_tab[i] = cw[i];  // len << 27 | code
   __syncthreads();
   const int wv = threadIdx.x >> 6;
   uint32_t* words = (uint32_t*)s_dyn + (size_t)wv * enc_words_per_wave(C);
@@ -1381,6 +1698,7 @@ __global__ void __launch_bounds__(1024) dectab_kernel(const uint8_t* comp, uint6
   __shared__ uint64_t s_keys[4096];
   __shared__ uint32_t s_lut[4096];  // the single-code table, built here and copied out once
   __shared__ uint32_t s_cnt[32], s_first[32], s_start[32];
+  __shared__ uint32_t s_lc[16][32];
   __shared__ int s_bad;
   const int tid = threadIdx.x;
   if (tid == 0) s_bad = 0;
@@ -1408,10 +1726,7 @@ __global__ void __launch_bounds__(1024) dectab_kernel(const uint8_t* comp, uint6
           const uint8_t* pb = b - 3;
           if ((uint32_t)(pb[0] | (pb[1] << 8)) >= sym) s_bad = 1;
         }
-        K[e] = ((uint64_t)l << 16) | sym;
         if (l >= 1 && l <= kLmax) atomicAdd(&s_cnt[l], 1u);
-      } else {
-        K[e] = ~0ull;
       }
     }
     __syncthreads();
@@ -1440,11 +1755,16 @@ __global__ void __launch_bounds__(1024) dectab_kernel(const uint8_t* comp, uint6
       if (tid == 0) set_status(P, SZ_ECORRUPT);
       return;
     }
-    if (lds)
-      bitonic_sort<1024>(K, np2);
-    else
-      bitonic_sort_big<1024>(K, np2, s_keys, 4096);
-    for (uint32_t v = tid; v < n_used; v += 1024) sorted_syms[v] = (uint32_t)(K[v] & 0xFFFF);
+    // the used symbols in (length, symbol) order: the section is in symbol
+    // order, so each goes to the start of its length plus its rank there
+    rank_by_length<1024>(
+        n_used, [&](uint32_t e) { return (uint32_t)comp[off_cb + 3ull * e + 2]; }, s_start, s_lc,
+        [&](uint32_t e, uint32_t pos) {
+          const uint8_t* b = comp + off_cb + 3ull * e;
+          const uint32_t sym = b[0] | (b[1] << 8);
+          K[pos] = ((uint64_t)b[2] << 16) | sym;
+          sorted_syms[pos] = sym;
+        });
     // Codes of length l <= kLutBits own the windows [end_{l-1}, end_l), with
     // end_l = (first_l + count_l) << (kLutBits - l): a canonical code's ranges
     // follow each other as l grows.  Each window takes the smallest l whose

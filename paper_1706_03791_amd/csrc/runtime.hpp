@@ -43,6 +43,8 @@ struct sz_ctx {
   size_t arena_size = 0;
   bool fixed_arena = false;        // arena memory lent by someone else: never (re)allocated here
   void* scratch = nullptr;         // this device's static scratch (no-allocation entry point)
+  int dbg_sched = 0;               // sz_ctx_debug_sweep: 1 = row-per-thread tiles for every field
+  uint32_t dbg_claim = 0;          // sz_ctx_debug_sweep: tile claim order
   szh::DevPlan* plan = nullptr;    // device
   szh::DevPlan* h_plan = nullptr;  // pinned host mirror
   uint8_t* h_hdr = nullptr;   // pinned host header staging
@@ -113,11 +115,7 @@ struct Sched {
   int nw, az;  // wave tile
 };
 
-inline Sched default_sched(int dtype, int ndim, int nl) {
-  static const bool legacy = [] {
-    const char* e = std::getenv("SZHIP_LEGACY_SWEEP");
-    return e && e[0] == '1';
-  }();
+inline Sched default_sched(int dtype, int ndim, int nl, bool legacy = false) {
   Sched s;
   tile_shape(dtype, ndim, s.rz, s.ry);
   s.wave = (ndim == 3 || ndim == 2) && nl == 1 && !legacy;
@@ -127,7 +125,7 @@ inline Sched default_sched(int dtype, int ndim, int nl) {
 }
 
 int resolve(const sz_params* p, Layout& L, const Sched* sched_override = nullptr) {
-  if (!p) return SZ_EINVAL;
+  if (!p || p->struct_size != sizeof(sz_params)) return SZ_EINVAL;
   if (p->dtype > 1 || p->ndim < 1 || p->ndim > 3) return SZ_EINVAL;
   if (p->layers < 1 || p->layers > 4 || p->quant_bits > 16 || p->eb_mode > 2) return SZ_EINVAL;
   if (p->chunk != 0 && (p->chunk < 256 || p->chunk > (uint32_t)kMaxChunk || p->chunk % 256)) return SZ_EINVAL;
@@ -275,7 +273,8 @@ size_t carve_comp(const Layout& L, uint8_t* base, CompWs* W, bool keep_values = 
   w.xs = keep_values ? c.take<uint8_t>(L.n * L.ts) : nullptr;
   w.xchg = c.take<uint8_t>(L.xchg_bytes + 512);
   w.hist = c.take<uint32_t>(65536 * 4);
-  w.hpart = L.cw == 1 ? c.take<uint32_t>(kHistBlocks * 256 * 4) : nullptr;
+  w.hpart = L.cw == 1 ? c.take<uint32_t>(kHistBlocks * 256 * 4)
+                       : c.take<uint32_t>((size_t)2 * hist2_blocks((uint64_t)L.n) * kHist2Half * 4);
   w.progress = c.take<uint32_t>((L.g.ntiles + 1) * 4);
   w.ticket = w.progress + L.g.ntiles;
   w.cbits = c.take<uint32_t>(L.n_chunks * 4);
@@ -379,6 +378,17 @@ void launch_hist(const Layout& L, const void* codes, uint32_t* hist, uint32_t* h
                        pass2);
     return;
   }
+  if (L.cw == 2 && hpart) {
+    // two halves of 32768 bins, each block with its half in LDS, then the rows
+    const uint32_t nb = hist2_blocks((uint64_t)L.n);
+    const int lds = (int)(kHist2Half * 4);
+    (void)hipFuncSetAttribute((const void*)hist2_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipLaunchKernelGGL(hist2_kernel, dim3(nb, 2), dim3(1024), lds, st, (const uint16_t*)codes, (uint64_t)L.n, hpart,
+                       P, pass2);
+    hipLaunchKernelGGL(hist2_reduce_kernel, dim3(65536 / 256), dim3(256), 0, st, (const uint32_t*)hpart, nb, hist,
+                       P, pass2);
+    return;
+  }
   const uint64_t g = std::min<uint64_t>(ceil_div((uint64_t)L.n, 1024 * 16), 1024);
   if (L.cw == 1)
     hipLaunchKernelGGL(hist_kernel<uint8_t>, dim3((unsigned)g), dim3(1024), 0, st, (const uint8_t*)codes,
@@ -468,11 +478,13 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
   a.plan = P;
   a.pass2 = 0;
   a.export_all = debug_codes_only ? 1 : 0;
+  a.claim = ctx->dbg_claim;
   stage_begin(ctx, ST_SWEEP_C, st);
   int sweep_stage_open = ST_SWEEP_C;
   if (L.wave) {
     WArgs wa = make_wargs(L, d_in, W.codes, W.xs, W.xchg, W.progress, W.ticket, P);
     wa.export_all = a.export_all;
+    wa.claim = ctx->dbg_claim;
     if ((rc = launch_wsweep(L, true, wa, st))) return rc;
     if (!adaptive) {
       // the sweep alone is timed; the histogram has a stage of its own
@@ -609,6 +621,7 @@ void fill_stats(const DevPlan& P, const Layout& L, sz_stats* s) {
 // -------------------------------------------------------------- decompress
 void hdr_params(const Hdr& h, sz_params* p) {
   std::memset(p, 0, sizeof *p);
+  p->struct_size = sizeof(sz_params);
   p->dtype = h.dtype;
   p->ndim = h.ndim;
   for (uint32_t d = 0; d < h.ndim && d < 3; d++) {
@@ -745,8 +758,10 @@ int enqueue_decompress_t(sz_ctx* ctx, const Layout& L, const Hdr& h, const void*
   a.plan = P;
   a.pass2 = 0;
   a.export_all = 0;
+  a.claim = ctx->dbg_claim;
   if (L.wave) {
     WArgs wa = make_wargs(L, nullptr, W.codes, d_out, W.xchg, W.progress, W.ticket, P);
+    wa.claim = ctx->dbg_claim;
     wa.uvals = W.uvals;
     wa.useg = W.useg;
     wa.n_unpred = U;
@@ -774,14 +789,16 @@ __global__ void raw_unpack_kernel(const uint8_t* comp, uint8_t* out, uint64_t by
 // Header checks of a container (host copy of its first kHdr bytes) against
 // its size and the output capacity; fills the header and the layout the
 // decompressor uses.
-int prepare_decompress(const uint8_t* hdr, size_t comp_size, size_t cap, Hdr& h, Layout& L) {
+int prepare_decompress(const uint8_t* hdr, size_t comp_size, size_t cap, Hdr& h, Layout& L,
+                       bool legacy_sweep = false) {
   int rc = parse_header(hdr, comp_size, h);
   if (rc) return rc;
   if ((rc = check_sections(h))) return rc;
   sz_params p;
   hdr_params(h, &p);
   p.quant_bits = (h.flags & 1) ? 0 : h.m;  // intermediate code width follows the stored m
-  if (resolve(&p, L)) return SZ_ECORRUPT;
+  const Sched sched = default_sched((int)h.dtype, (int)h.ndim, (int)h.layers, legacy_sweep);
+  if (resolve(&p, L, &sched)) return SZ_ECORRUPT;
   for (uint32_t d = 0; d < h.ndim; d++)
     if (h.block[d] != L.out_block[d]) return SZ_ECORRUPT;
   if ((uint64_t)L.n != h.n) return SZ_ECORRUPT;

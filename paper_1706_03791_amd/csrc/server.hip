@@ -7,8 +7,10 @@
 // that arrive while others are on the GPU overlap with them on the device.
 // Workspaces (codes, exchange rows, histograms, code tables, scan arrays)
 // are carved from one device pool allocated at start-up, whose size is the
-// HBM budget: admission is by workspace footprint, and nothing is allocated
-// while serving.  Requests are admitted in arrival order; a request that does
+// HBM budget, and nothing is allocated while serving.  Admission is by HBM
+// footprint: a request's input, its output capacity and its workspace all
+// count against the budget while it is in flight (the client owns the first
+// two, the pool holds the third).  Requests are admitted in arrival order; a request that does
 // not fit in the free pool lets later, smaller requests pass for a bounded
 // time (then admission waits for it).  Each result is the same as that of a
 // single sz_compress / sz_decompress call: a request runs the same kernel
@@ -86,6 +88,7 @@ struct Req {
   Layout L{};
   Hdr h{};
   size_t fp = 0, off = 0;
+  size_t fp_total = 0;  // fp + input bytes + output capacity
   int slot = -1;
 };
 
@@ -119,6 +122,7 @@ struct sz_server {
   uint64_t n_done = 0, n_admitted = 0;
   uint32_t max_inflight = 0, inflight = 0;
   size_t pool_peak = 0;
+  size_t accounted = 0;  // fp_total of the requests in flight
   double backfill_s = 0.05;
 };
 
@@ -133,6 +137,7 @@ int prepare(sz_server* s, Req* q) {
     int rc = resolve(&r.params, q->L);
     if (rc) return rc;
     q->fp = carve_comp(q->L, nullptr, nullptr);
+    q->fp_total = q->fp + (size_t)q->L.n * q->L.ts + r.out_cap;
     return SZ_OK;
   }
   if (r.op != SZ_REQ_DECOMPRESS) return SZ_EINVAL;
@@ -147,6 +152,7 @@ int prepare(sz_server* s, Req* q) {
   int rc = prepare_decompress(hdr, r.in_bytes, r.out_cap, q->h, q->L);
   if (rc) return rc;
   q->fp = dec_footprint(q->L, q->h);
+  q->fp_total = q->fp + r.in_bytes + r.out_cap;
   return SZ_OK;
 }
 
@@ -198,6 +204,7 @@ void scheduler(sz_server* s) {
       const DevPlan& P = *sl.ctx.h_plan;
       const uint64_t size = q->r.op == SZ_REQ_COMPRESS ? P.total : (uint64_t)q->L.n * q->L.ts;
       if (q->fp) s->pool.release(q->off, q->fp);
+      s->accounted -= q->fp_total;
       sl.req = nullptr;
       sl.ctx.arena = nullptr;
       sl.ctx.arena_size = 0;
@@ -224,7 +231,7 @@ void scheduler(sz_server* s) {
       if (!q->prepared) {
         const int rc = prepare(s, q);
         q->prepared = true;
-        if (!rc && q->fp > s->budget) {
+        if (!rc && q->fp_total > s->budget) {
           it = s->pending.erase(it);
           finish(s, q, SZ_ENOMEM, 0);
           progress = true;
@@ -241,17 +248,19 @@ void scheduler(sz_server* s) {
         // behind a blocked request: only while it has not waited too long
         if (t - s->pending.front()->t_submit > s->backfill_s) break;
       }
-      const size_t off = q->fp ? s->pool.alloc(q->fp) : 0;
-      {
-        std::lock_guard<std::mutex> g(s->mu);
-        s->pool_peak = s->pool.peak;
-      }
+      const bool fits = s->accounted + q->fp_total <= s->budget;
+      const size_t off = !fits ? Pool::kNone : (q->fp ? s->pool.alloc(q->fp) : 0);
       if (off == Pool::kNone) {
         head_blocked = true;
         ++it;
         continue;
       }
       q->off = off;
+      s->accounted += q->fp_total;
+      {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->pool_peak = std::max(s->pool_peak, s->accounted);
+      }
       Slot& sl = s->slots[(size_t)free_slot];
       sl.req = q;
       q->slot = free_slot;
@@ -268,6 +277,7 @@ void scheduler(sz_server* s) {
         // nothing usable was enqueued: release at once
         (void)hipStreamSynchronize(sl.st);
         if (q->fp) s->pool.release(q->off, q->fp);
+        s->accounted -= q->fp_total;
         sl.req = nullptr;
         {
           std::lock_guard<std::mutex> g(s->mu);

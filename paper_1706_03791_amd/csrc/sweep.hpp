@@ -138,6 +138,7 @@ struct SweepArgs {
   DevPlan* plan;
   uint32_t pass2;         // adaptive-m second sweep: skip unless plan->rerun
   uint32_t export_all;    // compress debug: store every recorded value to xo
+  uint32_t claim = 0;     // tile claim order of the single-field launch (claim_tile)
 };
 
 constexpr uint32_t kDone = 0xFFFFFFFFu;
@@ -700,7 +701,8 @@ __global__ void __launch_bounds__(RZ * RY) sweep_kernel(SweepArgs A) {
   extern __shared__ __align__(16) uint8_t sz_lds[];
   __shared__ int s_tile;
   if (A.plan->status != 0 || (A.pass2 && !A.plan->rerun)) return;
-  if (threadIdx.x == 0) s_tile = (int)atomicAdd(A.ticket, 1u);
+  if (threadIdx.x == 0)
+    s_tile = claim_tile((int)atomicAdd(A.ticket, 1u), A.claim, A.g.tz_per_blk, A.g.ty_per_blk, A.g.ntiles);
   __syncthreads();
   sweep_body<T, CT, DIM, NL, COMP, RZ, RY>(A, s_tile, sz_lds);
 }

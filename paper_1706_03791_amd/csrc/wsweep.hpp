@@ -64,6 +64,7 @@ struct WArgs {
   DevPlan* plan;
   uint32_t pass2;
   uint32_t export_all;
+  uint32_t claim = 0;  // tile claim order of the single-field launch (claim_tile)
 };
 
 // Lane l takes lane l-1's value; lane 0 takes `old` (wave_shr:1).
@@ -1037,7 +1038,7 @@ wsweep_kernel(WArgs A) {
   extern __shared__ __align__(16) uint8_t sz_lds[];
   __shared__ int s_tile;
   if (A.plan->status != 0 || (A.pass2 && !A.plan->rerun)) return;
-  if (threadIdx.x == 0) s_tile = (int)atomicAdd(A.ticket, 1u);
+  if (threadIdx.x == 0) s_tile = claim_tile((int)atomicAdd(A.ticket, 1u), A.claim, A.tz_per_blk, A.ty_per_blk, A.ntiles);
   __syncthreads();
   wsweep_body<T, CT, COMP, NW, AZ, DBG>(A, s_tile, sz_lds);
 }

@@ -92,3 +92,16 @@ def test_header_declares_citations():
         text = f.read()
     for needle in ("Sec. III-A", "Sec. IV-A", "Sec. IV-B", "Algorithm 1", "Metric 1"):
         assert needle in text
+
+
+def test_struct_size_checked(Z):
+    p = Z.make_params((100, 100), "float32", layers=1, m=8, eb_mode="rel", eb_rel=1e-4)
+    assert Z.sz_compress_bound(p) == 192 + 100 * 100 * 4
+    p.struct_size = p.struct_size - 8  # a caller built against another layout
+    assert Z.sz_compress_bound(p) == 0
+    p.struct_size = 0
+    assert Z.sz_compress_bound(p) == 0
+
+
+def test_debug_sweep_argument_checks(Z):
+    assert Z.sz_ctx_debug_sweep(0, 0, 0) == Z.SZ_EINVAL

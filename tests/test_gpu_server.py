@@ -129,3 +129,20 @@ def test_server_errors(Z):
     rc, _ = Z.sz_server_wait(srv.handle, 987654, 10)
     assert rc == Z.SZ_EINVAL
     srv.close()
+    # the footprint counts input and output as well as the workspace: a 1D
+    # field whose workspace alone fits the budget but whose input, output
+    # capacity and workspace together do not is refused
+    srv = Z.Server(hbm_budget=16 << 20, slots=2)
+    w = dev(np.cumsum(np.random.default_rng(72).normal(0, 1, 1 << 20)).astype(np.float32))
+    ob = torch.zeros(Z.sz_compress_bound(Z.make_params(tuple(w.shape), w.dtype, m=8, eb_mode="rel", eb_rel=1e-4)),
+                     dtype=torch.uint8, device="cuda")
+    rid = srv.submit_compress(w, ob, m=8, eb_mode="rel", eb_rel=1e-4)
+    res = srv.wait(rid, 60000)
+    assert res["status"] == 0 and res["workspace_bytes"] < (16 << 20) - 8 * (1 << 20)
+    w2 = dev(np.cumsum(np.random.default_rng(73).normal(0, 1, 3 << 20)).astype(np.float32))
+    ob2 = torch.zeros(Z.sz_compress_bound(Z.make_params(tuple(w2.shape), w2.dtype, m=8, eb_mode="rel",
+                                                        eb_rel=1e-4)), dtype=torch.uint8, device="cuda")
+    rid = srv.submit_compress(w2, ob2, m=8, eb_mode="rel", eb_rel=1e-4)
+    res = srv.wait(rid, 60000)
+    assert res["status"] == Z.SZ_ENOMEM and res["workspace_bytes"] < (16 << 20)
+    srv.close()
