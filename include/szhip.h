@@ -77,6 +77,13 @@ typedef struct {
   double eb_abs;       /* absolute bound (>= 0) */
   double eb_rel;       /* value-range-relative bound (>= 0) */
   double theta;        /* hit-rate threshold of the adaptive rule, 0 = 0.9 */
+  uint32_t unpred_coding; /* storage of unpredictable values (Sec. IV-B, Algorithm 1):
+                             0 = binary-representation reduction: sign and
+                             exponent, then the kept mantissa bits of each value;
+                             1 = the same reduced values, each XORed with the
+                             previous one of its decode chunk, storing the count
+                             of identical leading bytes and the bits after them */
+  uint32_t reserved;   /* 0 */
 } sz_params;
 
 typedef struct {

@@ -44,7 +44,8 @@ class Params(C.Structure):
                 ("dims", C.c_uint64 * 3), ("block", C.c_uint64 * 3),
                 ("layers", C.c_uint32), ("quant_bits", C.c_uint32),
                 ("eb_mode", C.c_uint32), ("chunk", C.c_uint32),
-                ("eb_abs", C.c_double), ("eb_rel", C.c_double), ("theta", C.c_double)]
+                ("eb_abs", C.c_double), ("eb_rel", C.c_double), ("theta", C.c_double),
+                ("unpred_coding", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class Stats(C.Structure):
@@ -100,7 +101,7 @@ class OracleError(RuntimeError):
 
 
 def make_params(shape, dtype=np.float32, layers=1, m=8, eb_mode="abs", eb_abs=0.0,
-                eb_rel=0.0, block=None, chunk=0, theta=0.0) -> Params:
+                eb_rel=0.0, block=None, chunk=0, theta=0.0, unpred_coding=0) -> Params:
     p = Params()
     p.dtype = 0 if np.dtype(dtype) == np.float32 else 1
     p.ndim = len(shape)
@@ -116,6 +117,7 @@ def make_params(shape, dtype=np.float32, layers=1, m=8, eb_mode="abs", eb_abs=0.
     p.eb_abs = eb_abs
     p.eb_rel = eb_rel
     p.theta = theta
+    p.unpred_coding = unpred_coding
     return p
 
 
@@ -227,5 +229,5 @@ def inspect(buf: bytes) -> dict:
     d.update(dtype=p.dtype, ndim=p.ndim, dims=[p.dims[i] for i in range(p.ndim)],
              block=[p.block[i] for i in range(p.ndim)], layers=p.layers,
              quant_bits=p.quant_bits, eb_mode=p.eb_mode, chunk=p.chunk,
-             eb_abs=p.eb_abs, eb_rel=p.eb_rel)
+             eb_abs=p.eb_abs, eb_rel=p.eb_rel, unpred_coding=p.unpred_coding)
     return d

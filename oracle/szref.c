@@ -244,6 +244,7 @@ static int check_params(const szref_params* p) {
   if (p->eb_mode > 2) return SZREF_EINVAL;
   if (p->chunk != 0 && (p->chunk < 256 || p->chunk > 4096 || p->chunk % 256)) return SZREF_EINVAL;
   if (p->theta < 0 || p->theta > 1 || p->theta != p->theta) return SZREF_EINVAL;
+  if (p->unpred_coding > 1) return SZREF_EINVAL;
   return SZREF_OK;
 }
 
@@ -445,6 +446,7 @@ static int read_hdr(const uint8_t* b, size_t size, struct hdr* h) {
   h->off_tl = get_u64(b + 168);
   h->total = get_u64(b + 176);
   if (h->dtype > 1 || h->ndim < 1 || h->ndim > 3 || h->layers < 1 || h->layers > 4) return SZREF_ECORRUPT;
+  if (h->flags > 3 || h->flags == 3) return SZREF_ECORRUPT; /* raw copy, or the XOR coding of unpredictable values */
   if (h->total > size) return SZREF_ECORRUPT;
   return SZREF_OK;
 }
@@ -479,6 +481,7 @@ static int compress_impl(const szref_params* p, const void* data, uint8_t** out,
 
   struct bitwriter bs = {0}, hd = {0}, tl = {0};
   uint32_t* chunk_bits = NULL;
+  uint32_t* uchunk = NULL;
   uint8_t* len = NULL;
   uint32_t* cw = NULL;
   uint16_t* codes = (uint16_t*)malloc(n * 2);
@@ -523,14 +526,26 @@ static int compress_impl(const szref_params* p, const void* data, uint8_t** out,
     bw_put(&bs, cw[codes[i]], len[codes[i]]);
     chunk_bits[i / C] += (uint32_t)(bs.nbits - before);
   }
-  if (p->dtype == 0) pack_unpred_f32(codes, (const float*)xp, n, (uint32_t)E.ebT_bits, &hd, &tl);
-  else pack_unpred_f64(codes, (const double*)xp, n, E.ebT_bits, &hd, &tl);
+  const int xor_coding = p->unpred_coding == 1;
+  if (xor_coding) {
+    /* records in the tails section, their per-chunk bit counts in the heads section */
+    uchunk = (uint32_t*)calloc(n_chunks, 4);
+    if (!uchunk) { rc = SZREF_ENOMEM; goto done; }
+    if (p->dtype == 0) pack_unpred_xor_f32(codes, (const float*)xp, n, C, (uint32_t)E.ebT_bits, &tl, uchunk);
+    else pack_unpred_xor_f64(codes, (const double*)xp, n, C, E.ebT_bits, &tl, uchunk);
+    for (uint64_t c = 0; c < n_chunks; c++) bw_put(&hd, uchunk[c], 32);
+  } else if (p->dtype == 0) {
+    pack_unpred_f32(codes, (const float*)xp, n, (uint32_t)E.ebT_bits, &hd, &tl);
+  } else {
+    pack_unpred_f64(codes, (const double*)xp, n, E.ebT_bits, &hd, &tl);
+  }
 
   uint32_t n_used = 0;
   for (uint32_t q = 0; q < nsym; q++) if (len[q]) n_used++;
 
   struct hdr h;
   memset(&h, 0, sizeof h);
+  h.flags = xor_coding ? 2 : 0;
   h.dtype = p->dtype; h.ndim = p->ndim; h.layers = p->layers; h.m = m;
   h.eb_mode = p->eb_mode; h.m_req = p->quant_bits;
   for (int d = 0; d < 3; d++) { h.dims[d] = 1; h.block[d] = 1; }
@@ -599,6 +614,7 @@ static int compress_impl(const szref_params* p, const void* data, uint8_t** out,
   rc = SZREF_OK;
 done:
   free(chunk_bits);
+  free(uchunk);
   free(bs.words); free(hd.words); free(tl.words);
   free(codes); free(xp); free(hist); free(len); free(cw);
   return rc;
@@ -622,6 +638,7 @@ int szref_inspect(const uint8_t* comp, size_t size, szref_params* p, szref_stats
     memset(p, 0, sizeof *p);
     p->dtype = h.dtype; p->ndim = h.ndim; p->layers = h.layers; p->quant_bits = h.m_req;
     p->eb_mode = h.eb_mode; p->chunk = h.chunk; p->eb_abs = h.eb_abs; p->eb_rel = h.eb_rel;
+    p->unpred_coding = (h.flags >> 1) & 1;
     for (uint32_t d = 0; d < h.ndim; d++) { p->dims[d] = h.dims[d]; p->block[d] = h.block[d]; }
   }
   if (s) {
@@ -665,12 +682,16 @@ int szref_decompress(const uint8_t* comp, size_t size, void* out, size_t cap) {
   /* Section bounds.  The counts are bounded first so that no section
    * length below can wrap around, and each check is written so that a huge
    * offset cannot wrap either. */
-  if (h.n_used > nsym || h.n_unpred > n || h.huff_bits > n * LMAX ||
-      h.tail_bits > h.n_unpred * (h.dtype ? 52 : 23))
+  /* With the XOR coding (flag bit 1) the heads section holds one u32 bit
+   * count per chunk and a record takes at most LZB + W bits. */
+  const int xor_coding = (h.flags & 2) != 0;
+  const uint64_t head_bits = xor_coding ? 32ull * h.n_chunks : h.n_unpred * (h.dtype ? 12 : 9);
+  const uint64_t max_tail = xor_coding ? (h.dtype ? 3 + 64 : 2 + 32) : (h.dtype ? 52 : 23);
+  if (h.n_used > nsym || h.n_unpred > n || h.huff_bits > n * LMAX || h.tail_bits > h.n_unpred * max_tail)
     return SZREF_ECORRUPT;
   if (!section_fits(h.off_cb, 3ull * h.n_used, h.total) || !section_fits(h.off_ch, 4ull * h.n_chunks, h.total) ||
       !section_fits(h.off_bs, 4ull * ((h.huff_bits + 31) / 32), h.total) ||
-      !section_fits(h.off_hd, 4ull * ((h.n_unpred * (h.dtype ? 12 : 9) + 31) / 32), h.total) ||
+      !section_fits(h.off_hd, 4ull * ((head_bits + 31) / 32), h.total) ||
       !section_fits(h.off_tl, 4ull * ((h.tail_bits + 31) / 32), h.total))
     return SZREF_ECORRUPT;
 
@@ -679,7 +700,7 @@ int szref_decompress(const uint8_t* comp, size_t size, void* out, size_t cap) {
   uint16_t* codes = (uint16_t*)malloc(n * 2);
   void* uv = malloc((h.n_unpred ? h.n_unpred : 1) * es);
   uint32_t* bsw = (uint32_t*)malloc(4 * (((h.huff_bits + 31) / 32) + 1));
-  uint32_t* hdw = (uint32_t*)malloc(4 * (((h.n_unpred * (h.dtype ? 12 : 9) + 31) / 32) + 1));
+  uint32_t* hdw = (uint32_t*)malloc(4 * (((head_bits + 31) / 32) + 1));
   uint32_t* tlw = (uint32_t*)malloc(4 * (((h.tail_bits + 31) / 32) + 1));
   rc = SZREF_ENOMEM;
   if (!len || !cw || !codes || !uv || !bsw || !hdw || !tlw) goto out;
@@ -692,7 +713,7 @@ int szref_decompress(const uint8_t* comp, size_t size, void* out, size_t cap) {
   }
   canonical_codes(len, nsym, cw);
   for (uint64_t wd = 0; wd < (h.huff_bits + 31) / 32; wd++) bsw[wd] = get_u32(comp + h.off_bs + 4 * wd);
-  for (uint64_t wd = 0; wd < (h.n_unpred * (h.dtype ? 12 : 9) + 31) / 32; wd++) hdw[wd] = get_u32(comp + h.off_hd + 4 * wd);
+  for (uint64_t wd = 0; wd < (head_bits + 31) / 32; wd++) hdw[wd] = get_u32(comp + h.off_hd + 4 * wd);
   for (uint64_t wd = 0; wd < (h.tail_bits + 31) / 32; wd++) tlw[wd] = get_u32(comp + h.off_tl + 4 * wd);
 
   /* Sequential canonical decode, one bit at a time: extend the bit string
@@ -721,8 +742,13 @@ int szref_decompress(const uint8_t* comp, size_t size, void* out, size_t cap) {
     }
     if (br.pos != h.huff_bits || want != h.huff_bits || nz != h.n_unpred) goto out;
   }
-  {
-    struct bitreader hr = {hdw, h.n_unpred * (h.dtype ? 12 : 9), 0};
+  if (xor_coding) {
+    struct bitreader tr = {tlw, h.tail_bits, 0};
+    int urc = h.dtype ? unpack_unpred_xor_f64(codes, n, h.chunk, h.ebT_bits, &tr, hdw, (double*)uv)
+                      : unpack_unpred_xor_f32(codes, n, h.chunk, (uint32_t)h.ebT_bits, &tr, hdw, (float*)uv);
+    if (urc || tr.pos != h.tail_bits) goto out;
+  } else {
+    struct bitreader hr = {hdw, head_bits, 0};
     struct bitreader tr = {tlw, h.tail_bits, 0};
     int urc = h.dtype ? unpack_unpred_f64(&hr, &tr, h.n_unpred, h.ebT_bits, (double*)uv)
                       : unpack_unpred_f32(&hr, &tr, h.n_unpred, (uint32_t)h.ebT_bits, (float*)uv);

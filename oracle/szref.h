@@ -45,6 +45,11 @@ typedef struct {
   double eb_abs;
   double eb_rel;
   double theta;        /* hit-rate threshold for the adaptive rule, 0 = 0.9 */
+  uint32_t unpred_coding; /* 0: unpredictable values as sign+exponent heads and
+                             kept-bit tails; 1: each value of a chunk XORed
+                             with the chunk's previous one, leading zero bytes
+                             counted, the remaining kept bits stored */
+  uint32_t reserved;
 } szref_params;
 
 typedef struct {

@@ -38,7 +38,8 @@ class SzParams(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("dtype", C.c_uint32), ("ndim", C.c_uint32), ("dims", C.c_uint64 * 3),
                 ("block", C.c_uint64 * 3), ("layers", C.c_uint32), ("quant_bits", C.c_uint32),
                 ("eb_mode", C.c_uint32), ("chunk", C.c_uint32), ("eb_abs", C.c_double),
-                ("eb_rel", C.c_double), ("theta", C.c_double)]
+                ("eb_rel", C.c_double), ("theta", C.c_double), ("unpred_coding", C.c_uint32),
+                ("reserved", C.c_uint32)]
 
 
 class SzStats(C.Structure):
@@ -322,7 +323,7 @@ def context(device: int = 0) -> int:
 
 
 def make_params(shape, dtype="float32", layers=1, m=8, eb_mode="rel", eb_abs=0.0, eb_rel=0.0,
-                block=None, chunk=0, theta=0.0) -> SzParams:
+                block=None, chunk=0, theta=0.0, unpred_coding=0) -> SzParams:
     p = SzParams()
     p.struct_size = C.sizeof(SzParams)
     p.dtype = SZ_F32 if str(dtype).endswith("float32") else SZ_F64
@@ -340,6 +341,7 @@ def make_params(shape, dtype="float32", layers=1, m=8, eb_mode="rel", eb_abs=0.0
     p.eb_abs = float(eb_abs)
     p.eb_rel = float(eb_rel)
     p.theta = float(theta)
+    p.unpred_coding = int(unpred_coding)
     return p
 
 

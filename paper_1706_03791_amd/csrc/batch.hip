@@ -373,6 +373,7 @@ void fill_jobs(sz_batch* b, const BPlan& P, const void* const* d_in, void* const
     j.init.eb_rel = p.eb_rel;
     j.init.dtype = (uint32_t)L.dtype;
     j.init.cap = caps[i];
+    j.init.xorc = (uint32_t)L.xorc;
     CodebookArgs& cb = j.cb;
     cb.hist = j.w.hist;
     cb.len = j.w.len;
@@ -393,6 +394,7 @@ void fill_jobs(sz_batch* b, const BPlan& P, const void* const* d_in, void* const
     la.n_chunks = L.n_chunks;
     la.raw_size = kHdr + (uint64_t)L.n * L.ts;
     la.head_bits = L.dtype == SZ_F32 ? 1 + FTr<float>::EXPB : 1 + FTr<double>::EXPB;
+    la.xorc = (uint32_t)L.xorc;
     HeaderArgs& h = j.hd;
     h.out = j.out;
     h.len = j.w.len;

@@ -41,6 +41,7 @@ struct DevPlan {
   uint64_t n_unpred, huff_bits, tail_bits;
   uint64_t off_cb, off_ch, off_bs, off_hd, off_tl, total;
   uint32_t raw;
+  uint32_t xorc;         // unpredictable values XOR-coded (container flag bit 1)
   uint32_t max_len;
   uint64_t out_cap;
 };

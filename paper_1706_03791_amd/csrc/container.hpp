@@ -16,7 +16,9 @@
 // (u32 bits per chunk); Huffman bitstream; heads (sign+exponent, 9 or 12
 // bits each); tails (kept mantissa bits).  Bit streams are MSB-first in
 // little-endian u32 words.  A raw container (flag bit 0) is the header
-// followed by the field itself.
+// followed by the field itself.  With flag bit 1 the unpredictable values
+// are XOR-coded: the heads section holds one u32 per chunk (the bits of the
+// chunk's records) and the tails section the records.
 #pragma once
 
 #include <stdint.h>
@@ -99,7 +101,7 @@ inline int parse_header(const uint8_t* b, size_t size, Hdr& h, bool check_total 
 // wrap around: an offset field holding a huge value is rejected rather than
 // turned into a small one.
 inline int check_sections(const Hdr& h) {
-  if (h.eb_mode > 2 || h.flags > 1) return SZ_ECORRUPT;
+  if (h.eb_mode > 2 || h.flags > 2) return SZ_ECORRUPT;
   uint64_t n = 1;
   for (uint32_t d = 0; d < 3; d++) {
     if (d >= h.ndim) {
@@ -125,16 +127,20 @@ inline int check_sections(const Hdr& h) {
   if (h.chunk < 256 || h.chunk > kMaxChunk || h.chunk % 256) return SZ_ECORRUPT;
   if (h.n_chunks != (n + h.chunk - 1) / h.chunk) return SZ_ECORRUPT;
   if (h.n_used < 1 || h.n_used > (1u << h.m)) return SZ_ECORRUPT;
-  const uint64_t mant = h.dtype ? 52 : 23, head_bits = h.dtype ? 12 : 9;
+  const bool xorc = (h.flags & 2) != 0;
+  // bits per unpredictable value in the tails section at most: the kept
+  // mantissa bits, or a whole XOR record (count of leading bytes + value)
+  const uint64_t max_tail = xorc ? (h.dtype ? 3 + 64 : 2 + 32) : (h.dtype ? 52 : 23);
+  const uint64_t head_bits = xorc ? 32ull * h.n_chunks : h.n_unpred * (h.dtype ? 12 : 9);
   if (h.n_unpred > n || h.huff_bits > n * (uint64_t)kLmax || h.huff_bits < n ||
-      h.tail_bits > h.n_unpred * mant)
+      h.tail_bits > h.n_unpred * max_tail)
     return SZ_ECORRUPT;
   // each term below is < 2^46, so none of the sums can wrap
   const uint64_t off_cb = kHdr;
   const uint64_t off_ch = hdr_align64(off_cb + 3ull * h.n_used);
   const uint64_t off_bs = hdr_align64(off_ch + 4ull * h.n_chunks);
   const uint64_t off_hd = hdr_align64(off_bs + 4ull * ((h.huff_bits + 31) / 32));
-  const uint64_t off_tl = hdr_align64(off_hd + 4ull * ((h.n_unpred * head_bits + 31) / 32));
+  const uint64_t off_tl = hdr_align64(off_hd + 4ull * ((head_bits + 31) / 32));
   const uint64_t total = off_tl + 4ull * ((h.tail_bits + 31) / 32);
   if (h.off_cb != off_cb || h.off_ch != off_ch || h.off_bs != off_bs || h.off_hd != off_hd ||
       h.off_tl != off_tl || h.total != total)

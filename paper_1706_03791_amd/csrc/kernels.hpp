@@ -90,6 +90,7 @@ struct PlanInit {
   double eb_abs, eb_rel;
   uint32_t dtype;
   uint64_t cap;
+  uint32_t xorc;
 };
 
 __device__ __forceinline__ void plan_init_kernel_dev(DevPlan* P, PlanInit I) {
@@ -101,6 +102,7 @@ __device__ __forceinline__ void plan_init_kernel_dev(DevPlan* P, PlanInit I) {
     z.minmax64[0] = ~0ull;
     z.minmax64[1] = 0;
     z.out_cap = I.cap;
+    z.xorc = I.xorc;
     *P = z;
   }
 }
@@ -1183,6 +1185,56 @@ __device__ __forceinline__ void load4(const T* __restrict__ x, uint64_t i, uint6
   }
 }
 
+// ------------------------------ XOR coding of unpredictable values (flag 1)
+// Each unpredictable value's reduced pattern u (sign, exponent and kept
+// mantissa bits, q = 1 + EXPB + r significant bits) is coded against the
+// previous one of its chunk (0 for the first): a count of the leading zero
+// bytes of u ^ prev (at most W/8 - 1, in LZB bits), then the significant
+// bits of u after those bytes.
+template <typename T>
+struct XorRec {
+  using U = typename FTr<T>::U;
+  static constexpr int W = 8 * (int)sizeof(U);
+  static constexpr int BMAX = W / 8 - 1;
+  static constexpr int LZB = W == 32 ? 2 : 3;
+  static constexpr int HB = 1 + FTr<T>::EXPB;
+  __device__ static __forceinline__ int lead_bytes(U d) {
+    int lz;
+    if constexpr (sizeof(U) == 4)
+      lz = d ? __clz((int)d) : W;
+    else
+      lz = d ? __clzll((long long)d) : W;
+    return min(lz >> 3, BMAX);
+  }
+  // record bits of u after prev; q = significant bits of u
+  __device__ static __forceinline__ int bits(U u, U prev, int q) {
+    const int nb = q - 8 * lead_bytes(u ^ prev);
+    return LZB + (nb > 0 ? nb : 0);
+  }
+};
+
+// The pattern of the last unpredictable value in the lanes before this one
+// (0 if none): a wave scan of (has, pattern) keeping the latest present.
+template <typename U>
+__device__ __forceinline__ U wave_prev_present(bool has, U last) {
+  const int lane = threadIdx.x & 63;
+  int h = has ? 1 : 0;
+  uint64_t v = (uint64_t)last;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int hu = __shfl_up(h, o, 64);
+    const uint64_t vu = __shfl_up(v, o, 64);
+    if (lane >= o && !h) {
+      h = hu;
+      v = vu;
+    }
+  }
+  // exclusive: the inclusive result of the lane before
+  const int hp = __shfl_up(h, 1, 64);
+  const uint64_t vp = __shfl_up(v, 1, 64);
+  return (U)((lane > 0 && hp) ? vp : 0ull);
+}
+
 template <typename T, typename CT, bool LT>
 __device__ __forceinline__ void chunk_stats_body(const CT* __restrict__ codes, const T* __restrict__ x,
                                                  const uint8_t* __restrict__ len, const uint32_t* s_tab,
@@ -1256,6 +1308,81 @@ __device__ __forceinline__ void chunk_stats_body(const CT* __restrict__ codes, c
   }
 }
 
+// Per-chunk totals with XOR-coded unpredictable values: the bits of the
+// chunk's records instead of its tail bits.  Two passes over each lane's
+// codes: the first finds the lane's last unpredictable pattern (its
+// successor lanes' starting point), the second sizes the records.
+template <typename T, typename CT, bool LT>
+__device__ __forceinline__ void chunk_stats_xor_body(const CT* __restrict__ codes, const T* __restrict__ x,
+                                                     const uint8_t* __restrict__ len, const uint32_t* s_tab,
+                                                     CT* sc, uint64_t n, uint32_t C, uint32_t* cbits, uint32_t* cu,
+                                                     uint32_t* ctb, typename FTr<T>::U ebb) {
+  using U = typename FTr<T>::U;
+  using XR = XorRec<T>;
+  const uint64_t n_chunks = (n + C - 1) / C;
+  const int lane = threadIdx.x & 63;
+  const uint32_t per = C / 64;
+  for (uint64_t c = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < n_chunks; c += (uint64_t)gridDim.x * 4) {
+    const uint32_t cnt = stage_codes<CT>(codes, n, c, C, sc, lane);
+    const uint32_t k0 = (uint32_t)lane * per;
+    const uint64_t i0 = c * C + k0;
+    uint32_t b = 0, z = 0, tb = 0;
+    bool has = false;
+    U last = 0;
+    for (uint32_t j = 0; j < per; j += 4) {
+      uint32_t sym[4];
+      lds_code4<CT>(sc, k0 + j, sym);
+      bool anyz = false;
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        const bool real = k0 + j + k < cnt;
+        b += real ? (code_entry<LT>(sym[k], s_tab, len, nullptr) >> 27) : 0u;
+        anyz |= real && sym[k] == 0;
+      }
+      if (anyz) {
+        T xv[4];
+        load4<T>(x, i0 + j, n, xv);
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+          if (k0 + j + k < cnt && sym[k] == 0) {
+            z++;
+            has = true;
+            last = to_bits<T>(truncate_unpred<T>(xv[k], ebb));
+          }
+      }
+    }
+    U prev = wave_prev_present<U>(has, last);
+    if (z) {
+      for (uint32_t j = 0; j < per; j += 4) {
+        uint32_t sym[4];
+        lds_code4<CT>(sc, k0 + j, sym);
+        bool anyz = false;
+#pragma unroll
+        for (int k = 0; k < 4; k++) anyz |= k0 + j + k < cnt && sym[k] == 0;
+        if (!anyz) continue;
+        T xv[4];
+        load4<T>(x, i0 + j, n, xv);
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+          if (k0 + j + k < cnt && sym[k] == 0) {
+            const U u = to_bits<T>(truncate_unpred<T>(xv[k], ebb));
+            tb += (uint32_t)XR::bits(u, prev, XR::HB + kept_bits<T>(xv[k], ebb));
+            prev = u;
+          }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    b = wave_sum(b);
+    z = wave_sum(z);
+    tb = wave_sum(tb);
+    if (lane == 0) {
+      cbits[c] = b;
+      cu[c] = z;
+      ctb[c] = tb;
+    }
+  }
+}
+
 template <typename T, typename CT>
 __device__ __forceinline__ void chunk_stats_kernel_dev(const CT* __restrict__ codes, const T* __restrict__ x,
                                                           const uint8_t* __restrict__ len, uint64_t n,
@@ -1271,10 +1398,16 @@ __device__ __forceinline__ void chunk_stats_kernel_dev(const CT* __restrict__ co
   __syncthreads();
   CT* sc = (CT*)s_dyn + (size_t)(threadIdx.x >> 6) * C;
   const auto ebb = (typename FTr<T>::U)P->ebT_bits;
-  if (sizeof(CT) == 1 || lt)
+  if (P->xorc) {
+    if (sizeof(CT) == 1 || lt)
+      chunk_stats_xor_body<T, CT, true>(codes, x, len, s_tab, sc, n, C, cbits, cu, ctb, ebb);
+    else
+      chunk_stats_xor_body<T, CT, false>(codes, x, len, s_tab, sc, n, C, cbits, cu, ctb, ebb);
+  } else if (sizeof(CT) == 1 || lt) {
     chunk_stats_body<T, CT, true>(codes, x, len, s_tab, sc, n, C, cbits, cu, ctb, ebb);
-  else
+  } else {
     chunk_stats_body<T, CT, false>(codes, x, len, s_tab, sc, n, C, cbits, cu, ctb, ebb);
+  }
 }
 template <typename T, typename CT>
 __global__ void __launch_bounds__(256) chunk_stats_kernel(const CT* __restrict__ codes, const T* __restrict__ x,
@@ -1378,6 +1511,7 @@ struct LayoutArgs {
   uint64_t n_chunks;
   uint64_t raw_size;  // header + S
   uint32_t head_bits;
+  uint32_t xorc;      // heads section = one u32 record-bit count per chunk
 };
 __device__ __forceinline__ uint64_t align64(uint64_t v) { return (v + 63) & ~63ull; }
 
@@ -1391,7 +1525,7 @@ __device__ __forceinline__ void layout_kernel_dev(LayoutArgs A) {
   P->off_ch = align64(kHdr + 3ull * P->n_used);
   P->off_bs = align64(P->off_ch + 4ull * A.n_chunks);
   P->off_hd = align64(P->off_bs + 4ull * ((P->huff_bits + 31) / 32));
-  P->off_tl = align64(P->off_hd + 4ull * ((P->n_unpred * A.head_bits + 31) / 32));
+  P->off_tl = align64(P->off_hd + (A.xorc ? 4ull * A.n_chunks : 4ull * ((P->n_unpred * A.head_bits + 31) / 32)));
   P->total = P->off_tl + 4ull * ((P->tail_bits + 31) / 32);
   P->raw = P->total >= A.raw_size;
   if (P->raw) P->total = A.raw_size;
@@ -1415,7 +1549,7 @@ __host__ __device__ constexpr uint32_t enc_lds_bytes(uint32_t C, uint32_t code_b
   return 4u * (enc_words_per_wave(C) * 4u + C * code_bytes);
 }
 
-template <typename T, typename CT, bool LT>
+template <typename T, typename CT, bool LT, bool XORC>
 __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const T* __restrict__ x,
                                             const uint8_t* __restrict__ len, const uint32_t* __restrict__ cw,
                                             const uint32_t* s_tab, uint32_t* words, CT* sc, uint64_t n,
@@ -1442,6 +1576,8 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
     const uint32_t k0 = (uint32_t)lane * per;
     const uint64_t i0 = c * C + k0;  // a multiple of 4
     uint32_t mybits = 0, myz = 0, mytb = 0;
+    bool has = false;
+    U last = 0;
     for (uint32_t j = 0; j < per; j += 4) {
       uint32_t sym[4];
       lds_code4<CT>(sc, k0 + j, sym);
@@ -1460,9 +1596,44 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
         for (int k = 0; k < 4; k++)
           if (k0 + j + k < cnt && sym[k] == 0) {
             myz++;
-            mytb += (uint32_t)kept_bits<T>(xv[k], ebb);
+            if constexpr (XORC) {
+              has = true;
+              last = to_bits<T>(truncate_unpred<T>(xv[k], ebb));
+            } else {
+              mytb += (uint32_t)kept_bits<T>(xv[k], ebb);
+            }
           }
       }
+    }
+    // XOR coding: the chunk's previous pattern before the lane's first value
+    // (the last of the lanes before it), then the sizes of the lane's records
+    U prev0 = 0;
+    if constexpr (XORC) {
+      using XR = XorRec<T>;
+      prev0 = wave_prev_present<U>(has, last);
+      U prev = prev0;
+      if (myz) {
+        for (uint32_t j = 0; j < per; j += 4) {
+          uint32_t sym[4];
+          lds_code4<CT>(sc, k0 + j, sym);
+          bool anyz = false;
+#pragma unroll
+          for (int k = 0; k < 4; k++) anyz |= k0 + j + k < cnt && sym[k] == 0;
+          if (!anyz) continue;
+          T xv[4];
+          load4<T>(x, i0 + j, n, xv);
+#pragma unroll
+          for (int k = 0; k < 4; k++)
+            if (k0 + j + k < cnt && sym[k] == 0) {
+              const U u = to_bits<T>(truncate_unpred<T>(xv[k], ebb));
+              mytb += (uint32_t)XR::bits(u, prev, XR::HB + kept_bits<T>(xv[k], ebb));
+              prev = u;
+            }
+        }
+      }
+      // the chunk's entry of the table of record bits (the heads section)
+      const uint32_t tot = wave_sum(mytb);
+      if (lane == 0) hd[c] = tot;
     }
     const uint64_t bpos = (b0 & 31) + wave_exscan(mybits);
     const uint64_t zpos = uoff[c] + wave_exscan(myz);
@@ -1471,6 +1642,7 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
     // codes into the wave's LDS words; heads and tails of unpredictable
     // values straight into their streams
     BitWriter wb(words, bpos), wh(hd, zpos * HB), wt(tl, tpos);
+    U prev = prev0;
     for (uint32_t j = 0; j < per; j += 4) {
       uint32_t sym[4];
       lds_code4<CT>(sc, k0 + j, sym);
@@ -1490,13 +1662,32 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
           if (k0 + j + k >= cnt || sym[k] != 0) continue;
           const U ub = to_bits<T>(truncate_unpred<T>(xv[k], ebb));
           const int r = kept_bits<T>(xv[k], ebb);
-          wh.put((uint32_t)(ub >> MANT), HB);
-          const U tail = (ub & ((((U)1) << MANT) - 1)) >> (MANT - r);  // the top r mantissa bits
-          if (r > 32) {
-            wt.put((uint32_t)((uint64_t)tail >> 32), r - 32);
-            wt.put((uint32_t)tail, 32);
+          if constexpr (XORC) {
+            // leading-byte count, then the significant bits after those bytes
+            using XR = XorRec<T>;
+            const int q = XR::HB + r;
+            const int lzb = XR::lead_bytes(ub ^ prev);
+            wt.put((uint32_t)lzb, XR::LZB);
+            const int nb = q - 8 * lzb;
+            if (nb > 0) {
+              const U v = (ub >> (XR::W - q)) & ((((U)1) << (nb - 1) << 1) - 1);
+              if (nb > 32) {
+                wt.put((uint32_t)((uint64_t)v >> 32), nb - 32);
+                wt.put((uint32_t)v, 32);
+              } else {
+                wt.put((uint32_t)v, nb);
+              }
+            }
+            prev = ub;
           } else {
-            wt.put((uint32_t)tail, r);
+            wh.put((uint32_t)(ub >> MANT), HB);
+            const U tail = (ub & ((((U)1) << MANT) - 1)) >> (MANT - r);  // the top r mantissa bits
+            if (r > 32) {
+              wt.put((uint32_t)((uint64_t)tail >> 32), r - 32);
+              wt.put((uint32_t)tail, 32);
+            } else {
+              wt.put((uint32_t)tail, r);
+            }
           }
         }
       }
@@ -1541,10 +1732,16 @@ __device__ __forceinline__ void encode_kernel_dev(const CT* __restrict__ codes, 
   const int wv = threadIdx.x >> 6;
   uint32_t* words = (uint32_t*)s_dyn + (size_t)wv * enc_words_per_wave(C);
   CT* sc = (CT*)((uint32_t*)s_dyn + 4 * (size_t)enc_words_per_wave(C)) + (size_t)wv * C;
-  if (sizeof(CT) == 1 || lt)
-    encode_body<T, CT, true>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P);
-  else
-    encode_body<T, CT, false>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P);
+  if (P->xorc) {
+    if (sizeof(CT) == 1 || lt)
+      encode_body<T, CT, true, true>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P);
+    else
+      encode_body<T, CT, false, true>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P);
+  } else if (sizeof(CT) == 1 || lt) {
+    encode_body<T, CT, true, false>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P);
+  } else {
+    encode_body<T, CT, false, false>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P);
+  }
 }
 template <typename T, typename CT>
 __global__ void __launch_bounds__(kEncNT) encode_kernel(const CT* __restrict__ codes, const T* __restrict__ x,
@@ -1582,7 +1779,8 @@ __device__ __forceinline__ void header_kernel_dev(HeaderArgs A) {
   __syncthreads();
   if (tid == 0) {
     const bool raw = P->raw;
-    put64(h + 0, kMagic | ((uint64_t)kVersion << 32) | ((uint64_t)(raw ? 1 : 0) << 48));
+    const uint64_t flags = raw ? 1 : (P->xorc ? 2 : 0);  // raw copy; XOR-coded unpredictable values
+    put64(h + 0, kMagic | ((uint64_t)kVersion << 32) | (flags << 48));
     h[8] = (uint8_t)A.dtype;
     h[9] = (uint8_t)A.ndim;
     h[10] = (uint8_t)A.layers;
@@ -2187,6 +2385,106 @@ __global__ void __launch_bounds__(1024) unpred_values_kernel(const uint8_t* comp
     vals[j] = bits_to<T>(u);
     if (j == U - 1 && pos + r != tail_bits) set_status(P, SZ_ECORRUPT);
   }
+}
+
+// ------------------------- XOR-coded unpredictable values (flag bit 1)
+// Zero codes of each chunk of the decoded code array (one wave per chunk).
+template <typename CT>
+__global__ void __launch_bounds__(256) chunk_zeros_kernel(const CT* __restrict__ codes, uint64_t n, uint32_t C,
+                                                          uint32_t* cz, const DevPlan* P) {
+  if (P->status) return;
+  const uint64_t n_chunks = (n + C - 1) / C;
+  const int lane = threadIdx.x & 63;
+  for (uint64_t c = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < n_chunks; c += (uint64_t)gridDim.x * 4) {
+    const uint64_t i0 = c * C, i1 = min(n, i0 + C);
+    uint32_t z = 0;
+    for (uint64_t i = i0 + lane; i < i1; i += 64) z += codes[i] == 0;
+    z = wave_sum(z);
+    if (lane == 0) cz[c] = z;
+  }
+}
+
+// MSB-first bits of a stream read in order through a 64-bit buffer.
+struct SeqBits {
+  const uint32_t* w;
+  uint64_t nw, next, buf;
+  int have;
+  __device__ __forceinline__ SeqBits(const uint32_t* words, uint64_t nwords, uint64_t pos)
+      : w(words), nw(nwords), next(pos >> 5), buf(0), have(0) {
+    refill();
+    const int off = (int)(pos & 31);
+    buf <<= off;
+    have -= off;
+  }
+  __device__ __forceinline__ void refill() {
+    const uint32_t word = next < nw ? w[next] : 0u;
+    next++;
+    buf |= (uint64_t)word << (32 - have);
+    have += 32;
+  }
+  // 1 <= nb <= 32
+  __device__ __forceinline__ uint32_t get(int nb) {
+    if (have < nb) refill();
+    const uint32_t v = (uint32_t)(buf >> (64 - nb));
+    buf <<= nb;
+    have -= nb;
+    return v;
+  }
+  __device__ __forceinline__ uint64_t get64(int nb) {  // 0 <= nb <= 64
+    if (nb <= 0) return 0;
+    if (nb <= 32) return get(nb);
+    const uint64_t hi = get(nb - 32);
+    return (hi << 32) | get(32);
+  }
+};
+
+// One thread per chunk parses the chunk's records in order: the leading
+// bytes come from the previous value of the chunk, sign and exponent are
+// completed from the stream, the exponent gives the kept bits and so the
+// rest of the record.  A chunk whose records do not end where its table
+// entry says marks the container corrupt.
+template <typename T>
+__global__ void __launch_bounds__(256) unpred_xor_kernel(const uint8_t* comp, uint64_t off_tl, uint64_t tl_words,
+                                                         const uint32_t* __restrict__ table,
+                                                         const uint64_t* __restrict__ roff,
+                                                         const uint32_t* __restrict__ cz,
+                                                         const uint64_t* __restrict__ uoff, uint64_t n_chunks,
+                                                         uint64_t ebT_bits, T* vals, DevPlan* P) {
+  using U = typename FTr<T>::U;
+  using XR = XorRec<T>;
+  constexpr int MANT = FTr<T>::MANT, EMAX = FTr<T>::EMAX;
+  if (P->status) return;
+  const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_chunks) return;
+  const int e_eb = (int)((ebT_bits >> MANT) & (uint64_t)EMAX);
+  const uint64_t start = roff[c];
+  SeqBits br((const uint32_t*)(comp + off_tl), tl_words, start);
+  uint64_t consumed = 0;
+  U prev = 0;
+  T* out = vals + uoff[c];
+  const uint32_t cnt = cz[c];
+  for (uint32_t k = 0; k < cnt; k++) {
+    const int lzb = (int)br.get(XR::LZB);
+    if (lzb > XR::BMAX) {
+      set_status(P, SZ_ECORRUPT);
+      return;
+    }
+    U u = lzb ? (prev & ~((((U)1) << (XR::W - 8 * lzb)) - 1)) : (U)0;
+    const int kk = max(0, XR::HB - 8 * lzb);  // sign and exponent bits still to read
+    if (kk) u |= (U)br.get(kk) << (XR::W - 8 * lzb - kk);
+    const int e = (int)((u >> MANT) & (U)EMAX);
+    int r;
+    if (e_eb == 0 || e == EMAX) r = MANT;
+    else if (e == 0) r = 0;
+    else r = min(max(e - e_eb, 0), MANT);
+    const int q = XR::HB + r;
+    const int rest = q - 8 * lzb - kk;
+    if (rest > 0) u |= (U)br.get64(rest) << (XR::W - q);
+    out[k] = bits_to<T>(u);
+    prev = u;
+    consumed += (uint64_t)XR::LZB + (uint64_t)kk + (uint64_t)(rest > 0 ? rest : 0);
+  }
+  if (consumed != table[c]) set_status(P, SZ_ECORRUPT);
 }
 
 __global__ void check_total_kernel(const uint64_t* got, uint64_t want, DevPlan* P) {

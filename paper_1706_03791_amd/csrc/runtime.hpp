@@ -101,6 +101,7 @@ struct Layout {
   int nw, az;       // its waves per workgroup and z sub-rows per lane
   uint64_t xy_bytes;  // y-exchange part of the exchange buffer (wave sweep)
   double theta;
+  int xorc;         // unpredictable values XOR-coded (flag bit 1)
   uint64_t out_dims[3], out_block[3];
 };
 
@@ -130,6 +131,7 @@ int resolve(const sz_params* p, Layout& L, const Sched* sched_override = nullptr
   if (p->layers < 1 || p->layers > 4 || p->quant_bits > 16 || p->eb_mode > 2) return SZ_EINVAL;
   if (p->chunk != 0 && (p->chunk < 256 || p->chunk > (uint32_t)kMaxChunk || p->chunk % 256)) return SZ_EINVAL;
   if (!(p->theta >= 0 && p->theta <= 1)) return SZ_EINVAL;
+  if (p->unpred_coding > 1 || p->reserved != 0) return SZ_EINVAL;
   if (!std::isfinite(p->eb_abs) || !std::isfinite(p->eb_rel) || p->eb_abs < 0 || p->eb_rel < 0) return SZ_EINVAL;
   L.dtype = (int)p->dtype;
   L.ndim = (int)p->ndim;
@@ -137,6 +139,7 @@ int resolve(const sz_params* p, Layout& L, const Sched* sched_override = nullptr
   L.m_req = (int)p->quant_bits;
   L.eb_mode = (int)p->eb_mode;
   L.theta = p->theta > 0 ? p->theta : 0.9;
+  L.xorc = (int)p->unpred_coding;
   L.ts = p->dtype == SZ_F32 ? 4 : 8;
   L.cw = (p->quant_bits >= 1 && p->quant_bits <= 8) ? 1 : 2;
   const int pad = 3 - L.ndim;
@@ -449,6 +452,7 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
   I.eb_rel = p->eb_rel;
   I.dtype = (uint32_t)L.dtype;
   I.cap = cap;
+  I.xorc = (uint32_t)L.xorc;
   hipLaunchKernelGGL(plan_init_kernel, dim3(1), dim3(64), 0, st, P, I);
   stage_begin(ctx, ST_RANGE, st);
   if (L.eb_mode != SZ_EB_ABS) {
@@ -551,6 +555,7 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
   la.n_chunks = L.n_chunks;
   la.raw_size = kHdr + (uint64_t)L.n * L.ts;
   la.head_bits = 1 + FTr<T>::EXPB;
+  la.xorc = (uint32_t)L.xorc;
   hipLaunchKernelGGL(layout_kernel, dim3(1), dim3(64), 0, st, la);
   {
     // zeroed container body, or the raw field when the layout chose raw
@@ -634,6 +639,7 @@ void hdr_params(const Hdr& h, sz_params* p) {
   p->chunk = h.chunk;
   p->eb_abs = h.eb_abs;
   p->eb_rel = h.eb_rel;
+  p->unpred_coding = (h.flags >> 1) & 1;
 }
 
 struct DecWs {
@@ -650,6 +656,9 @@ struct DecWs {
   uint32_t* progress;
   uint32_t* ticket;
   void* xchg;
+  uint32_t* xcz;            // XOR coding: zero codes per chunk
+  uint64_t *xuoff, *xroff;  // their scan; the scan of the chunks' record bits
+  uint64_t *xts_u, *xts_r;
 };
 
 size_t carve_dec(const Layout& L, uint64_t U, uint8_t* base, DecWs* W) {
@@ -673,6 +682,16 @@ size_t carve_dec(const Layout& L, uint64_t U, uint8_t* base, DecWs* W) {
   w.progress = c.take<uint32_t>((L.g.ntiles + 1) * 4);
   w.ticket = w.progress + L.g.ntiles;
   w.xchg = c.take<uint8_t>(L.xchg_bytes + 512);
+  w.xcz = nullptr;
+  w.xuoff = w.xroff = w.xts_u = w.xts_r = nullptr;
+  if (L.xorc) {
+    const uint64_t nt = ceil_div(L.n_chunks, 4096) + 1;
+    w.xcz = c.take<uint32_t>(L.n_chunks * 4);
+    w.xuoff = c.take<uint64_t>(L.n_chunks * 8);
+    w.xroff = c.take<uint64_t>(L.n_chunks * 8);
+    w.xts_u = c.take<uint64_t>(nt * 8);
+    w.xts_r = c.take<uint64_t>(nt * 8);
+  }
   if (W) *W = w;
   return c.off + 256;
 }
@@ -728,7 +747,24 @@ int enqueue_decompress_t(sz_ctx* ctx, const Layout& L, const Hdr& h, const void*
   scan_u32_check(W.segcnt, L.nseg, W.useg, W.tsum_s, W.tot + 1, U, P, st);
   stage_end(ctx, ST_DECODE, st);
   stage_begin(ctx, ST_UNPRED, st);
-  if (U) {
+  if (U && L.xorc) {
+    // XOR-coded values: each chunk's first value index and first record bit,
+    // then one thread per chunk
+    const unsigned gz = (unsigned)std::min<uint64_t>(ceil_div(L.n_chunks, 4), 8192);
+    if (L.cw == 1)
+      hipLaunchKernelGGL(chunk_zeros_kernel<uint8_t>, dim3(gz), dim3(256), 0, st, (const uint8_t*)W.codes,
+                         (uint64_t)L.n, L.chunk, W.xcz, (const DevPlan*)P);
+    else
+      hipLaunchKernelGGL(chunk_zeros_kernel<uint16_t>, dim3(gz), dim3(256), 0, st, (const uint16_t*)W.codes,
+                         (uint64_t)L.n, L.chunk, W.xcz, (const DevPlan*)P);
+    scan_u32_check(W.xcz, L.n_chunks, W.xuoff, W.xts_u, W.tot + 2, U, P, st);
+    const uint32_t* table = (const uint32_t*)(comp + h.off_hd);
+    scan_u32_check(table, L.n_chunks, W.xroff, W.xts_r, W.tot + 3, h.tail_bits, P, st);
+    const uint64_t tlw = (h.tail_bits + 31) / 32;
+    hipLaunchKernelGGL(unpred_xor_kernel<T>, dim3((unsigned)ceil_div(L.n_chunks, 256)), dim3(256), 0, st, comp,
+                       h.off_tl, tlw, table, (const uint64_t*)W.xroff, (const uint32_t*)W.xcz,
+                       (const uint64_t*)W.xuoff, L.n_chunks, h.ebT_bits, (T*)W.uvals, P);
+  } else if (U) {
     constexpr int HB = 1 + FTr<T>::EXPB;
     const uint64_t ngr = ceil_div(U, 1024);
     const uint64_t hdw = (U * HB + 31) / 32, tlw = (h.tail_bits + 31) / 32;

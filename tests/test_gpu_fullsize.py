@@ -103,6 +103,14 @@ def test_velocity_512_f32(Z, oracle):
     assert s["n_unpred"] > xh.size // 2  # most points take the unpredictable branch
 
 
+def test_velocity_512_f32_xor(Z, oracle):
+    """The velocity field with its unpredictable values XOR-coded."""
+    import fieldgen.gpu as G
+    xh, xd = _gpu_field(lambda: G.velocity3d((512, 512, 512), F.BASE_SEED + 102))
+    check_full(Z, oracle, xh, xd, "velocity 512^3 f32 XOR", layers=1, m=8, eb_mode="rel", eb_rel=1e-4,
+               unpred_coding=1)
+
+
 def test_batch_cube_384(Z, oracle):
     import fieldgen.gpu as G
     xh, xd = _gpu_field(lambda: G.smooth3d((384, 384, 384), F.BASE_SEED + 33))

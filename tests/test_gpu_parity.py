@@ -225,3 +225,38 @@ def test_capacity_error(Z):
     rc, size, st = Z.sz_compress(Z.context(0), p, xi.data_ptr(), out.data_ptr(), 400,
                                  torch.cuda.current_stream().cuda_stream)
     assert rc == Z.SZ_ECAPACITY
+
+
+XOR_CASES = [
+    ("velocity 40x50x60 f32", lambda: __import__("fieldgen.gpu", fromlist=["x"]).velocity3d(
+        (40, 50, 60), 5, device="cpu").numpy(), dict(layers=1, m=8, eb_mode="rel", eb_rel=1e-4)),
+    ("velocity 33x70x129 f64", lambda: __import__("fieldgen.gpu", fromlist=["x"]).velocity3d(
+        (33, 70, 129), 6, device="cpu").numpy().astype(np.float64), dict(layers=1, m=0, eb_mode="rel", eb_rel=1e-7)),
+    ("climate 300x500 f32 2 layers", lambda: F.climate2d((300, 500)), dict(layers=2, m=0, eb_mode="rel", eb_rel=1e-6)),
+    ("walk 50000 f32 chunk 256", lambda: np.cumsum(np.random.default_rng(8).normal(0, 20, 50000)).astype(np.float32),
+     dict(layers=1, m=4, eb_mode="rel", eb_rel=1e-5, chunk=256)),
+    ("walk 20001 f64 chunk 4096", lambda: np.cumsum(np.random.default_rng(9).normal(0, 20, 20001)),
+     dict(layers=3, m=6, eb_mode="abs", eb_abs=1e-4, chunk=4096)),
+    ("lossless 30x40 f32", lambda: np.random.default_rng(2).normal(0, 1, (30, 40)).astype(np.float32),
+     dict(layers=1, m=8, eb_mode="abs", eb_abs=0.0)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(XOR_CASES)), ids=[c[0] for c in XOR_CASES])
+def test_xor_unpredictable_coding(Z, oracle, case):
+    """Unpredictable values XOR-coded against the previous one of their
+    chunk (container flag bit 1): bytes and decompressed bits equal the
+    oracle's."""
+    _, make, kw = XOR_CASES[case]
+    x = np.ascontiguousarray(make())
+    s = check(Z, oracle, x, unpred_coding=1, **kw)
+    assert s["n_unpred"] > 0
+
+
+def test_xor_coding_nonfinite(Z, oracle):
+    x = F.smooth3d((20, 30, 40))
+    x[3, 4, 5] = np.nan
+    x[10, 0, 0] = np.inf
+    x[0, 29, 39] = -np.inf
+    x[7, 7, 7] = 1e30
+    check(Z, oracle, x, layers=1, m=8, eb_mode="abs", eb_abs=1e-3, unpred_coding=1)

@@ -492,3 +492,68 @@ def test_fibonacci_field_forces_the_length_limit(oracle):
     lens = cb[:, 2].astype(np.int64)
     assert lens.max() <= 27 and np.sum(2.0 ** -lens) <= 1.0
     assert np.array_equal(oracle.decompress(buf), x)
+
+
+def test_hand_xor_unpredictable(oracle):
+    """The XOR coding of unpredictable values against the hand-worked records
+    of tests/golden/hand_xor_unpred.txt: the per-chunk bit table in the heads
+    section, the records in the tails section, flag bit 1, and the
+    reconstruction (the same values as the plain coding)."""
+    g = golden("hand_xor_unpred.txt")
+    x = np.zeros(512, np.float32)
+    x[10:13] = [100.0, 100.25, 100.5]
+    x[13:300] = 100.5
+    x[300] = 100.0
+    x[301:317] = 100.0 - 0.125 * np.arange(1, 17)
+    x[317] = 100.0
+    kw = dict(m=2, eb_mode="abs", eb_abs=0.0625, chunk=256)
+    buf, st = oracle.compress(x, unpred_coding=1, **kw)
+    plain, sp = oracle.compress(x, **kw)
+    assert st["raw_fallback"] == 0 and st["n_unpred"] == int(g["n_unpred"][0][0]) == sp["n_unpred"]
+    assert struct.unpack("<H", buf[6:8])[0] == 2
+    bits = "".join("".join(r) for r in g["record"])
+    assert st["tail_bits"] == len(bits) == 73
+    table = _container_words(buf, HDR["off_hd"], 2)
+    assert table == [int(v) for v in g["chunk_bits"][0]]
+    nw = (len(bits) + 31) // 32
+    want = [int(bits[32 * i:32 * i + 32].ljust(32, "0"), 2) for i in range(nw)]
+    assert _container_words(buf, HDR["off_tl"], nw) == want
+    out = oracle.decompress(buf)
+    assert np.array_equal(out.view(np.uint32), oracle.decompress(plain).view(np.uint32))
+    assert out[10:15].tolist() == [100.0, 100.25, 100.5, 100.5, 100.5] and out[318] == 0.0
+    assert out[317] == 100.0 and np.all(np.abs(out.astype(np.float64) - x) < 0.0625)
+    assert oracle.inspect(buf)["unpred_coding"] == 1
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_xor_coding_round_trip_and_bound(oracle, dtype):
+    """Both codings of unpredictable values reconstruct the same values (the
+    XOR coding only re-encodes the reduced patterns), within the bound, on
+    fields with many unpredictable points, non-finite values in ABS mode and a
+    lossless bound."""
+    import fieldgen as F
+    rng = np.random.default_rng(21)
+    cases = [
+        (np.cumsum(rng.normal(0, 30, 6000)).astype(dtype), dict(m=4, eb_mode="rel", eb_rel=1e-4)),
+        (F.climate2d((60, 80)).astype(dtype), dict(m=8, eb_mode="rel", eb_rel=1e-6, layers=2)),
+        (F.smooth3d((12, 14, 16)).astype(dtype), dict(m=0, eb_mode="abs", eb_abs=1e-5, chunk=512)),
+        (rng.normal(0, 1, 3000).astype(dtype), dict(m=8, eb_mode="abs", eb_abs=0.0)),
+    ]
+    spiky = np.cumsum(rng.normal(0, 1, 4000)).astype(dtype)
+    spiky[[5, 77, 900]] = [np.nan, np.inf, -np.inf]
+    cases.append((spiky, dict(m=6, eb_mode="abs", eb_abs=1e-2)))
+    for x, kw in cases:
+        a, sa = oracle.compress(x, **kw)
+        b, sb, _, xp = oracle.compress(x, debug=True, unpred_coding=1, **kw)
+        assert sa["n_unpred"] == sb["n_unpred"] > 0
+        ya, yb = oracle.decompress(a), oracle.decompress(b)
+        u = np.uint32 if dtype == np.float32 else np.uint64
+        # a container that would not be smaller than the field is a raw copy
+        for y, s in ((ya, sa), (yb, sb)):
+            assert np.array_equal(y.view(u), (x if s["raw_fallback"] else xp).view(u))
+        fin = np.isfinite(x)
+        eb = sb["eb_used"]
+        if eb > 0:
+            assert np.all(np.abs(yb[fin].astype(np.float64) - x[fin]) < eb)
+        else:
+            assert np.array_equal(yb.view(u), x.view(u))

@@ -78,9 +78,12 @@ def _containers(oracle):
                                      chunk=256)[0],
         "1d_f64_m12": oracle.compress(x1, layers=3, m=12, eb_mode="abs", eb_abs=1e-3)[0],
         "raw_f32": oracle.compress(raw, layers=1, m=8, eb_mode="abs", eb_abs=1e-30)[0],
+        "1d_f32_xor": oracle.compress(x1.astype(np.float32), layers=1, m=4, eb_mode="abs", eb_abs=1e-3,
+                                      chunk=256, unpred_coding=1)[0],
     }
     assert out["raw_f32"][6] & 1  # raw fallback
-    assert not any(out[k][6] & 1 for k in ("3d_f32", "2d_f32_l2", "1d_f64_m12"))
+    assert not any(out[k][6] & 1 for k in ("3d_f32", "2d_f32_l2", "1d_f64_m12", "1d_f32_xor"))
+    assert out["1d_f32_xor"][6] == 2
     return out
 
 
