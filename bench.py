@@ -50,6 +50,41 @@ def load_traffic(kernel: str, workload: str, n_launch_bytes: float):
     return t.get("bytes_per_launch")
 
 
+# Algorithmic bytes of each stage per launch: what the method itself must
+# move there (the range pass reads the field, the prediction sweep reads it,
+# the encoder writes the container, the decoder reads it, the reconstruction
+# writes the field).  The intermediate code array (one code of w bytes per
+# point, written by the sweep and read by the coder, or written by the
+# decoder and read by the reconstruction) is design traffic, reported apart.
+def stage_bytes(S: int, Cb: int, npts: int, w: int):
+    alg = {"range": S, "sweep_compress": S, "encode": Cb, "decode": Cb, "sweep_decompress": S}
+    design = {"range": 0, "sweep_compress": npts * w, "encode": npts * w, "decode": npts * w,
+              "sweep_decompress": npts * w}
+    return alg, design
+
+
+def stage_roofline(per_call_ms: dict, S: int, Cb: int, npts: int, w: int):
+    """Roofline line of the stage with the longest launch: its algorithmic
+    bytes per launch over its HIP-event duration, against the HBM peak."""
+    alg, design = stage_bytes(S, Cb, npts, w)
+    dom = max(alg, key=lambda k: per_call_ms.get(k, 0.0))
+    ms = per_call_ms[dom]
+    achieved = alg[dom] / (ms / 1e3) / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+            "algorithmic_bytes_per_launch": int(alg[dom]), "design_bytes_per_launch": int(design[dom]),
+            "launch_ms": round(ms, 4)}
+
+
+def host_cpus() -> dict:
+    """The host's processor as the run sees it."""
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
 def cpu_baseline(x: np.ndarray, planes: int, kw: dict):
     import oracle as O
     sample = np.ascontiguousarray(x[:planes])
@@ -63,8 +98,7 @@ def cpu_baseline(x: np.ndarray, planes: int, kw: dict):
     return {"value": round(gbps, 6), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"first {planes} z-planes of the same field ({sample.shape[0]}x{sample.shape[1]}x"
                       f"{sample.shape[2]} f32, {sample.nbytes / 2**20:.0f} MiB): compress "
-                      f"{t1 - t0:.2f} s + decompress {t2 - t1:.2f} s, single thread",
-            "cpu_model": cpu_model()}
+                      f"{t1 - t0:.2f} s + decompress {t2 - t1:.2f} s, single thread", **host_cpus()}
 
 
 def cpu_model() -> str:
@@ -72,7 +106,7 @@ def cpu_model() -> str:
         with open("/proc/cpuinfo") as f:
             for line in f:
                 if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                    return " ".join(line.split(":", 1)[1].split())
     except OSError:
         pass
     return "unknown"
@@ -127,8 +161,7 @@ def cpu_all_cores(x: np.ndarray, planes: int, kw: dict, workers: int):
     return {"value": round(2 * total / wall / 1e9, 6), "unit": "GB/s", "cores": workers,
             "kind": "oracle, slab-split: one process per core on independent slabs",
             "sample": f"{workers} slabs of {planes} z-planes ({total / 2**20:.0f} MiB in all), compress + "
-                      f"decompress each, {wall:.2f} s wall including process start",
-            "cpu_model": cpu_model()}
+                      f"decompress each, {wall:.2f} s wall including process start", **host_cpus()}
 
 
 def roundtrip(Z, torch, x, kw, steps=3, warmup=1):
@@ -196,6 +229,9 @@ def bench_cosmo_extras(Z, torch, n, steps=3):
         row, xr, st = roundtrip(Z, torch, x, kw, steps=steps)
         row.update(quality_row(Z, x, xr, st.eb_used))
         row["eb_rel"] = extra["eb_rel"]
+        S = x.numel() * x.element_size()
+        row["roofline"] = stage_roofline(row["stage_ms"], S, int(round(S / row["compression_factor"])), x.numel(),
+                                         1 if st.m_used <= 8 else 2)
         out[name] = row
         del x, xr
         torch.cuda.empty_cache()
@@ -317,15 +353,21 @@ def bench_batched(Z, torch, count=64, reps=5):
             "quality": {"min_psnr_db": round(min_psnr, 3), "max_err_over_eb": round(worst_ratio, 6)}}
 
 
-def bench_served(Z, torch, rates=(50, 500), durations=(2.0, 0.4), slots=8, budget=24 << 30):
+def bench_served(Z, torch, rates=(10, 20, 50, 100, 200, 500), durations=(3.0, 2.0, 1.0, 0.8, 0.6, 0.4), slots=8,
+                 budget=6 << 30):
     """Served form: Poisson arrivals of compress/decompress requests (sizes
     lognormal, median 32 MB, clipped to [1 MB, 2 GB], 80/20 f32/f64, 1-3D,
-    relative bounds 1e-6..1e-3) through the request server with `slots`
-    concurrent slots, against the same server with one slot (a plain
-    sequential FIFO).  Latency = completion - arrival."""
+    relative bounds 1e-6..1e-3) at each rate, through the request server with
+    `slots` concurrent slots and an HBM budget that binds (a request's input,
+    output capacity and workspace count against it; the largest request
+    needs about 5 GB), against plain per-call sz_compress / sz_decompress on
+    one host thread in arrival order (a sequential FIFO).  Decompress
+    requests carry the host copy of their container header, as a client that
+    made the container has it.  Latency = completion - arrival."""
     import fieldgen as F
     import fieldgen.gpu as G
     out = {"slots": slots, "hbm_budget_bytes": int(budget), "rates": []}
+    ctx = Z.context(0)
     for k, (rate, duration) in enumerate(zip(rates, durations)):
         reqs = F.request_stream(rate, duration, seed=F.BASE_SEED + 40 + k)
         print(f"[bench] served: rate {rate}/s, {len(reqs)} requests", file=sys.stderr, flush=True)
@@ -334,46 +376,82 @@ def bench_served(Z, torch, rates=(50, 500), durations=(2.0, 0.4), slots=8, budge
             data.append(G.request_field(r))
             torch.cuda.synchronize()
         kws = [dict(layers=1, m=8, eb_mode="rel", eb_rel=r["eb_rel"]) for r in reqs]
-        print("[bench] served: inputs made", file=sys.stderr, flush=True)
-        comps = {}
+        comps, hdrs = {}, {}
         for i, r in enumerate(reqs):
             if r["op"] == "decompress":
                 comps[i] = Z.compress(data[i], **kws[i])[0].clone()
+                hdrs[i] = comps[i][:HEADER].cpu().numpy().tobytes()
         torch.cuda.synchronize()
-        print("[bench] served: containers made", file=sys.stderr, flush=True)
+        print("[bench] served: inputs and containers made", file=sys.stderr, flush=True)
         nbytes = sum(x.numel() * x.element_size() for x in data)
-        row = {"rate": rate, "duration_s": duration, "requests": len(reqs), "bytes": int(nbytes)}
-        for mode, ns in (("served", slots), ("sequential", 1)):
-            outs = []
-            for i, (r, x) in enumerate(zip(reqs, data)):
-                if r["op"] == "compress":
-                    cap = Z.sz_compress_bound(Z.make_params(tuple(x.shape), x.dtype, **kws[i]))
-                    outs.append(torch.empty(cap, dtype=torch.uint8, device="cuda"))
-                else:
-                    outs.append(torch.empty_like(x))
-            srv = Z.Server(budget, ns)
-            ids = []
+        row = {"rate": rate, "duration_s": duration, "requests": len(reqs), "bytes": int(nbytes),
+               "largest_request_bytes": int(max(x.numel() * x.element_size() for x in data))}
+        outs = []
+        for i, (r, x) in enumerate(zip(reqs, data)):
+            if r["op"] == "compress":
+                cap = Z.sz_compress_bound(Z.make_params(tuple(x.shape), x.dtype, **kws[i]))
+                outs.append(torch.empty(cap, dtype=torch.uint8, device="cuda"))
+            else:
+                outs.append(torch.empty_like(x))
+        for mode in ("served", "plain"):
             t0 = time.perf_counter()
-            for i, r in enumerate(reqs):
-                dt = t0 + r["t"] - time.perf_counter()
-                if dt > 0:
-                    time.sleep(dt)
-                if r["op"] == "compress":
-                    ids.append(srv.submit_compress(data[i], outs[i], **kws[i]))
-                else:
-                    ids.append(srv.submit_decompress(comps[i], outs[i]))
-            res = []
-            for n_done, i in enumerate(ids):
-                res.append(srv.wait(i, timeout_ms=120000))
-                if n_done % 50 == 49:
-                    print(f"[bench] served: {mode} {n_done + 1} done", file=sys.stderr, flush=True)
-            stats = srv.stats()
-            print(f"[bench] served: {mode} finished", file=sys.stderr, flush=True)
-            srv.close()
-            qrow = None
             if mode == "served":
-                # on-device distortion of every served compress result and
-                # every decompress result against its original field
+                srv = Z.Server(budget, slots)
+                ids = []
+                for i, r in enumerate(reqs):
+                    dt = t0 + r["t"] - time.perf_counter()
+                    if dt > 0:
+                        time.sleep(dt)
+                    if r["op"] == "compress":
+                        ids.append(srv.submit_compress(data[i], outs[i], **kws[i]))
+                    else:
+                        ids.append(srv.submit_decompress(comps[i], outs[i], header=hdrs[i]))
+                res = []
+                for n_done, i in enumerate(ids):
+                    res.append(srv.wait(i, timeout_ms=120000))
+                    if n_done % 50 == 49:
+                        print(f"[bench] served: {n_done + 1} done", file=sys.stderr, flush=True)
+                stats = srv.stats()
+                srv.close()
+                lat = np.array([x["t_done"] - x["t_submit"] for x in res]) * 1e3
+                wait = np.array([x["t_admit"] - x["t_submit"] for x in res]) * 1e3
+                span = max(x["t_done"] for x in res) - min(x["t_submit"] for x in res)
+                errs = sum(1 for x in res if x["status"])
+                codes = sorted({int(x["status"]) for x in res if x["status"]})
+            else:
+                # plain calls, one at a time in arrival order, each waiting for
+                # its arrival; latency from arrival to the call's return
+                stream = torch.cuda.current_stream().cuda_stream
+                lat, errs, codes = [], 0, set()
+                for i, r in enumerate(reqs):
+                    dt = t0 + r["t"] - time.perf_counter()
+                    if dt > 0:
+                        time.sleep(dt)
+                    if r["op"] == "compress":
+                        p = Z.make_params(tuple(data[i].shape), data[i].dtype, **kws[i])
+                        rc, _, _ = Z.sz_compress(ctx, p, data[i].data_ptr(), outs[i].data_ptr(), outs[i].numel(),
+                                                 stream)
+                    else:
+                        rc = Z.sz_decompress(ctx, comps[i].data_ptr(), comps[i].numel(), outs[i].data_ptr(),
+                                             outs[i].numel() * outs[i].element_size(), stream)
+                    errs += rc != 0
+                    if rc:
+                        codes.add(int(rc))
+                    lat.append(time.perf_counter() - (t0 + r["t"]))
+                lat = np.array(lat) * 1e3
+                span = time.perf_counter() - (t0 + reqs[0]["t"])
+            print(f"[bench] served: {mode} finished", file=sys.stderr, flush=True)
+            row[mode] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+                         "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                         "GBps": round(nbytes / span / 1e9, 3), "errors": int(errs),
+                         "error_codes": sorted(codes)}
+            if mode == "served":
+                row[mode].update({"admission_wait_p50_ms": round(float(np.percentile(wait, 50)), 3),
+                                  "admission_wait_p99_ms": round(float(np.percentile(wait, 99)), 3),
+                                  "max_in_flight": stats["max_in_flight"],
+                                  "peak_footprint_bytes": stats["pool_peak_bytes"]})
+                # on-device distortion of every compress result and every
+                # decompress result against its original field
                 worst, min_psnr = 0.0, float("inf")
                 for i, r in enumerate(reqs):
                     if res[i]["status"]:
@@ -386,20 +464,9 @@ def bench_served(Z, torch, rates=(50, 500), durations=(2.0, 0.4), slots=8, budge
                     worst = max(worst, q["max_abs_err"] / (kws[i]["eb_rel"] * q["value_range"]))
                     min_psnr = min(min_psnr, q["psnr"])
                     del xr
-                qrow = {"min_psnr_db": round(min_psnr, 3), "max_err_over_eb": round(worst, 6)}
-            bad = [x["status"] for x in res if x["status"]]
-            lat = np.array([x["t_done"] - x["t_submit"] for x in res]) * 1e3
-            span = max(x["t_done"] for x in res) - min(x["t_submit"] for x in res)
-            row[mode] = {"p50_ms": round(float(np.percentile(lat, 50)), 3),
-                         "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                         "GBps": round(nbytes / span / 1e9, 3), "errors": len(bad),
-                         "max_in_flight": stats["max_in_flight"],
-                         "pool_peak_bytes": stats["pool_peak_bytes"]}
-            if qrow:
-                row[mode]["quality"] = qrow
-            del outs
+                row[mode]["quality"] = {"min_psnr_db": round(min_psnr, 3), "max_err_over_eb": round(worst, 6)}
         out["rates"].append(row)
-        del data, comps
+        del outs, data, comps
         torch.cuda.empty_cache()
     return out
 
@@ -513,16 +580,11 @@ def main():
 
     # dominant kernel stage and its algorithmic bytes per launch
     per_call = {k: (ms / calls if calls else 0.0) for k, (ms, calls) in prof.items()}
-    # algorithmic bytes per launch: the sweep reads the field and writes one
-    # code byte per point (m = 8); the reconstruction reads the codes and
-    # writes the field; the coder reads the codes and writes the container
     npts = S // 4
-    alg_per_stage = {"range": S, "sweep_compress": S + npts, "encode": npts + Cb, "decode": Cb + npts,
-                     "sweep_decompress": npts + S, "unpred": 0, "dectab": 0, "codebook": 0, "hist": npts}
-    dom = max(("sweep_compress", "sweep_decompress", "encode", "decode", "range"), key=lambda k: per_call[k])
-    dom_ms = per_call[dom]
-    achieved = alg_per_stage[dom] / (dom_ms / 1e3) / 1e9
-    traffic = load_traffic(dom, f"cosmo{n}", alg_per_stage[dom])
+    roof = stage_roofline(per_call, S, Cb, npts, 1)
+    dom, dom_ms = roof["kernel"], roof["launch_ms"]
+    traffic = load_traffic(dom, f"cosmo{n}", roof["algorithmic_bytes_per_launch"])
+    roof["traffic"] = traffic
 
     res = {
         "metric": METRIC,
@@ -553,11 +615,7 @@ def main():
         "n_unpred": int(st.n_unpred),
         "quality": quality,
         "stage_ms": {k: round(v, 4) for k, v in per_call.items()},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2),
-                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic,
-                     "algorithmic_bytes_per_launch": int(alg_per_stage[dom]),
-                     "launch_ms": round(dom_ms, 4)},
+        "roofline": roof,
     }
     x_host = xd.cpu().numpy() if not args.no_cpu_baseline else None
     x_slab = x_host[: args.cpu_planes] if x_host is not None else None

@@ -124,7 +124,8 @@ def request_field(req, device="cuda"):
     sin(0.05x) cos(0.04y) sin(0.03z) + N(0, 1e-3) in 3D."""
     import torch
     shape, sd = req["shape"], req["seed"]
-    dt = torch.float32 if str(req["dtype"]).endswith("float32") else torch.float64
+    import numpy as np
+    dt = torch.float32 if np.dtype(req["dtype"]) == np.float32 else torch.float64
     g = _gen(sd, device)
     if len(shape) == 1:
         n = shape[0]
