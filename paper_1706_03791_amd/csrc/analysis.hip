@@ -345,7 +345,7 @@ int survey_t(sz_ctx* ctx, const sz_params* p, const Layout& Lf, const void* d_in
     q.layers = nl;
     Layout L;
     if ((rc = resolve(&q, L))) return rc;
-    need = std::max(need, carve_comp(L, nullptr, nullptr, true));
+    need = std::max(need, carve_comp(L, nullptr, nullptr, true, xchg_reserve(ctx)));
   }
   // the sweep carves from ctx->arena; keep the sample in a buffer of its own
   T* samp = nullptr;
@@ -374,7 +374,7 @@ int survey_t(sz_ctx* ctx, const sz_params* p, const Layout& Lf, const void* d_in
     // decompressed neighbours: one sweep at m = 1, unpredictable count = H[0]
     if ((rc = enqueue_compress_t<T>(ctx, L, &q, samp, nullptr, 0, st, true))) break;
     CompWs W;
-    carve_comp(L, (uint8_t*)ctx->arena, &W, true);
+    carve_comp(L, (uint8_t*)ctx->arena, &W, true, ctx->xres_used);
     uint32_t h0 = 0;
     HIPCHK(hipMemcpyAsync(&h0, W.hist, 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(ctx->h_plan, ctx->plan, sizeof(DevPlan), hipMemcpyDeviceToHost, st));

@@ -204,7 +204,7 @@ int sz_quantize(sz_ctx* ctx, const sz_params* p, const void* d_in, uint16_t* d_c
                          : enqueue_compress_t<double>(ctx, L, &q, d_in, nullptr, 0, st, true);
   if (rc) return rc;
   CompWs W;
-  carve_comp(L, (uint8_t*)ctx->arena, &W, true);
+  carve_comp(L, (uint8_t*)ctx->arena, &W, true, ctx->xres_used);
   HIPCHK(hipMemcpyAsync(d_codes, W.codes, (size_t)L.n * 2, hipMemcpyDeviceToDevice, st));
   if (d_xprime) HIPCHK(hipMemcpyAsync(d_xprime, W.xs, (size_t)L.n * L.ts, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(ctx->h_plan, ctx->plan, sizeof(DevPlan), hipMemcpyDeviceToHost, st));

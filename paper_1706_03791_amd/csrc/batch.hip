@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(NT) b_sweep(const BJob* J, const uint32_t* tst
   if (P->status != 0 || (pass2 && !P->rerun)) return;
   constexpr int AZ = WaveShape<T>::AZ;
   if (j.kind == BK_WAVE3)
-    wsweep_body<T, CT, true, NT / 64, AZ, false>(j.wa, t, sz_lds);
+    wsweep_body<T, CT, true, NT / 64, AZ, false>(j.wa, t, sz_lds, pass2);
   else if (j.kind == BK_LEG2)
     sweep_body<T, CT, 2, 1, true, 1, NT>(j.sa, t, sz_lds);
   else if (j.kind == BK_LEG1)
@@ -431,7 +431,7 @@ void fill_jobs(sz_batch* b, const BPlan& P, const void* const* d_in, void* const
     a.plan = j.plan;
     a.pass2 = 0;
     a.export_all = 0;
-    if (L.wave) j.wa = make_wargs(L, d_in[i], j.w.codes, nullptr, j.w.xchg, j.w.progress, j.w.ticket, j.plan);
+    if (L.wave) j.wa = make_wargs(L, d_in[i], j.w.codes, nullptr, j.w.xchg, j.w.ticket, j.plan);
   }
 }
 
@@ -551,6 +551,9 @@ int activate(sz_batch* b, int cand) {
   if (rc) return rc;
   if (hipDeviceSynchronize() != hipSuccess) return SZ_EHIP;
   if ((rc = ensure_batch_arena(b, P.arena))) return rc;
+  // The wave sweep tells the exchange records of a launch by their tag: a new
+  // layout starts from an arena holding none of anything else.
+  if (hipMemset(b->arena, 0, P.arena) != hipSuccess) return SZ_EHIP;
   if (b->d_tstart) (void)hipFree(b->d_tstart);
   b->d_tstart = nullptr;
   if (hipMalloc(&b->d_tstart, sizeof(uint32_t) * (b->n + 1)) != hipSuccess) return SZ_ENOMEM;

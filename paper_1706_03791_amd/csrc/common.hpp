@@ -44,6 +44,7 @@ struct DevPlan {
   uint32_t xorc;         // unpredictable values XOR-coded (container flag bit 1)
   uint32_t max_len;
   uint64_t out_cap;
+  uint32_t epoch;        // launches on this plan so far (kept across inits): tags exchange records
 };
 
 // --------------------------------------------------------------- geometry

@@ -79,6 +79,11 @@ __device__ __forceinline__ void zero_container_kernel_dev(uint32_t* out, const D
        i += (uint64_t)gridDim.x * blockDim.x)
     out[i] = 0;
 }
+// Zero n 16-byte words.
+__global__ void zero16_kernel(uint4* p, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = make_uint4(0, 0, 0, 0);
+}
 __global__ void zero_container_kernel(uint32_t* out, const DevPlan* P) {
   zero_container_kernel_dev(out, P);
 }
@@ -103,6 +108,7 @@ __device__ __forceinline__ void plan_init_kernel_dev(DevPlan* P, PlanInit I) {
     z.minmax64[1] = 0;
     z.out_cap = I.cap;
     z.xorc = I.xorc;
+    z.epoch = P->epoch + 1;  // a new tag for this launch's exchange records
     *P = z;
   }
 }

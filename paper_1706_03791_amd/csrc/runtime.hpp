@@ -42,6 +42,11 @@ struct sz_ctx {
   void* arena = nullptr;
   size_t arena_size = 0;
   bool fixed_arena = false;        // arena memory lent by someone else: never (re)allocated here
+  // The first xclean_bytes of the arena at xclean hold nothing but zeros and
+  // tagged exchange records of this context's launches (wave sweep).
+  void* xclean = nullptr;
+  size_t xclean_bytes = 0;
+  size_t xres_used = 0;  // exchange reserve of the last workspace carve (carve again with it)
   void* scratch = nullptr;         // this device's static scratch (no-allocation entry point)
   int dbg_sched = 0;               // sz_ctx_debug_sweep: 1 = row-per-thread tiles for every field
   uint32_t dbg_claim = 0;          // sz_ctx_debug_sweep: tile claim order
@@ -223,9 +228,11 @@ int resolve(const sz_params* p, Layout& L, const Sched* sched_override = nullptr
     const uint64_t nsteps = (uint64_t)L.blk3[2] + (tz - 1) + (kWLanes - 1);
     L.nsp = (uint32_t)(ceil_div(nsteps + kWLanes + tz + 4 * kWG, 16) * 16);
     L.ne = 0;
-    L.xy_bytes = (uint64_t)g.ntiles * nw * L.nsp * 8;  // 8-byte records
+    // tagged records: 16 bytes per step along y, 8 bytes per 32-bit word of
+    // a value along z
+    L.xy_bytes = (uint64_t)g.ntiles * nw * L.nsp * 16;
     // z-exchange records only when a block holds several tiles along z
-    const uint64_t xz_bytes = g.tz_per_blk > 1 ? (uint64_t)g.ntiles * 2 * 64 * L.nsp * L.ts : 0;
+    const uint64_t xz_bytes = g.tz_per_blk > 1 ? (uint64_t)g.ntiles * 2 * 64 * L.nsp * (2 * L.ts) : 0;
     L.xchg_bytes = L.xy_bytes + xz_bytes;
     // elements one tile's input and code descriptors span past their base
     const uint64_t rows = L.ndim == 2 ? (uint64_t)kWLanes + 1 : ((uint64_t)tz + 1) * L.dims3[1];
@@ -268,13 +275,19 @@ struct CompWs {
   uint32_t *gpar, *ganc, *gdep;
 };
 
-size_t carve_comp(const Layout& L, uint8_t* base, CompWs* W, bool keep_values = false) {
+// Bytes of the exchange region the sweep of L uses, and those a workspace
+// reserves for it: at least `reserve`, the part of the region an earlier
+// call kept clean (xchg_reserve).  The region comes first in a workspace.
+inline uint64_t xchg_need(const Layout& L) { return (L.xchg_bytes + 512 + 15) & ~(uint64_t)15; }
+inline size_t xchg_reserve(const sz_ctx* ctx) { return ctx->fixed_arena ? 0 : ctx->xclean_bytes; }
+
+size_t carve_comp(const Layout& L, uint8_t* base, CompWs* W, bool keep_values = false, size_t reserve = 0) {
   Carve c{base};
   const uint64_t nt = ceil_div(L.n_chunks, 4096) + 1;
   CompWs w;
+  w.xchg = c.take<uint8_t>(std::max<uint64_t>(xchg_need(L), reserve));
   w.codes = c.take<uint8_t>((L.n + 64) * L.cw);
   w.xs = keep_values ? c.take<uint8_t>(L.n * L.ts) : nullptr;
-  w.xchg = c.take<uint8_t>(L.xchg_bytes + 512);
   w.hist = c.take<uint32_t>(65536 * 4);
   w.hpart = L.cw == 1 ? c.take<uint32_t>(kHistBlocks * 256 * 4)
                        : c.take<uint32_t>((size_t)2 * hist2_blocks((uint64_t)L.n) * kHist2Half * 4);
@@ -310,6 +323,8 @@ int ensure_arena(sz_ctx* ctx, size_t bytes) {
     ctx->arena = nullptr;
     ctx->arena_size = 0;
   }
+  ctx->xclean = nullptr;
+  ctx->xclean_bytes = 0;
   size_t want = bytes + bytes / 8;
   if (hipMalloc(&ctx->arena, want) != hipSuccess) {
     ctx->arena = nullptr;
@@ -317,6 +332,38 @@ int ensure_arena(sz_ctx* ctx, size_t bytes) {
   }
   ctx->arena_size = want;
   return SZ_OK;
+}
+
+// Zero `bytes` (a multiple of 16) at p, on st (a fill kernel: no memset
+// node in a captured graph).
+void zero_bytes(void* p, uint64_t bytes, hipStream_t st) {
+  const uint64_t n = bytes / 16;
+  if (!n) return;
+  const uint64_t g = std::min<uint64_t>(ceil_div(n, 256), 1024);
+  hipLaunchKernelGGL(zero16_kernel, dim3((unsigned)g), dim3(256), 0, st, (uint4*)p, n);
+}
+
+// Before a sweep that uses the exchange region at xchg.  The wave sweep polls
+// records its writer may not have stored yet and tells them by their tag, so
+// the region must hold nothing but zeros and this plan's earlier records:
+// the part the context knows to be clean is kept, the rest is cleared (all
+// of it for a lent arena, whose earlier contents are unknown).  The other
+// sweeps write untagged records, after which nothing is known to be clean.
+void prepare_xchg(sz_ctx* ctx, const Layout& L, void* xchg, hipStream_t st) {
+  if (!L.wave) {
+    ctx->xclean = nullptr;
+    ctx->xclean_bytes = 0;
+    return;
+  }
+  const uint64_t need = xchg_need(L);
+  const bool known = !ctx->fixed_arena && xchg == ctx->xclean;
+  const uint64_t clean = known ? ctx->xclean_bytes : 0;
+  if (need > clean) zero_bytes((uint8_t*)xchg + clean, need - clean, st);
+  if (!ctx->fixed_arena) {
+    // the workspace reserved max(need, clean) bytes for the region
+    ctx->xclean = xchg;
+    ctx->xclean_bytes = std::max<uint64_t>(need, clean);
+  }
 }
 
 int launch_sweep(const Layout& L, bool comp, const SweepArgs& a, hipStream_t st) {
@@ -334,8 +381,8 @@ int launch_sweep(const Layout& L, bool comp, const SweepArgs& a, hipStream_t st)
   return e == hipSuccess ? SZ_OK : SZ_EHIP;
 }
 
-WArgs make_wargs(const Layout& L, const void* x, void* codes, void* xo, void* xchg, uint32_t* progress,
-                 uint32_t* ticket, DevPlan* P) {
+WArgs make_wargs(const Layout& L, const void* x, void* codes, void* xo, void* xchg, uint32_t* ticket,
+                 DevPlan* P) {
   WArgs a;
   for (int d = 0; d < 3; d++) {
     a.dims[d] = L.dims3[d];
@@ -356,7 +403,6 @@ WArgs make_wargs(const Layout& L, const void* x, void* codes, void* xo, void* xc
   a.n_unpred = 0;
   a.codes_cap = (uint64_t)L.n + 64;
   a.n = (uint64_t)L.n;
-  a.progress = progress;
   a.ticket = ticket;
   a.plan = P;
   a.pass2 = 0;
@@ -439,10 +485,11 @@ template <typename T>
 int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const void* d_in, void* d_out, size_t cap,
                        hipStream_t st, bool debug_codes_only) {
   CompWs W;
-  const size_t need = carve_comp(L, nullptr, nullptr, debug_codes_only);
+  const size_t need = carve_comp(L, nullptr, nullptr, debug_codes_only, xchg_reserve(ctx));
   int rc = ensure_arena(ctx, need);
   if (rc) return rc;
-  carve_comp(L, (uint8_t*)ctx->arena, &W, debug_codes_only);
+  ctx->xres_used = xchg_reserve(ctx);  // (none after a new arena)
+  carve_comp(L, (uint8_t*)ctx->arena, &W, debug_codes_only, ctx->xres_used);
   DevPlan* P = ctx->plan;
   const bool adaptive = L.m_req == 0;
   PlanInit I;
@@ -483,10 +530,11 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
   a.pass2 = 0;
   a.export_all = debug_codes_only ? 1 : 0;
   a.claim = ctx->dbg_claim;
+  prepare_xchg(ctx, L, W.xchg, st);
   stage_begin(ctx, ST_SWEEP_C, st);
   int sweep_stage_open = ST_SWEEP_C;
   if (L.wave) {
-    WArgs wa = make_wargs(L, d_in, W.codes, W.xs, W.xchg, W.progress, W.ticket, P);
+    WArgs wa = make_wargs(L, d_in, W.codes, W.xs, W.xchg, W.ticket, P);
     wa.export_all = a.export_all;
     wa.claim = ctx->dbg_claim;
     if ((rc = launch_wsweep(L, true, wa, st))) return rc;
@@ -661,9 +709,10 @@ struct DecWs {
   uint64_t *xts_u, *xts_r;
 };
 
-size_t carve_dec(const Layout& L, uint64_t U, uint8_t* base, DecWs* W) {
+size_t carve_dec(const Layout& L, uint64_t U, uint8_t* base, DecWs* W, size_t reserve = 0) {
   Carve c{base};
   DecWs w;
+  w.xchg = c.take<uint8_t>(std::max<uint64_t>(xchg_need(L), reserve));
   const uint64_t ngr = ceil_div(U, 1024) + 1;
   w.codes = c.take<uint8_t>((L.n + 64) * L.cw);
   w.boff = c.take<uint64_t>(L.n_chunks * 8);
@@ -681,7 +730,6 @@ size_t carve_dec(const Layout& L, uint64_t U, uint8_t* base, DecWs* W) {
   w.tsum_r = c.take<uint64_t>((ceil_div(ngr, 4096) + 1) * 8);
   w.progress = c.take<uint32_t>((L.g.ntiles + 1) * 4);
   w.ticket = w.progress + L.g.ntiles;
-  w.xchg = c.take<uint8_t>(L.xchg_bytes + 512);
   w.xcz = nullptr;
   w.xuoff = w.xroff = w.xts_u = w.xts_r = nullptr;
   if (L.xorc) {
@@ -713,9 +761,10 @@ int enqueue_decompress_t(sz_ctx* ctx, const Layout& L, const Hdr& h, const void*
                          hipStream_t st) {
   DecWs W;
   const uint64_t U = h.n_unpred;
-  int rc = ensure_arena(ctx, carve_dec(L, U, nullptr, nullptr));
+  int rc = ensure_arena(ctx, carve_dec(L, U, nullptr, nullptr, xchg_reserve(ctx)));
   if (rc) return rc;
-  carve_dec(L, U, (uint8_t*)ctx->arena, &W);
+  ctx->xres_used = xchg_reserve(ctx);  // (none after a new arena)
+  carve_dec(L, U, (uint8_t*)ctx->arena, &W, ctx->xres_used);
   DevPlan* P = ctx->plan;
   PlanInit I = {};
   I.m = h.m;
@@ -795,8 +844,9 @@ int enqueue_decompress_t(sz_ctx* ctx, const Layout& L, const Hdr& h, const void*
   a.pass2 = 0;
   a.export_all = 0;
   a.claim = ctx->dbg_claim;
+  prepare_xchg(ctx, L, W.xchg, st);
   if (L.wave) {
-    WArgs wa = make_wargs(L, nullptr, W.codes, d_out, W.xchg, W.progress, W.ticket, P);
+    WArgs wa = make_wargs(L, nullptr, W.codes, d_out, W.xchg, W.ticket, P);
     wa.claim = ctx->dbg_claim;
     wa.uvals = W.uvals;
     wa.useg = W.useg;

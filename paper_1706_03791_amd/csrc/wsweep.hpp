@@ -16,7 +16,8 @@
 // The dependence chain inside a workgroup therefore costs one step per row
 // and needs no LDS traffic along y.  Tiles are claimed through an atomic
 // ticket in dependence order and publish their boundary rows every kWG
-// steps with device-coherent stores followed by a relaxed progress flag.
+// steps as device-coherent records tagged with the launch (sweep_tag); the
+// next tile polls the records themselves, so no store is ever waited for.
 //
 // Input values (compress) and decompressed values (decompress) stream
 // through per-row LDS rings of two aligned chunks; codes stream through
@@ -33,16 +34,6 @@ namespace szh {
 constexpr int kWG = 8;       // steps per group (also the chunk length in elements)
 constexpr int kWRing = 16;   // ring slots per row: two chunks
 constexpr int kWLanes = 64;  // y-rows per tile
-// Steps of a group before a tile checks its predecessors' progress and
-// loads the next group's halo, and the step after which it reads that
-// progress (measured per direction: compression checks after the last step).
-template <bool COMP>
-struct HaloSteps {
-  static constexpr int kHalo = COMP ? 8 : 7;
-  static constexpr int kPoll = COMP ? 7 : 4;
-  static_assert(kPoll < kHalo && kHalo <= kWG, "progress is read before it is checked, inside the group");
-};
-
 struct WArgs {
   int64_t dims[3];   // Z, Y, X
   int64_t blk[3];
@@ -52,14 +43,13 @@ struct WArgs {
   const void* x;     // compress: input field
   void* codes;       // compress: output codes; decompress: input codes
   void* xo;          // compress (debug): every recorded value; decompress: output field
-  void* xy;          // exchange towards the next tile along y: [tile][wave][step][AZ]
+  void* xy;          // exchange towards the next tile along y: [tile][wave][step] tagged records
   void* xz;          // exchange towards the next tile along z: [tile][out | y-moved][group][piece][lane]
   const void* uvals; // decompress: unpredictable values in raster order
   const uint64_t* useg;
   uint64_t n_unpred;
   uint64_t codes_cap;  // elements in the code workspace
   uint64_t n;
-  uint32_t* progress;
   uint32_t* ticket;
   DevPlan* plan;
   uint32_t pass2;
@@ -182,24 +172,60 @@ __device__ __forceinline__ T rec_elem(u32x2 v, int a) {
     return __builtin_bit_cast(T, ((uint64_t)v[1] << 32) | v[0]);
 }
 
+// Exchange records carry the launch's tag in every 8-byte unit: a 32-bit
+// payload and the tag.  An aligned 8-byte access is a single unit, so a
+// reader that finds the tag has this launch's payload, whatever the order in
+// which the units of a record or of a group become visible; every record slot
+// is written once per launch, slots of earlier launches hold older tags, and
+// cleared memory holds none.  The tag sets bit 31, so it is never zero.
+__device__ __forceinline__ uint32_t sweep_tag(const DevPlan* P, uint32_t pass2) {
+  return 0x80000000u | (P->epoch << 1) | (pass2 & 1u);
+}
+// A 16-byte piece of z-records: two f32 values, or one f64 value.
+template <typename T>
+__device__ __forceinline__ u32x4 tag_piece(const T* v, uint32_t tag) {
+  if constexpr (sizeof(T) == 4) {
+    return u32x4{__builtin_bit_cast(uint32_t, v[0]), tag, __builtin_bit_cast(uint32_t, v[1]), tag};
+  } else {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v[0]);
+    return u32x4{(uint32_t)b, tag, (uint32_t)(b >> 32), tag};
+  }
+}
+// Value e of a tagged piece (e < 2 for f32, 0 for f64).
+template <typename T>
+__device__ __forceinline__ T piece_value(u32x4 p, int e) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, (uint32_t)p[2 * e]);
+  else
+    return __builtin_bit_cast(T, ((uint64_t)p[2] << 32) | p[0]);
+}
+
 // LDS of one workgroup of the wave-tiled sweep (dynamic allocation).
+// The z-exchange between waves is a ring of one entry per step of a group:
+// entry e, slot s holds the value of a step e (mod kWG) of the row below
+// wave s, that is wave s - 1's last sub-row, or for s = 0 the tile's
+// z-halo, which wave 0 writes for a whole group at the end of the group
+// before.  Every wave thus reads the row below at the same offsets.
 template <typename T, int NW, int AZ>
 struct WSweepLds {
   static constexpr size_t OFF_RING = 0;
   static constexpr size_t OFF_XW = OFF_RING + sizeof(T) * NW * AZ * kWRing * 64;
-  static constexpr size_t OFF_YIN = OFF_XW + sizeof(T) * 2 * NW * 2 * 64;
+  static constexpr size_t OFF_YIN = OFF_XW + sizeof(T) * kWG * (NW + 1) * 2 * 64;
   static constexpr size_t BYTES = OFF_YIN + 8 * NW * kWG;
 };
 
 // One tile of the wave-tiled sweep, run by a workgroup of NW waves; `lds` is
-// WSweepLds::BYTES of dynamic LDS.
+// WSweepLds::BYTES of dynamic LDS; pass2 marks the second sweep of an
+// adaptive compression.
 template <typename T, typename CT, bool COMP, int NW, int AZ, bool DBG>
-__device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint8_t* lds) {
+__device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile_in, uint8_t* lds, const uint32_t pass2) {
+  // the tile is the same for every lane: keep everything derived from it in
+  // scalar registers
+  const int tile = __builtin_amdgcn_readfirstlane(tile_in);
   using U = typename FTr<T>::U;
   using CW = CWord<CT>;
   constexpr int G = kWG;
   constexpr int TZ = NW * AZ;
-  constexpr int kHaloStep = HaloSteps<COMP>::kHalo, kPollStep = HaloSteps<COMP>::kPoll;
   constexpr int SB = 8 * sizeof(CT);
   constexpr int XPC = (G * (int)sizeof(T)) / 16;  // 16-byte pieces per chunk of values
   constexpr int EPP = 16 / (int)sizeof(T);        // values per piece
@@ -208,18 +234,17 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   using LD = WSweepLds<T, NW, AZ>;
   // per-row input (compress) or output (decompress) rings
   auto& s_ring = *reinterpret_cast<T (*)[NW][AZ][kWRing][64]>(lds + LD::OFF_RING);
-  // last sub-row of each wave: [step parity][wave][out | moved][lane]
-  auto& s_xw = *reinterpret_cast<T (*)[2][NW][2][64]>(lds + LD::OFF_XW);
+  // the row below each wave: [step mod G][wave + 1 | 0 for the z-halo][out | moved][lane]
+  auto& s_xw = *reinterpret_cast<T (*)[G][NW + 1][2][64]>(lds + LD::OFF_XW);
   auto& s_yin = *reinterpret_cast<u32x2 (*)[NW][kWG]>(lds + LD::OFF_YIN);   // y-halo records, one per step
 
   DevPlan* P = A.plan;
   if (P->status != 0) return;
-  if (A.pass2 && !P->rerun) return;
+  if (pass2 && !P->rerun) return;
 
   const int tid = threadIdx.x;
-  const int w = NW == 1 ? 0 : tid >> 6, ly = tid & 63;
-  const int wprev = w > 0 ? w - 1 : 0;
-  for (int i = tid; i < 2 * NW * 2 * 64; i += NW * 64) (&s_xw[0][0][0][0])[i] = T(0);
+  const int w = NW == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid >> 6), ly = tid & 63;
+  for (int i = tid; i < G * (NW + 1) * 2 * 64; i += NW * 64) (&s_xw[0][0][0][0])[i] = T(0);
   __syncthreads();
 
   // ---- tile geometry
@@ -239,6 +264,9 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   const int BX = (int)(xb1 - xb0);
   const int nsteps = BX + (TZ - 1) + (kWLanes - 1);
   const int ngroups = (nsteps + G - 1) / G;
+  // groups run in pairs (the buffer sets alternate): an odd count gets one
+  // more group, in which no point is active
+  const int ngr = (ngroups + 1) & ~1;
   const int64_t yr = y0 + ly;
 
   int64_t rb[AZ];   // raster index of the row's first element
@@ -265,22 +293,24 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   const int e_eb = (int)(((U)P->ebT_bits >> FTr<T>::MANT) & (U)FTr<T>::EMAX);
 
   // ---- exchange descriptors (one each for all tiles; offsets < 2 GiB)
+  const uint32_t tag = sweep_tag(P, pass2);
   const uint64_t nsp = A.nsp;
-  const __amdgpu_buffer_rsrc_t ry =
-      make_rsrc(A.xy, (uint64_t)A.ntiles * NW * nsp * 8);
+  constexpr int VPP = sizeof(T) == 4 ? 2 : 1;  // values per tagged 16-byte piece
+  constexpr int ZP = G / VPP;                  // pieces per group of z-records
+  const __amdgpu_buffer_rsrc_t ry = make_rsrc(A.xy, (uint64_t)A.ntiles * NW * nsp * 16);
   // (no z-exchange when a block holds one tile along z: its loads read zero)
   const __amdgpu_buffer_rsrc_t rz =
-      make_rsrc(A.xz, A.tz_per_blk > 1 ? (uint64_t)A.ntiles * 2 * 64 * nsp * sizeof(T) : 0);
-  auto y_off = [&](int t, int step) -> int {  // 8-byte record of (tile t, wave w, step)
-    return (int)((((int64_t)t * NW + w) * (int64_t)nsp + step) * 8);
+      make_rsrc(A.xz, A.tz_per_blk > 1 ? (uint64_t)A.ntiles * 2 * 64 * nsp * (2 * sizeof(T)) : 0);
+  auto y_off = [&](int t, int step) -> int {  // 16-byte record of (tile t, wave w, step)
+    return (int)((((int64_t)t * NW + w) * (int64_t)nsp + step) * 16);
   };
-  // z records: [tile][out | y-moved][group][piece][lane] of 16-byte pieces,
-  // so one wave's access to a piece of a group is 1 KiB of whole cache lines
+  // z records: [tile][out | y-moved][group][piece][lane] of tagged pieces, so
+  // one wave's access to a piece of a group is 1 KiB of whole cache lines
   auto z_piece = [&](int t, int kind, int grp, int j) -> int {  // piece j of group grp of lane ly
-    return (int)((((((int64_t)t * 2 + kind) * (int64_t)(nsp / G) + grp) * XPC + j) * 64 + ly) * 16);
+    return (int)((((((int64_t)t * 2 + kind) * (int64_t)(nsp / G) + grp) * ZP + j) * 64 + ly) * 16);
   };
-  auto z_off = [&](int t, int kind, int idx) -> int {  // element idx (tile t, kind, lane ly)
-    return z_piece(t, kind, idx / G, (idx % G) / EPP) + (idx % EPP) * (int)sizeof(T);
+  auto z_unit = [&](int t, int kind, int idx) -> int {  // the tagged unit(s) of element idx (lane ly)
+    return z_piece(t, kind, idx / G, (idx % G) / VPP) + (idx % VPP) * 8;
   };
   constexpr int kOut = 0x7FFFFF00;  // offset past every descriptor: loads read zero
 
@@ -296,81 +326,64 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
            : make_rsrc((const CT*)A.codes + ebase, (uint64_t)max((int64_t)0, (int64_t)A.codes_cap - ebase) *
                                                        sizeof(CT));
 
-  // ---- waits on predecessor tiles: the records a group needs
-  // y records of steps [gr*G + 64, +G) are written by the predecessor's
-  // group (gr*G + 64 + G - 1) / G; z records of indices [gr*G + TZ, +G)
-  // (index k holds step k - 1) by its group (gr*G + TZ + G - 1) / G.
-  auto need_of = [&](int gr, int lead) -> uint32_t {  // progress a predecessor must reach for group gr
-    return (uint32_t)(((gr * G + lead + G - 1) / G + 1) * G);
+  // ---- halo records of group gr
+  // A predecessor writes its records of steps [0, ngr * G) along y and of
+  // indices [0, ngr * G] along z (index k holds step k - 1); later records
+  // are never needed by an active step and never waited for.  A missing
+  // predecessor is a descriptor of zero records (its loads read zero and
+  // touch no memory), chosen per tile in scalar registers.  Only wave 0
+  // loads and writes the z-halo.
+  const bool wave0 = w == 0;  // uniform: scalar selects below
+  // A predecessor stores records only for a successor with rows in the block
+  // (a tile past the block's edge waits for none: its points are inactive).
+  const bool need_y = pred_y >= 0 && y0 < yb1, need_z = pred_z >= 0 && z0 < zb1 && wave0;
+  const __amdgpu_buffer_rsrc_t ry_in = need_y ? ry : make_rsrc(A.xy, 0);
+  const __amdgpu_buffer_rsrc_t rz_in = need_z ? rz : make_rsrc(A.xz, 0);
+  const int pred_y0 = pred_y >= 0 ? pred_y : 0, pred_z0 = pred_z >= 0 ? pred_z : 0;
+  const int last_rec = ngr * G;  // y-steps below it and z-indices up to it are written
+  // y: lanes l and l + G hold the record of the values lane 0 needs at step gr*G + (l mod G)
+  auto load_yh = [&](int gr) -> u32x4 {
+    return __builtin_amdgcn_raw_buffer_load_b128(ry_in, y_off(pred_y0, gr * G + kWLanes + (ly & (G - 1))), 0,
+                                                 kCoherent);
   };
-  auto wait_preds = [&](int gr) {
-    if (tid == 0) {
-      const int preds[2] = {pred_z, pred_y};
-      const uint32_t needs[2] = {need_of(gr, TZ), need_of(gr, kWLanes)};
-      for (int q = 0; q < 2; q++) {
-        if (preds[q] < 0) continue;
-        uint32_t spins = 0;
-        while (__hip_atomic_load(&A.progress[preds[q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < needs[q]) {
-          if (__hip_atomic_load(&P->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-          if (++spins > kSpinLimit) {
-            atomicCAS(&P->status, 0, kStatusStalled);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
+  // z (wave 0): the moved and unmoved values of the row below at steps
+  // gr*G - 1 + i, records of indices gr*G + TZ + i (TZ is a multiple of VPP,
+  // so they form whole pieces)
+  auto load_zh = [&](int gr, u32x4 (&zo)[ZP], u32x4 (&zy)[ZP]) {
+    if (!wave0) return;  // (a uniform branch)
+#pragma unroll
+    for (int j = 0; j < ZP; j++) {
+      zo[j] = __builtin_amdgcn_raw_buffer_load_b128(rz_in, z_unit(pred_z0, 0, gr * G + TZ + VPP * j), 0, kCoherent);
+      zy[j] = __builtin_amdgcn_raw_buffer_load_b128(rz_in, z_unit(pred_z0, 1, gr * G + TZ + VPP * j), 0, kCoherent);
+    }
+  };
+  // Whether the halo of group gr holds this launch's records (wave-uniform).
+  auto halo_ok = [&](int gr, u32x4 yh, const u32x4 (&zo)[ZP], const u32x4 (&zy)[ZP]) -> bool {
+    const int ys = gr * G + kWLanes + (ly & (G - 1));
+    bool ok = !need_y || ys >= last_rec || (yh[1] == tag && yh[3] == tag);
+    if (need_z) {
+#pragma unroll
+      for (int j = 0; j < ZP; j++) {
+        const int k0 = gr * G + TZ + VPP * j, k1 = k0 + VPP - 1;  // indices of the piece's units
+        ok &= k0 > last_rec || (zo[j][1] == tag && zy[j][1] == tag);
+        ok &= k1 > last_rec || (zo[j][3] == tag && zy[j][3] == tag);
       }
     }
-    __syncthreads();
+    return __builtin_amdgcn_ballot_w64(!ok) == 0;
   };
-  // In the loop every wave reads its predecessors' progress itself: the
-  // reads go out after step kPollStep - 1 and are checked after step
-  // kHaloStep - 1 (HaloSteps), so a predecessor that is already far enough costs no
-  // round trip and no workgroup barrier.  Otherwise the wave polls.
-  const uint32_t* prog_z = &A.progress[pred_z >= 0 ? pred_z : tile];
-  const uint32_t* prog_y = &A.progress[pred_y >= 0 ? pred_y : tile];
-  auto ready_for = [&](int gr, uint32_t pz, uint32_t py) -> bool {
-    return (pred_z < 0 || pz >= need_of(gr, TZ)) && (pred_y < 0 || py >= need_of(gr, kWLanes));
-  };
-  auto wave_wait = [&](int gr, uint32_t pz, uint32_t py) {
+  // Reload the halo of group gr until it holds this launch's records (the
+  // predecessor is still writing it), or until the launch has failed.
+  auto poll_halo = [&](int gr, u32x4& yh, u32x4 (&zo)[ZP], u32x4 (&zy)[ZP]) {
     uint32_t spins = 0;
-    while (!ready_for(gr, pz, py)) {
+    while (!halo_ok(gr, yh, zo, zy)) {
       if (__hip_atomic_load(&P->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
       if (++spins > kSpinLimit) {
         if (ly == 0) atomicCAS(&P->status, 0, kStatusStalled);
         break;
       }
       __builtin_amdgcn_s_sleep(1);
-      pz = __builtin_amdgcn_readfirstlane(__hip_atomic_load(prog_z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-      py = __builtin_amdgcn_readfirstlane(__hip_atomic_load(prog_y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    }
-  };
-
-  // ---- halo records of group gr
-  // Loads are issued one group ahead and must stay straight-line code: a
-  // branch around them makes the compiler wait for their data at the join.
-  // A missing predecessor is a descriptor of zero records (its loads read
-  // zero), chosen per tile in scalar registers.  Only wave 0 needs the
-  // z-halo; the branch around its loads is uniform (`wave0` lives in scalar
-  // registers) and leaves the registers in place.
-  const bool wave0 = __builtin_amdgcn_readfirstlane(w) == 0;  // uniform: scalar selects below
-  const __amdgpu_buffer_rsrc_t ry_in = pred_y >= 0 ? ry : make_rsrc(A.xy, 0);
-  const __amdgpu_buffer_rsrc_t rz_in = (pred_z >= 0 && wave0) ? rz : make_rsrc(A.xz, 0);
-  const int pred_y0 = pred_y >= 0 ? pred_y : 0, pred_z0 = pred_z >= 0 ? pred_z : 0;
-  // y: lanes 0..G-1 hold the AZ values lane 0 needs at step gr*G + lane
-  auto load_yh = [&](int gr) -> u32x2 {
-    return __builtin_amdgcn_raw_buffer_load_b64(ry_in, y_off(pred_y0, gr * G + kWLanes + (ly & (G - 1))), 0,
-                                                kCoherent);
-  };
-  // z (wave 0): the moved and unmoved values of the row below at steps gr*G - 1 + i
-  // (TZ is a multiple of EPP whenever tiles exchange along z, so the records
-  // of indices gr * G + TZ on form whole pieces)
-  auto load_zh = [&](int gr, uint4 (&zo)[XPC], uint4 (&zy)[XPC]) {
-#pragma unroll
-    for (int j = 0; j < XPC; j++) {
-      const int o0 = z_off(pred_z0, 0, gr * G + TZ + EPP * j);
-      const int o1 = z_off(pred_z0, 1, gr * G + TZ + EPP * j);
-      zo[j] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rz_in, o0, 0, kCoherent));
-      zy[j] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rz_in, o1, 0, kCoherent));
+      yh = load_yh(gr);
+      load_zh(gr, zo, zy);
     }
   };
 
@@ -533,17 +546,27 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   for (int a = 0; a < AZ; a++) O1[a] = O2[a] = Y1[a] = Y2[a] = Y3[a] = T(0);
   T VO1 = T(0), VO2 = T(0), VY1 = T(0), VY2 = T(0), VY3 = T(0);  // row below sub-row 0
 
-  u32x2 yh_cur = {0, 0}, yh_nxt = {0, 0};
-  uint4 zo_cur[XPC], zy_cur[XPC], zo_nxt[XPC], zy_nxt[XPC];
+  // halo records of the next group, loaded during this one
+  u32x4 yh_nx = {0, 0, 0, 0};
+  u32x4 zo_nx[ZP], zy_nx[ZP];
 #pragma unroll
-  for (int j = 0; j < XPC; j++) zo_cur[j] = zy_cur[j] = zo_nxt[j] = zy_nxt[j] = make_uint4(0, 0, 0, 0);
-  T ezo[G], ezy[G];  // wave 3: records of indices g*G + i (index k = value of step k - 1)
+  for (int j = 0; j < ZP; j++) zo_nx[j] = zy_nx[j] = u32x4{0, 0, 0, 0};
+  T ezo[G], ezy[G];  // last wave: records of indices g*G + i (index k = value of step k - 1)
 #pragma unroll
   for (int i = 0; i < G; i++) ezo[i] = ezy[i] = T(0);
   T co = T(0), cy = T(0);  // value of the group's last step: record 0 of the next group
 
-  uint4 xpre[AZ][COMP ? XPC : 1];  // compress: prefetched input chunk
-  CW c0[AZ], c1[AZ], c2[AZ], cpre[AZ];  // decompress: code chunks of this window and two ahead
+  // compress: input chunks of groups g + 1 (entry 0) and g + 2 (entry 1)
+  uint4 xq2[2][AZ][COMP ? XPC : 1];
+#pragma unroll
+  for (int k = 0; k < 2; k++)
+#pragma unroll
+    for (int a = 0; a < AZ; a++)
+#pragma unroll
+      for (int h = 0; h < (COMP ? XPC : 1); h++) xq2[k][a][h] = make_uint4(0, 0, 0, 0);
+  // decompress: code chunks of this window, the three after it, and the one
+  // being loaded
+  CW c0[AZ], c1[AZ], c2[AZ], c3[AZ], cpre[AZ];
   CW cacc[AZ], cprv[AZ];           // compress: codes of this and the previous group's window
   CW chold[AZ];                    // compress: an even chunk waiting for its partner
   int64_t qhold[AZ];               // its index, -1 for none
@@ -565,7 +588,7 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   int zc[AZ];        // values this group consumes
 #pragma unroll
   for (int a = 0; a < AZ; a++) {
-    c0[a] = c1[a] = c2[a] = cpre[a] = cacc[a] = cprv[a] = chold[a] = (CW)0;
+    c0[a] = c1[a] = c2[a] = c3[a] = cpre[a] = cacc[a] = cprv[a] = chold[a] = (CW)0;
     qhold[a] = -1;
     cpk[a][0] = cpk[a][1] = 0;
     const int64_t q0 = wlo[a] >> 3;
@@ -624,25 +647,74 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
     }
   };
 
-  // ---- prologue: group 0's halo and input
-  wait_preds(0);
-  yh_cur = load_yh(0);
-  if (w == 0) {
-    load_zh(0, zo_cur, zy_cur);
-    // Rows before lane 0 run ahead of it: the y-halo row (skew -1) already
-    // produced x = 0 at step -1, and the corner row (z-1, y-1; skew -2) at
-    // step -2.  Their values enter the histories before step 0.
-    if (pred_y >= 0) {
-      const u32x2 r = __builtin_amdgcn_raw_buffer_load_b64(ry, y_off(pred_y, kWLanes - 1), 0, kCoherent);
-      const T v = rec_elem<T>(r, 0);
-      Y1[0] = ly == 0 ? v : T(0);
+  // The halo of a group into LDS: the y-records into s_yin, and the z-halo
+  // into slot 0 of the exchange ring, the value of step gr*G + i - 1 at entry
+  // (i - 1) mod G, where wave 0 reads it at step gr*G + i.  The other waves
+  // write their (unloaded) z registers to slot NW, which nobody reads: every
+  // path that loads a register then reads it, so the compiler's count of
+  // loads in flight stays exact and it adds no waits of its own.
+  const int zslot = wave0 ? 0 : NW;
+  auto put_halo = [&](u32x4 yh, const u32x4 (&zo)[ZP], const u32x4 (&zy)[ZP]) {
+    s_yin[w][ly & (G - 1)] = u32x2{yh[0], yh[2]};  // lanes l and l + G hold the same record
+#pragma unroll
+    for (int i = 0; i < G; i++) {
+      s_xw[(i + G - 1) & (G - 1)][zslot][0][ly] = piece_value<T>(zo[i / VPP], i % VPP);
+      s_xw[(i + G - 1) & (G - 1)][zslot][1][ly] = piece_value<T>(zy[i / VPP], i % VPP);
     }
-    if (pred_z >= 0) VY1 = load_coherent<T>(rz, z_off(pred_z, 1, TZ - 1));
+    // lanes 0..G-1 wrote the records every lane of the wave reads next;
+    // keep the compiler from moving the reads above the writes
+    __builtin_amdgcn_wave_barrier();
+  };
+  // One 16-byte piece of the cooperative input load of group gr.
+  auto coop_load1 = [&](int a, int h, int gr) -> uint4 {
+    const int bo = cb0[a][h] + gr * (int)(G * sizeof(T));
+    return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rin, bo < 0 ? kOut : bo + 16 * (ly % XPC),
+                                                                           0, 0));
+  };
+  // Input load instructions of a group (compress: one per step from step 0).
+  constexpr int kInLoads = AZ * XPC;
+  static_assert(!COMP || kInLoads <= G, "one input load per step");
+
+  // ---- prologue: halo and input of the first group
+  {
+    u32x4 yh0 = load_yh(0);
+    u32x4 zo0[ZP], zy0[ZP];
+    load_zh(0, zo0, zy0);
+    poll_halo(0, yh0, zo0, zy0);
+    put_halo(yh0, zo0, zy0);
+    if (wave0) {
+      // Rows before lane 0 run ahead of it: the y-halo row (skew -1) already
+      // produced x = 0 at step -1, and the corner row (z-1, y-1; skew -2) at
+      // step -2.  Their values enter the histories before step 0 (polled for
+      // like the halo: records become visible in no particular order).
+      const bool sy = need_y, sz = need_z;
+      const int ez = (TZ - 1) % VPP;  // unit of the z value in its piece
+      u32x4 ry1 = {0, 0, 0, 0}, rz1 = {0, 0, 0, 0};
+      uint32_t spins = 0;
+      for (;;) {
+        ry1 = __builtin_amdgcn_raw_buffer_load_b128(ry_in, y_off(pred_y0, kWLanes - 1), 0, kCoherent);
+        rz1 = __builtin_amdgcn_raw_buffer_load_b128(need_z ? rz : rz_in, z_unit(pred_z0, 1, TZ - 1) & ~15, 0,
+                                                    kCoherent);
+        const bool ok = (!sy || (ry1[1] == tag && ry1[3] == tag)) &&
+                        (!sz || (rz1[2 * ez + 1] == tag && rz1[VPP == 1 ? 3 : 2 * ez + 1] == tag));
+        if (__builtin_amdgcn_ballot_w64(!ok) == 0) break;
+        if (__hip_atomic_load(&P->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+        if (++spins > kSpinLimit) {
+          if (ly == 0) atomicCAS(&P->status, 0, kStatusStalled);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      if (sy) Y1[0] = ly == 0 ? rec_elem<T>(u32x2{ry1[0], ry1[2]}, 0) : T(0);
+      if (sz) VY1 = piece_value<T>(rz1, ez);
+    }
   }
   // Step -1 of each wave's last sub-row, read by the next wave at step 0
   // (nonzero only for the seeded y-halo value above when AZ == 1).
-  s_xw[1][w][0][ly] = O1[AZ - 1];
-  s_xw[1][w][1][ly] = Y1[AZ - 1];
+  if (w + 1 < NW) {
+    s_xw[G - 1][w + 1][0][ly] = O1[AZ - 1];
+    s_xw[G - 1][w + 1][1][ly] = Y1[AZ - 1];
+  }
 #pragma unroll
   for (int a = 0; a < AZ; a++) {
     const int64_t q0 = wlo[a] >> 3;
@@ -653,11 +725,13 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
       wait_vm();
       ring_put(a, q0, t0);
       ring_put(a, q0 + 1, t1);
+      coop_load(a, 1, xq2[0][a]);
     } else {
       __amdgpu_buffer_rsrc_t r = rin;
       c0[a] = load_code_chunk<CT>(r, q0 - cbase);
       c1[a] = load_code_chunk<CT>(r, q0 + 1 - cbase);
       c2[a] = load_code_chunk<CT>(r, q0 + 2 - cbase);
+      c3[a] = load_code_chunk<CT>(r, q0 + 3 - cbase);
       if (rv[a]) {
         const int64_t seg = ((z0 + AZ * w + a) * Yd + yr) * A.nblk[2] + bx;
         uidx[a] = (int64_t)A.useg[seg];
@@ -678,270 +752,263 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
   }
   __syncthreads();
 
-  uint32_t pz_v = 0, py_v = 0;  // predecessors' progress, read during the group
-  for (int g = 0; g < ngroups; g++) {
-    const bool more = g + 1 < ngroups;
-    if (ly < G) s_yin[w][ly] = yh_cur;
-    // lanes 0..G-1 wrote the records every lane of the wave reads below;
-    // keep the compiler from moving the reads above the writes
-    __builtin_amdgcn_wave_barrier();
-    // The next group's loads are issued on every group, also the last (its
-    // records and chunks lie inside the buffers or past them and go unused),
-    // so that no branch joins their registers before the group ends.  The
-    // input chunks go out now; the halo records after step kHaloStep - 1,
-    // which lets this tile run that many steps closer behind its
-    // predecessors while the loads still have the rest of the group to land.
-    int zn[AZ];  // decompress: values the next group consumes
-#pragma unroll
-    for (int a = 0; a < AZ; a++) {
-      const int64_t q = (wlo[a] + (int64_t)(g + 1) * G) >> 3;  // first chunk of the next window
-      if constexpr (COMP) {
-        (void)q;
-        coop_load(a, g + 1, xpre[a]);
-        zn[a] = 0;
-      } else {
-        cpre[a] = load_code_chunk<CT>(rin, q + 2 - cbase);
-        zn[a] = 0;
-        if constexpr (UWIN) {
-          zn[a] = zeros_in(code_window<CT>(c1[a], c2[a], (int)(wlo[a] & (G - 1))), g + 1, a);
-          load_uw(uidx[a] + zc[a], zn[a], uw_nxt[a], 0, 2);
-        }
-      }
-    }
-    if constexpr (UWIN) {
-      // Most windows hold at most two unpredictable values: two loads per
-      // sub-row go out above.  Only when a lane of the wave needs more does
-      // the wave load the rest of its window.
-      bool several = false;
-#pragma unroll
-      for (int a = 0; a < AZ; a++) several |= zn[a] > 2;
-      if (__builtin_amdgcn_ballot_w64(several) != 0) {
-#pragma unroll
-        for (int a = 0; a < AZ; a++) load_uw(uidx[a] + zc[a], zn[a], uw_nxt[a], 2, UW);
-      }
-    }
-    // per-group window of each sub-row and its inputs
-    int bslot[AZ];
-    CW cwin[AZ];
-#pragma unroll
-    for (int a = 0; a < AZ; a++) {
-      const int64_t lo = wlo[a] + (int64_t)g * G;
-      bslot[a] = (int)(lo & (kWRing - 1));
-      if constexpr (!COMP) cwin[a] = code_window<CT>(c0[a], c1[a], (int)(lo & (G - 1)));
-    }
-    T xin[AZ][COMP ? G : 1];
-    T yk[G][AZ];  // this group's values; lane 63's are the y-successor's halo
-    if constexpr (COMP) {
-#pragma unroll
-      for (int a = 0; a < AZ; a++)
-#pragma unroll
-        for (int i = 0; i < G; i++) xin[a][i] = s_ring[w][a][(bslot[a] + i) & (kWRing - 1)][ly];
-    }
-
-#pragma unroll
-    for (int i = 0; i < G; i++) {
-      const int sig = g * G + i;
-      // the row below sub-row 0 at step sig - 1
-      // (a one-wave tile has no row below it inside the workgroup)
-      const T lo_o = NW > 1 ? s_xw[(sig - 1) & 1][wprev][0][ly] : T(0);
-      const T lo_y = NW > 1 ? s_xw[(sig - 1) & 1][wprev][1][ly] : T(0);
-      const T vn_o = w > 0 ? lo_o : piece_elem<T>(zo_cur, i);
-      const T vn_y = w > 0 ? lo_y : piece_elem<T>(zy_cur, i);
-      const u32x2 yrec = s_yin[w][i];  // the y-halo values lane 0 takes at this step
-      VO2 = VO1;
-      VO1 = vn_o;
-      VY3 = VY2;
-      VY2 = VY1;
-      VY1 = vn_y;
-      // The AZ sub-rows are independent within a step (each reads only
-      // values of earlier steps); every statement below runs across all of
-      // them so their dependence chains interleave.
-      T l1[AZ], l2[AZ], ly2[AZ], ly3[AZ], p[AZ], xq[AZ];
-      bool act[AZ];
+  // One group.  Compression loads the input of group g + 2 into X1 while it
+  // puts that of group g + 1 (X0) into the rings; the loop alternates the
+  // two buffers, so no register that a load may still be writing is ever
+  // copied (a copy would wait for the load).  Every load of a group is
+  // issued on every group, also the last (its records and chunks lie inside
+  // the buffers or past them and go unused), so that no branch joins their
+  // registers before they are used.
+  using XB = uint4[AZ][COMP ? XPC : 1];
+  auto group = [&](const int g, XB& X0, XB& X1) __attribute__((always_inline)) {
+      const bool more = g + 1 < ngr;
+      int zn[AZ];  // decompress: values the next group consumes
 #pragma unroll
       for (int a = 0; a < AZ; a++) {
-        l1[a] = a > 0 ? O1[a > 0 ? a - 1 : 0] : VO1;
-        l2[a] = a > 0 ? O2[a > 0 ? a - 1 : 0] : VO2;
-        ly2[a] = a > 0 ? Y2[a > 0 ? a - 1 : 0] : VY2;
-        ly3[a] = a > 0 ? Y3[a > 0 ? a - 1 : 0] : VY3;
-        act[a] = (unsigned)(sig - sk[a]) < (unsigned)xlen[a];
+        const int64_t q = (wlo[a] + (int64_t)(g + 1) * G) >> 3;  // first chunk of the next window
+        zn[a] = 0;
+        if constexpr (!COMP) {
+          cpre[a] = load_code_chunk<CT>(rin, q + 3 - cbase);
+          if constexpr (UWIN) {
+            zn[a] = zeros_in(code_window<CT>(c1[a], c2[a], (int)(wlo[a] & (G - 1))), g + 1, a);
+            load_uw(uidx[a] + zc[a], zn[a], uw_nxt[a], 0, 2);
+          }
+        } else {
+          (void)q;
+        }
       }
-      // Eq. predmodel, n = 1, terms in lexicographic order of (kz, ky, kx)
+      if constexpr (UWIN) {
+        // Most windows hold at most two unpredictable values: two loads per
+        // sub-row go out above.  Only when a lane of the wave needs more does
+        // the wave load the rest of its window.
+        bool several = false;
 #pragma unroll
-      for (int a = 0; a < AZ; a++) p[a] = T(0) + O1[a];  // (0,0,1) +1
+        for (int a = 0; a < AZ; a++) several |= zn[a] > 2;
+        if (__builtin_amdgcn_ballot_w64(several) != 0) {
 #pragma unroll
-      for (int a = 0; a < AZ; a++) p[a] = p[a] + Y1[a];  // (0,1,0) +1
+          for (int a = 0; a < AZ; a++) load_uw(uidx[a] + zc[a], zn[a], uw_nxt[a], 2, UW);
+        }
+      }
+      // per-group window of each sub-row and its inputs
+      int bslot[AZ];
+      CW cwin[AZ];
 #pragma unroll
-      for (int a = 0; a < AZ; a++) p[a] = p[a] - Y2[a];  // (0,1,1) -1
-#pragma unroll
-      for (int a = 0; a < AZ; a++) p[a] = p[a] + l1[a];  // (1,0,0) +1
-#pragma unroll
-      for (int a = 0; a < AZ; a++) p[a] = p[a] - l2[a];  // (1,0,1) -1
-#pragma unroll
-      for (int a = 0; a < AZ; a++) p[a] = p[a] - ly2[a];  // (1,1,0) -1
-#pragma unroll
-      for (int a = 0; a < AZ; a++) p[a] = p[a] + ly3[a];  // (1,1,1) +1
+      for (int a = 0; a < AZ; a++) {
+        const int64_t lo = wlo[a] + (int64_t)g * G;
+        bslot[a] = (int)(lo & (kWRing - 1));
+        if constexpr (!COMP) cwin[a] = code_window<CT>(c0[a], c1[a], (int)(lo & (G - 1)));
+      }
+      T xin[AZ][COMP ? G : 1];
+      T yk[G][AZ];  // this group's values; lane 63's are the y-successor's halo
       if constexpr (COMP) {
-        T t[AZ], rk[AZ], xqq[AZ];
-        bool ok[AZ];
 #pragma unroll
-        for (int a = 0; a < AZ; a++) t[a] = (xin[a][i] - p[a]) * inv2eb;
+        for (int a = 0; a < AZ; a++)
 #pragma unroll
-        for (int a = 0; a < AZ; a++) rk[a] = rint(t[a]);
+          for (int i = 0; i < G; i++) xin[a][i] = s_ring[w][a][(bslot[a] + i) & (kWRing - 1)][ly];
+      }
+
 #pragma unroll
-        for (int a = 0; a < AZ; a++) xqq[a] = p[a] + rk[a] * twoeb;
-        // |rk| <= half - 1 implies |t| < half (rint moves t by at most 1/2),
-        // so the format's test |t| < half needs no instruction of its own
-#pragma unroll
-        for (int a = 0; a < AZ; a++) ok[a] = (fabs(rk[a]) <= halfm1T) & (fabs(xin[a][i] - xqq[a]) < ebT);
-        U xb[AZ];
-        bool bad = false;
+      for (int i = 0; i < G; i++) {
+        const int sig = g * G + i;
+        // the row below sub-row 0 at step sig - 1: the last sub-row of the
+        // wave below, or the z-halo for wave 0 (ring slot w)
+        const T vn_o = s_xw[(i + G - 1) & (G - 1)][w][0][ly];
+        const T vn_y = s_xw[(i + G - 1) & (G - 1)][w][1][ly];
+        const u32x2 yrec = s_yin[w][i];  // the y-halo values lane 0 takes at this step
+        VO2 = VO1;
+        VO1 = vn_o;
+        VY3 = VY2;
+        VY2 = VY1;
+        VY1 = vn_y;
+        // The AZ sub-rows are independent within a step (each reads only
+        // values of earlier steps); every statement below runs across all of
+        // them so their dependence chains interleave.
+        T l1[AZ], l2[AZ], ly2[AZ], ly3[AZ], p[AZ], xq[AZ];
+        bool act[AZ];
 #pragma unroll
         for (int a = 0; a < AZ; a++) {
-          xb[a] = to_bits<T>(xqq[a]);
-          bad |= !ok[a];
+          l1[a] = a > 0 ? O1[a > 0 ? a - 1 : 0] : VO1;
+          l2[a] = a > 0 ? O2[a > 0 ? a - 1 : 0] : VO2;
+          ly2[a] = a > 0 ? Y2[a > 0 ? a - 1 : 0] : VY2;
+          ly3[a] = a > 0 ? Y3[a > 0 ? a - 1 : 0] : VY3;
+          act[a] = (unsigned)(sig - sk[a]) < (unsigned)xlen[a];
         }
-        // Unpredictable points are rare: the reduced representation is
-        // computed only in steps where a lane of the wave has one (a
-        // wave-uniform branch).
-        if (__builtin_amdgcn_ballot_w64(bad) != 0) {
+        // Eq. predmodel, n = 1, terms in lexicographic order of (kz, ky, kx)
+#pragma unroll
+        for (int a = 0; a < AZ; a++) p[a] = T(0) + O1[a];  // (0,0,1) +1
+#pragma unroll
+        for (int a = 0; a < AZ; a++) p[a] = p[a] + Y1[a];  // (0,1,0) +1
+#pragma unroll
+        for (int a = 0; a < AZ; a++) p[a] = p[a] - Y2[a];  // (0,1,1) -1
+#pragma unroll
+        for (int a = 0; a < AZ; a++) p[a] = p[a] + l1[a];  // (1,0,0) +1
+#pragma unroll
+        for (int a = 0; a < AZ; a++) p[a] = p[a] - l2[a];  // (1,0,1) -1
+#pragma unroll
+        for (int a = 0; a < AZ; a++) p[a] = p[a] - ly2[a];  // (1,1,0) -1
+#pragma unroll
+        for (int a = 0; a < AZ; a++) p[a] = p[a] + ly3[a];  // (1,1,1) +1
+        if constexpr (COMP) {
+          T t[AZ], rk[AZ], xqq[AZ];
+          bool ok[AZ];
+#pragma unroll
+          for (int a = 0; a < AZ; a++) t[a] = (xin[a][i] - p[a]) * inv2eb;
+#pragma unroll
+          for (int a = 0; a < AZ; a++) rk[a] = rint(t[a]);
+#pragma unroll
+          for (int a = 0; a < AZ; a++) xqq[a] = p[a] + rk[a] * twoeb;
+          // |rk| <= half - 1 implies |t| < half (rint moves t by at most 1/2),
+          // so the format's test |t| < half needs no instruction of its own
+#pragma unroll
+          for (int a = 0; a < AZ; a++) ok[a] = (fabs(rk[a]) <= halfm1T) & (fabs(xin[a][i] - xqq[a]) < ebT);
+          U xb[AZ];
+          bool bad = false;
 #pragma unroll
           for (int a = 0; a < AZ; a++) {
-            const U okm = (U)0 - (U)ok[a];
-            xb[a] = (xb[a] & okm) | (trunc_masked<T>(to_bits<T>(xin[a][i]), e_eb) & ~okm);
+            xb[a] = to_bits<T>(xqq[a]);
+            bad |= !ok[a];
           }
-        }
+          // Unpredictable points are rare: the reduced representation is
+          // computed only in steps where a lane of the wave has one (a
+          // wave-uniform branch).
+          if (__builtin_amdgcn_ballot_w64(bad) != 0) {
 #pragma unroll
-        for (int a = 0; a < AZ; a++) {
-          const U am = (U)0 - (U)act[a];
-          xq[a] = bits_to<T>(xb[a] & am);
-          if constexpr (sizeof(CT) == 1) {
-            // the code as a float (an exact integer below 256) packed into
-            // byte i % 4 of word i / 4
-            const float cf = ok[a] ? (float)(rk[a] + halfT) : 0.0f;
-            cpk[a][i >> 2] = __builtin_amdgcn_cvt_pk_u8_f32(cf, (uint32_t)(i & 3), cpk[a][i >> 2]);
-          } else {
-            const uint32_t code = ok[a] ? (uint32_t)((int)rk[a] + half) : 0u;
-            cacc[a] |= (CW)code << (SB * i);
-          }
-          if constexpr (DBG)
-            if (act[a]) ((T*)A.xo)[rb[a] + (sig - sk[a])] = xq[a];
-        }
-      } else {
-        bool took[AZ], any_took = false;
-#pragma unroll
-        for (int a = 0; a < AZ; a++) {
-          const uint32_t code = (uint32_t)(cwin[a] >> (SB * i)) & ((1u << SB) - 1);
-          const T v1 = p[a] + T((int32_t)code - half) * twoeb;
-          if constexpr (UWIN) {
-            xq[a] = act[a] ? (code != 0 ? v1 : uw[a][0]) : T(0);
-            took[a] = act[a] && code == 0;
-            any_took |= took[a];
-          } else {
-            xq[a] = act[a] ? (code != 0 ? v1 : unext[a]) : T(0);
-            if (act[a] && code == 0) {
-              uidx[a]++;
-              unext[a] = ((uint64_t)uidx[a] < A.n_unpred) ? ((const T*)A.uvals)[uidx[a]] : T(0);
+            for (int a = 0; a < AZ; a++) {
+              const U okm = (U)0 - (U)ok[a];
+              xb[a] = (xb[a] & okm) | (trunc_masked<T>(to_bits<T>(xin[a][i]), e_eb) & ~okm);
             }
           }
-          s_ring[w][a][(bslot[a] + i) & (kWRing - 1)][ly] = xq[a];
+#pragma unroll
+          for (int a = 0; a < AZ; a++) {
+            const U am = (U)0 - (U)act[a];
+            xq[a] = bits_to<T>(xb[a] & am);
+            if constexpr (sizeof(CT) == 1) {
+              // the code as a float (an exact integer below 256) packed into
+              // byte i % 4 of word i / 4
+              const float cf = ok[a] ? (float)(rk[a] + halfT) : 0.0f;
+              cpk[a][i >> 2] = __builtin_amdgcn_cvt_pk_u8_f32(cf, (uint32_t)(i & 3), cpk[a][i >> 2]);
+            } else {
+              const uint32_t code = ok[a] ? (uint32_t)((int)rk[a] + half) : 0u;
+              cacc[a] |= (CW)code << (SB * i);
+            }
+            if constexpr (DBG)
+              if (act[a]) ((T*)A.xo)[rb[a] + (sig - sk[a])] = xq[a];
+          }
+        } else {
+          bool took[AZ], any_took = false;
+#pragma unroll
+          for (int a = 0; a < AZ; a++) {
+            const uint32_t code = (uint32_t)(cwin[a] >> (SB * i)) & ((1u << SB) - 1);
+            const T v1 = p[a] + T((int32_t)code - half) * twoeb;
+            if constexpr (UWIN) {
+              xq[a] = act[a] ? (code != 0 ? v1 : uw[a][0]) : T(0);
+              took[a] = act[a] && code == 0;
+              any_took |= took[a];
+            } else {
+              xq[a] = act[a] ? (code != 0 ? v1 : unext[a]) : T(0);
+              if (act[a] && code == 0) {
+                uidx[a]++;
+                unext[a] = ((uint64_t)uidx[a] < A.n_unpred) ? ((const T*)A.uvals)[uidx[a]] : T(0);
+              }
+            }
+            s_ring[w][a][(bslot[a] + i) & (kWRing - 1)][ly] = xq[a];
+          }
+          if constexpr (UWIN) {
+            // A consumed value leaves the window (at most G - 1 - i values
+            // remain for the rest of the group).  Unpredictable points are
+            // rare: the shift runs only in steps where a lane of the wave took
+            // one (a wave-uniform branch).
+            if (__builtin_amdgcn_ballot_w64(any_took) != 0) {
+#pragma unroll
+              for (int a = 0; a < AZ; a++)
+#pragma unroll
+                for (int j = 0; j + 1 < UW - i; j++) uw[a][j] = took[a] ? uw[a][j + 1] : uw[a][j];
+            }
+          }
         }
-        if constexpr (UWIN) {
-          // A consumed value leaves the window (at most G - 1 - i values
-          // remain for the rest of the group).  Unpredictable points are
-          // rare: the shift runs only in steps where a lane of the wave took
-          // one (a wave-uniform branch).
-          if (__builtin_amdgcn_ballot_w64(any_took) != 0) {
+        // y-moved values: lane 0 takes the last row of the tile before along y
+        T ynew[AZ];
 #pragma unroll
-            for (int a = 0; a < AZ; a++)
+        for (int a = 0; a < AZ; a++) ynew[a] = wave_shr1<T>(xq[a], rec_elem<T>(yrec, a));
 #pragma unroll
-              for (int j = 0; j + 1 < UW - i; j++) uw[a][j] = took[a] ? uw[a][j + 1] : uw[a][j];
+        for (int a = 0; a < AZ; a++) {
+          O2[a] = O1[a];
+          O1[a] = xq[a];
+          Y3[a] = Y2[a];
+          Y2[a] = Y1[a];
+          Y1[a] = ynew[a];
+          yk[i][a] = xq[a];
+        }
+        // the wave above reads this wave's last sub-row at the next step
+        if (w + 1 < NW) {
+          s_xw[i][w + 1][0][ly] = xq[AZ - 1];
+          s_xw[i][w + 1][1][ly] = ynew[AZ - 1];
+        }
+        if (i + 1 < G) {
+          ezo[i + 1] = xq[AZ - 1];
+          ezy[i + 1] = ynew[AZ - 1];
+        } else {
+          co = xq[AZ - 1];
+          cy = ynew[AZ - 1];
+        }
+        // compression: one load of the input of group g + 2 per step
+        if constexpr (COMP) {
+          if (i < kInLoads) X1[i / XPC][i % XPC] = coop_load1(i / XPC, i % XPC, g + 2);
+        }
+        // the step's exchange between waves; a single wave needs no barrier
+        // (its own LDS accesses complete in order)
+        if constexpr (NW > 1) __syncthreads();
+        // the next group's halo, checked at the end of this one
+        if (i == 0) {
+          yh_nx = load_yh(g + 1);
+          load_zh(g + 1, zo_nx, zy_nx);
+        }
+      }
+
+
+      // ---- group end: the boundary records, stored and never waited for
+      if (succ_y) {
+        // lane 63's G records move to lanes 64 - G .. 63 (one record each)
+        // and leave with one store
+        u32x2 rec = {0, 0};
+#pragma unroll
+        for (int i = 0; i < G; i++) {
+          const u32x2 r = pack_rec<T, AZ>(yk[i]);
+          const u32x2 r63 = {(uint32_t)__builtin_amdgcn_readlane((int)r[0], kWLanes - 1),
+                             (uint32_t)__builtin_amdgcn_readlane((int)r[1], kWLanes - 1)};
+          if (ly == kWLanes - G + i) rec = r63;
+        }
+        if (ly >= kWLanes - G)
+          __builtin_amdgcn_raw_buffer_store_b128(u32x4{rec[0], tag, rec[1], tag}, ry,
+                                                 y_off(tile, g * G + ly - (kWLanes - G)), 0, kCoherent);
+      }
+      if (succ_z && w == NW - 1) {
+#pragma unroll
+        for (int j = 0; j < ZP; j++) {
+          __builtin_amdgcn_raw_buffer_store_b128(tag_piece<T>(ezo + VPP * j, tag), rz, z_piece(tile, 0, g, j), 0,
+                                                 kCoherent);
+          __builtin_amdgcn_raw_buffer_store_b128(tag_piece<T>(ezy + VPP * j, tag), rz, z_piece(tile, 1, g, j), 0,
+                                                 kCoherent);
+        }
+        if (!more) {
+          // the last step's value lives in record (g + 1) * G, past this group
+          if constexpr (sizeof(T) == 4) {
+            __builtin_amdgcn_raw_buffer_store_b64(u32x2{__builtin_bit_cast(uint32_t, co), tag}, rz,
+                                                  z_unit(tile, 0, (g + 1) * G), 0, kCoherent);
+            __builtin_amdgcn_raw_buffer_store_b64(u32x2{__builtin_bit_cast(uint32_t, cy), tag}, rz,
+                                                  z_unit(tile, 1, (g + 1) * G), 0, kCoherent);
+          } else {
+            __builtin_amdgcn_raw_buffer_store_b128(tag_piece<T>(&co, tag), rz, z_unit(tile, 0, (g + 1) * G), 0,
+                                                   kCoherent);
+            __builtin_amdgcn_raw_buffer_store_b128(tag_piece<T>(&cy, tag), rz, z_unit(tile, 1, (g + 1) * G), 0,
+                                                   kCoherent);
           }
         }
       }
-      // y-moved values: lane 0 takes the last row of the tile before along y
-      T ynew[AZ];
-#pragma unroll
-      for (int a = 0; a < AZ; a++) ynew[a] = wave_shr1<T>(xq[a], rec_elem<T>(yrec, a));
-#pragma unroll
-      for (int a = 0; a < AZ; a++) {
-        O2[a] = O1[a];
-        O1[a] = xq[a];
-        Y3[a] = Y2[a];
-        Y2[a] = Y1[a];
-        Y1[a] = ynew[a];
-        yk[i][a] = xq[a];
-      }
-      if constexpr (NW > 1) {
-        s_xw[sig & 1][w][0][ly] = xq[AZ - 1];
-        s_xw[sig & 1][w][1][ly] = ynew[AZ - 1];
-      }
-      if (i + 1 < G) {
-        ezo[i + 1] = xq[AZ - 1];
-        ezy[i + 1] = ynew[AZ - 1];
-      } else {
-        co = xq[AZ - 1];
-        cy = ynew[AZ - 1];
-      }
-      // the step's exchange between waves; a single wave needs no barrier
-      // (its own LDS accesses complete in order)
-      if constexpr (NW > 1) __syncthreads();
-      if (i == kPollStep - 1) {
-        pz_v = __hip_atomic_load(prog_z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        py_v = __hip_atomic_load(prog_y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      if (i == kHaloStep - 1) {
-        const uint32_t pz = __builtin_amdgcn_readfirstlane(pz_v), py = __builtin_amdgcn_readfirstlane(py_v);
-        if (more && !ready_for(g + 1, pz, py)) wave_wait(g + 1, pz, py);
-        yh_nxt = load_yh(g + 1);
-        if (wave0) load_zh(g + 1, zo_nxt, zy_nxt);
-      }
-    }
-
-    // ---- group end: publish boundary records, then the progress flag
-    if (succ_y && ly == kWLanes - 1) {
-      // lane 63 stores the group's G records itself, two per 16-byte store
-      // (no values move between lanes)
-#pragma unroll
-      for (int i = 0; i < G; i += 2) {
-        const u32x2 r0 = pack_rec<T, AZ>(yk[i]), r1 = pack_rec<T, AZ>(yk[i + 1]);
-        __builtin_amdgcn_raw_buffer_store_b128(u32x4{r0[0], r0[1], r1[0], r1[1]}, ry, y_off(tile, g * G + i), 0,
-                                               kCoherent);
-      }
-    }
-    if (succ_z && w == NW - 1) {
-#pragma unroll
-      for (int j = 0; j < XPC; j++) {
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, pack_piece<T>(ezo, j)), rz,
-                                               z_piece(tile, 0, g, j), 0, kCoherent);
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, pack_piece<T>(ezy, j)), rz,
-                                               z_piece(tile, 1, g, j), 0, kCoherent);
-      }
-    }
-    if (succ_z && w == NW - 1 && !more) {
-      // the last step's value lives in record (g + 1) * G, past this group
-      if constexpr (sizeof(T) == 4) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, co), rz, z_off(tile, 0, (g + 1) * G), 0,
-                                              kCoherent);
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, cy), rz, z_off(tile, 1, (g + 1) * G), 0,
-                                              kCoherent);
-      } else {
-        const uint64_t uo = __builtin_bit_cast(uint64_t, co), uy = __builtin_bit_cast(uint64_t, cy);
-        __builtin_amdgcn_raw_buffer_store_b64(u32x2{(uint32_t)uo, (uint32_t)(uo >> 32)}, rz,
-                                              z_off(tile, 0, (g + 1) * G), 0, kCoherent);
-        __builtin_amdgcn_raw_buffer_store_b64(u32x2{(uint32_t)uy, (uint32_t)(uy >> 32)}, rz,
-                                              z_off(tile, 1, (g + 1) * G), 0, kCoherent);
-      }
-    }
-    ezo[0] = co;
-    ezy[0] = cy;
-    // ---- completed chunk of each row, input refill, register rotation.
-    // None of it depends on the records just stored.  Compression (and any
-    // one-wave tile) does it while they drain, so the wait below rarely
-    // stalls; the reconstruction of a 3D tile does it after the flag, since
-    // its own output stores would otherwise join that wait.
-    constexpr bool kEndFirst = COMP || NW == 1;
-    auto group_end_work = [&]() {
+      ezo[0] = co;
+      ezy[0] = cy;
+      // ---- completed chunk of each row, input refill, register rotation.
+      // None of it depends on the records just stored.
 #pragma unroll
       for (int a = 0; a < AZ; a++) {
         const int64_t lo = wlo[a] + (int64_t)g * G;
@@ -976,13 +1043,15 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
           qhold[a] = qodd ? -1 : q;
           cprv[a] = cacc[a];
           cacc[a] = (CW)0;
-          if (more) coop_put(a, g + 1, xpre[a]);
+          // the chunk of group g + 1, loaded during group g - 1
+          coop_put(a, g + 1, X0[a]);  // (past the last group: unread)
         } else {
           (void)q;
           coop_flush(a, g);
           c0[a] = c1[a];
           c1[a] = c2[a];
-          c2[a] = cpre[a];
+          c2[a] = c3[a];
+          c3[a] = cpre[a];
           if constexpr (UWIN) {
             uidx[a] += zc[a];
             zc[a] = zn[a];
@@ -991,26 +1060,23 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile, uint
           }
         }
       }
-    };
-    if constexpr (kEndFirst) group_end_work();
-    wait_vm();
-    __syncthreads();
-    if (tid == 0) {
-      const uint32_t done = more ? (uint32_t)((g + 1) * G) : kDone;
-      __hip_atomic_store(&A.progress[tile], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if constexpr (!kEndFirst) group_end_work();
-    yh_cur = yh_nxt;
-#pragma unroll
-    for (int j = 0; j < XPC; j++) {
-      zo_cur[j] = zo_nxt[j];
-      zy_cur[j] = zy_nxt[j];
-    }
+      // ---- the halo of group g + 1 (loaded after step 0), once it holds this
+      // launch's records, into LDS (this wave's reads of group g's halo are
+      // done: its LDS accesses complete in order).  It comes after this
+      // group's stores, which thus leave without waiting for the
+      // predecessors.  (Past the last group the records are not waited for:
+      // see last_rec.)
+      poll_halo(g + 1, yh_nx, zo_nx, zy_nx);
+      put_halo(yh_nx, zo_nx, zy_nx);
+  };
+  for (int g = 0; g < ngr; g += 2) {
+    group(g, xq2[0], xq2[1]);
+    group(g + 1, xq2[1], xq2[0]);
   }
   // ---- the chunk after the last window (its head was produced in the last group)
 #pragma unroll
   for (int a = 0; a < AZ; a++) {
-    const int64_t lo = wlo[a] + (int64_t)(ngroups - 1) * G;
+    const int64_t lo = wlo[a] + (int64_t)(ngr - 1) * G;
     const int64_t q = (lo >> 3) + 1;
     const int o = (int)(lo & (G - 1));
     if constexpr (COMP) {
@@ -1040,7 +1106,7 @@ wsweep_kernel(WArgs A) {
   if (A.plan->status != 0 || (A.pass2 && !A.plan->rerun)) return;
   if (threadIdx.x == 0) s_tile = claim_tile((int)atomicAdd(A.ticket, 1u), A.claim, A.tz_per_blk, A.ty_per_blk, A.ntiles);
   __syncthreads();
-  wsweep_body<T, CT, COMP, NW, AZ, DBG>(A, s_tile, sz_lds);
+  wsweep_body<T, CT, COMP, NW, AZ, DBG>(A, s_tile, sz_lds, A.pass2);
 }
 
 }  // namespace szh
