@@ -665,6 +665,25 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile_in, u
     // keep the compiler from moving the reads above the writes
     __builtin_amdgcn_wave_barrier();
   };
+  // Load, check and write the halo of group gr until it holds this launch's
+  // records (after a failed check).
+  auto repoll_halo = [&](int gr) {
+    u32x4 yh, zo[ZP], zy[ZP];
+    uint32_t spins = 0;
+    do {
+      if (__hip_atomic_load(&P->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+      if (++spins > kSpinLimit) {
+        if (ly == 0) atomicCAS(&P->status, 0, kStatusStalled);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      yh = load_yh(gr);
+#pragma unroll
+      for (int j = 0; j < ZP; j++) zo[j] = zy[j] = u32x4{0, 0, 0, 0};
+      load_zh(gr, zo, zy);
+    } while (!halo_ok(gr, yh, zo, zy));
+    put_halo(yh, zo, zy);
+  };
   // One 16-byte piece of the cooperative input load of group gr.
   auto coop_load1 = [&](int a, int h, int gr) -> uint4 {
     const int bo = cb0[a][h] + gr * (int)(G * sizeof(T));
@@ -966,7 +985,11 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile_in, u
       }
 
 
-      // ---- group end: the boundary records, stored and never waited for
+      // ---- group end.  First the check of the next group's halo (loaded
+      // after step 0): vector memory operations retire in order, so the wait
+      // for its loads here includes none of this group's stores.
+      const bool halo_in = halo_ok(g + 1, yh_nx, zo_nx, zy_nx);
+      // ---- the boundary records, stored and never waited for
       if (succ_y) {
         // lane 63's G records move to lanes 64 - G .. 63 (one record each)
         // and leave with one store
@@ -1060,14 +1083,13 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile_in, u
           }
         }
       }
-      // ---- the halo of group g + 1 (loaded after step 0), once it holds this
-      // launch's records, into LDS (this wave's reads of group g's halo are
-      // done: its LDS accesses complete in order).  It comes after this
-      // group's stores, which thus leave without waiting for the
-      // predecessors.  (Past the last group the records are not waited for:
-      // see last_rec.)
-      poll_halo(g + 1, yh_nx, zo_nx, zy_nx);
+      // ---- the halo of group g + 1 into LDS (this wave's reads of group g's
+      // halo are done: its LDS accesses complete in order).  If the check
+      // found a record still missing, the halo is polled again, in registers
+      // of its own, and written again.  (Past the last group the records are
+      // not waited for: see last_rec.)
       put_halo(yh_nx, zo_nx, zy_nx);
+      if (!halo_in) repoll_halo(g + 1);
   };
   for (int g = 0; g < ngr; g += 2) {
     group(g, xq2[0], xq2[1]);
