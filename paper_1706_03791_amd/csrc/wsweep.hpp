@@ -331,12 +331,16 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile_in, u
   // indices [0, ngr * G] along z (index k holds step k - 1); later records
   // are never needed by an active step and never waited for.  A missing
   // predecessor is a descriptor of zero records (its loads read zero and
-  // touch no memory), chosen per tile in scalar registers.  Only wave 0
-  // loads and writes the z-halo.
+  // touch no memory), chosen per tile in scalar registers.  Each wave loads
+  // its own y-records; the z-halo's ZP pieces per kind are shared out among
+  // the waves, piece j to wave j mod NW (wave 0 owns piece 0, the values read
+  // at the first step of a group, before any barrier of that group).
   const bool wave0 = w == 0;  // uniform: scalar selects below
+  constexpr bool kZX = NW > 1;                           // z-exchange compiled in (a 2D field has none)
+  constexpr int ZPW = kZX ? (ZP + NW - 1) / NW : 1;      // z pieces per wave and kind
   // A predecessor stores records only for a successor with rows in the block
   // (a tile past the block's edge waits for none: its points are inactive).
-  const bool need_y = pred_y >= 0 && y0 < yb1, need_z = pred_z >= 0 && z0 < zb1 && wave0;
+  const bool need_y = pred_y >= 0 && y0 < yb1, need_z = kZX && pred_z >= 0 && z0 < zb1;
   const __amdgpu_buffer_rsrc_t ry_in = need_y ? ry : make_rsrc(A.xy, 0);
   const __amdgpu_buffer_rsrc_t rz_in = need_z ? rz : make_rsrc(A.xz, 0);
   const int pred_y0 = pred_y >= 0 ? pred_y : 0, pred_z0 = pred_z >= 0 ? pred_z : 0;
@@ -346,44 +350,58 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile_in, u
     return __builtin_amdgcn_raw_buffer_load_b128(ry_in, y_off(pred_y0, gr * G + kWLanes + (ly & (G - 1))), 0,
                                                  kCoherent);
   };
-  // z (wave 0): the moved and unmoved values of the row below at steps
-  // gr*G - 1 + i, records of indices gr*G + TZ + i (TZ is a multiple of VPP,
-  // so they form whole pieces)
-  auto load_zh = [&](int gr, u32x4 (&zo)[ZP], u32x4 (&zy)[ZP]) {
-    if (!wave0) return;  // (a uniform branch)
+  // The halo of one group as loaded: the wave's y-record and its z pieces
+  // (the moved and unmoved values of the row below at steps gr*G - 1 + i,
+  // records of indices gr*G + TZ + i; TZ is a multiple of VPP, so they form
+  // whole pieces).  A piece past ZP is loaded through a descriptor of zero
+  // records, so every wave issues the same loads on every path.
+  struct Halo {
+    u32x4 yh;
+    u32x4 zo[ZPW], zy[ZPW];
+  };
+  auto zpiece_of = [&](int k) -> int { return w + NW * k; };
+  auto load_h = [&](int gr, Halo& h) {
+    h.yh = load_yh(gr);
+    if constexpr (kZX) {
 #pragma unroll
-    for (int j = 0; j < ZP; j++) {
-      zo[j] = __builtin_amdgcn_raw_buffer_load_b128(rz_in, z_unit(pred_z0, 0, gr * G + TZ + VPP * j), 0, kCoherent);
-      zy[j] = __builtin_amdgcn_raw_buffer_load_b128(rz_in, z_unit(pred_z0, 1, gr * G + TZ + VPP * j), 0, kCoherent);
+      for (int k = 0; k < ZPW; k++) {
+        const int j = zpiece_of(k);
+        const __amdgpu_buffer_rsrc_t r = j < ZP ? rz_in : make_rsrc(A.xz, 0);
+        h.zo[k] = __builtin_amdgcn_raw_buffer_load_b128(r, z_unit(pred_z0, 0, gr * G + TZ + VPP * j), 0, kCoherent);
+        h.zy[k] = __builtin_amdgcn_raw_buffer_load_b128(r, z_unit(pred_z0, 1, gr * G + TZ + VPP * j), 0, kCoherent);
+      }
     }
   };
-  // Whether the halo of group gr holds this launch's records (wave-uniform).
-  auto halo_ok = [&](int gr, u32x4 yh, const u32x4 (&zo)[ZP], const u32x4 (&zy)[ZP]) -> bool {
+  // Whether the wave's part of the halo of group gr holds this launch's
+  // records (wave-uniform).
+  auto halo_ok = [&](int gr, const Halo& h) -> bool {
     const int ys = gr * G + kWLanes + (ly & (G - 1));
-    bool ok = !need_y || ys >= last_rec || (yh[1] == tag && yh[3] == tag);
-    if (need_z) {
+    bool ok = !need_y || ys >= last_rec || (h.yh[1] == tag && h.yh[3] == tag);
+    if constexpr (kZX) {
+      if (need_z) {
 #pragma unroll
-      for (int j = 0; j < ZP; j++) {
-        const int k0 = gr * G + TZ + VPP * j, k1 = k0 + VPP - 1;  // indices of the piece's units
-        ok &= k0 > last_rec || (zo[j][1] == tag && zy[j][1] == tag);
-        ok &= k1 > last_rec || (zo[j][3] == tag && zy[j][3] == tag);
+        for (int k = 0; k < ZPW; k++) {
+          const int j = zpiece_of(k);
+          const int k0 = gr * G + TZ + VPP * j, k1 = k0 + VPP - 1;  // indices of the piece's units
+          ok &= j >= ZP || k0 > last_rec || (h.zo[k][1] == tag && h.zy[k][1] == tag);
+          ok &= j >= ZP || k1 > last_rec || (h.zo[k][3] == tag && h.zy[k][3] == tag);
+        }
       }
     }
     return __builtin_amdgcn_ballot_w64(!ok) == 0;
   };
   // Reload the halo of group gr until it holds this launch's records (the
   // predecessor is still writing it), or until the launch has failed.
-  auto poll_halo = [&](int gr, u32x4& yh, u32x4 (&zo)[ZP], u32x4 (&zy)[ZP]) {
+  auto poll_halo = [&](int gr, Halo& h) {
     uint32_t spins = 0;
-    while (!halo_ok(gr, yh, zo, zy)) {
+    while (!halo_ok(gr, h)) {
       if (__hip_atomic_load(&P->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
       if (++spins > kSpinLimit) {
         if (ly == 0) atomicCAS(&P->status, 0, kStatusStalled);
         break;
       }
       __builtin_amdgcn_s_sleep(1);
-      yh = load_yh(gr);
-      load_zh(gr, zo, zy);
+      load_h(gr, h);
     }
   };
 
@@ -546,11 +564,13 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile_in, u
   for (int a = 0; a < AZ; a++) O1[a] = O2[a] = Y1[a] = Y2[a] = Y3[a] = T(0);
   T VO1 = T(0), VO2 = T(0), VY1 = T(0), VY2 = T(0), VY3 = T(0);  // row below sub-row 0
 
-  // halo records of the next group, loaded during this one
-  u32x4 yh_nx = {0, 0, 0, 0};
-  u32x4 zo_nx[ZP], zy_nx[ZP];
+  // halo records of the next group, loaded during this one (a halo loaded
+  // two groups ahead hides more of the loads' latency but adds a group to
+  // the lag between dependent tiles, which costs more)
+  Halo hnx;
+  hnx.yh = u32x4{0, 0, 0, 0};
 #pragma unroll
-  for (int j = 0; j < ZP; j++) zo_nx[j] = zy_nx[j] = u32x4{0, 0, 0, 0};
+  for (int k = 0; k < ZPW; k++) hnx.zo[k] = hnx.zy[k] = u32x4{0, 0, 0, 0};
   T ezo[G], ezy[G];  // last wave: records of indices g*G + i (index k = value of step k - 1)
 #pragma unroll
   for (int i = 0; i < G; i++) ezo[i] = ezy[i] = T(0);
@@ -649,17 +669,25 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile_in, u
 
   // The halo of a group into LDS: the y-records into s_yin, and the z-halo
   // into slot 0 of the exchange ring, the value of step gr*G + i - 1 at entry
-  // (i - 1) mod G, where wave 0 reads it at step gr*G + i.  The other waves
-  // write their (unloaded) z registers to slot NW, which nobody reads: every
-  // path that loads a register then reads it, so the compiler's count of
-  // loads in flight stays exact and it adds no waits of its own.
-  const int zslot = wave0 ? 0 : NW;
-  auto put_halo = [&](u32x4 yh, const u32x4 (&zo)[ZP], const u32x4 (&zy)[ZP]) {
-    s_yin[w][ly & (G - 1)] = u32x2{yh[0], yh[2]};  // lanes l and l + G hold the same record
+  // (i - 1) mod G, where wave 0 reads it at step gr*G + i.  A wave writes the
+  // pieces it owns; only wave 0's piece 0 is read before the next barrier.
+  // Pieces past ZP go to slot NW, which nobody reads: every path that loads
+  // a register then reads it, so the compiler's count of loads in flight
+  // stays exact and it adds no waits of its own.
+  auto put_halo = [&](const Halo& h) {
+    s_yin[w][ly & (G - 1)] = u32x2{h.yh[0], h.yh[2]};  // lanes l and l + G hold the same record
+    if constexpr (kZX) {
 #pragma unroll
-    for (int i = 0; i < G; i++) {
-      s_xw[(i + G - 1) & (G - 1)][zslot][0][ly] = piece_value<T>(zo[i / VPP], i % VPP);
-      s_xw[(i + G - 1) & (G - 1)][zslot][1][ly] = piece_value<T>(zy[i / VPP], i % VPP);
+      for (int k = 0; k < ZPW; k++) {
+        const int j = zpiece_of(k);
+        const int slot = j < ZP ? 0 : NW;
+#pragma unroll
+        for (int u = 0; u < VPP; u++) {
+          const int e = (VPP * j + u + G - 1) & (G - 1);
+          s_xw[e][slot][0][ly] = piece_value<T>(h.zo[k], u);
+          s_xw[e][slot][1][ly] = piece_value<T>(h.zy[k], u);
+        }
+      }
     }
     // lanes 0..G-1 wrote the records every lane of the wave reads next;
     // keep the compiler from moving the reads above the writes
@@ -668,7 +696,7 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile_in, u
   // Load, check and write the halo of group gr until it holds this launch's
   // records (after a failed check).
   auto repoll_halo = [&](int gr) {
-    u32x4 yh, zo[ZP], zy[ZP];
+    Halo h;
     uint32_t spins = 0;
     do {
       if (__hip_atomic_load(&P->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
@@ -677,12 +705,9 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile_in, u
         break;
       }
       __builtin_amdgcn_s_sleep(1);
-      yh = load_yh(gr);
-#pragma unroll
-      for (int j = 0; j < ZP; j++) zo[j] = zy[j] = u32x4{0, 0, 0, 0};
-      load_zh(gr, zo, zy);
-    } while (!halo_ok(gr, yh, zo, zy));
-    put_halo(yh, zo, zy);
+      load_h(gr, h);
+    } while (!halo_ok(gr, h));
+    put_halo(h);
   };
   // One 16-byte piece of the cooperative input load of group gr.
   auto coop_load1 = [&](int a, int h, int gr) -> uint4 {
@@ -696,11 +721,10 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile_in, u
 
   // ---- prologue: halo and input of the first group
   {
-    u32x4 yh0 = load_yh(0);
-    u32x4 zo0[ZP], zy0[ZP];
-    load_zh(0, zo0, zy0);
-    poll_halo(0, yh0, zo0, zy0);
-    put_halo(yh0, zo0, zy0);
+    Halo h0;
+    load_h(0, h0);
+    poll_halo(0, h0);
+    put_halo(h0);
     if (wave0) {
       // Rows before lane 0 run ahead of it: the y-halo row (skew -1) already
       // produced x = 0 at step -1, and the corner row (z-1, y-1; skew -2) at
@@ -978,17 +1002,14 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile_in, u
         // (its own LDS accesses complete in order)
         if constexpr (NW > 1) __syncthreads();
         // the next group's halo, checked at the end of this one
-        if (i == 0) {
-          yh_nx = load_yh(g + 1);
-          load_zh(g + 1, zo_nx, zy_nx);
-        }
+        if (i == 0) load_h(g + 1, hnx);
       }
 
 
       // ---- group end.  First the check of the next group's halo (loaded
       // after step 0): vector memory operations retire in order, so the wait
       // for its loads here includes none of this group's stores.
-      const bool halo_in = halo_ok(g + 1, yh_nx, zo_nx, zy_nx);
+      const bool halo_in = halo_ok(g + 1, hnx);
       // ---- the boundary records, stored and never waited for
       if (succ_y) {
         // lane 63's G records move to lanes 64 - G .. 63 (one record each)
@@ -1083,12 +1104,14 @@ __device__ __forceinline__ void wsweep_body(const WArgs& A, const int tile_in, u
           }
         }
       }
-      // ---- the halo of group g + 1 into LDS (this wave's reads of group g's
-      // halo are done: its LDS accesses complete in order).  If the check
-      // found a record still missing, the halo is polled again, in registers
-      // of its own, and written again.  (Past the last group the records are
-      // not waited for: see last_rec.)
-      put_halo(yh_nx, zo_nx, zy_nx);
+      // ---- the halo of group g + 1 into LDS.  Wave 0 read the entries of
+      // group g's halo before the barrier of the step that read them (the
+      // last at step G - 1), which every wave has passed, and its own reads
+      // complete in order.  If the check found a record still missing, the
+      // wave polls its part again, in registers of its own, and writes it
+      // again.  (Past the last group the records are not waited for: see
+      // last_rec.)
+      put_halo(hnx);
       if (!halo_in) repoll_halo(g + 1);
   };
   for (int g = 0; g < ngr; g += 2) {
