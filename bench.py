@@ -585,6 +585,11 @@ def main():
     dom, dom_ms = roof["kernel"], roof["launch_ms"]
     traffic = load_traffic(dom, f"cosmo{n}", roof["algorithmic_bytes_per_launch"])
     roof["traffic"] = traffic
+    if traffic:
+        # counter-measured HBM bytes over the same launch time, beside the
+        # algorithmic figure of `achieved`
+        roof["traffic_GBps"] = round(traffic / (dom_ms / 1e3) / 1e9, 2)
+        roof["traffic_frac"] = round(traffic / (dom_ms / 1e3) / 1e9 / HBM_PEAK_GBPS, 4)
 
     res = {
         "metric": METRIC,

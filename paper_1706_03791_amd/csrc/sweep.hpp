@@ -10,9 +10,17 @@
 // so all neighbours (z-a, y-b, x-c) were produced at strictly earlier steps.
 // Decompressed values live in an LDS ring of R slots along X; rows owned by
 // the neighbouring tiles ("halo rows") are copied into the same ring from a
-// global array that those tiles publish group by group (progress flags with
-// agent-scope release/acquire).  Tiles are claimed through an atomic ticket
-// in dependence order, so every tile a workgroup waits on is already running.
+// global array that those tiles publish group by group behind progress
+// flags.  The flags are relaxed agent-scope atomics; the ordering comes from
+// the data accesses themselves: the publishing tile writes its rows with
+// device-coherent stores (kCoherent: written through to the coherence point
+// of all XCDs), waits for every one of them to complete (vmcnt 0) and meets
+// its workgroup barrier before the flag store is issued; the waiting tile
+// reads the flag, meets a workgroup barrier (which the compiler does not
+// move memory accesses across) and only then issues its halo loads, also
+// device-coherent, so no cached copy can answer them.  Tiles are claimed
+// through an atomic ticket in dependence order, so every tile a workgroup
+// waits on is already running.
 //
 // Input and output rows stream through per-row LDS rings in aligned chunks of
 // kG elements, loaded and stored cooperatively (several lanes per row) so a

@@ -2,8 +2,9 @@
 check of the inter-tile exchange.
 
 Algorithm 1 predicts every point from decompressed neighbours, so the sweep
-tiles hand boundary values to each other and wait on each other's progress
-flags.  Running the same field under different tile shapes (wave tiles or
+tiles hand boundary values to each other: as tagged records that the next
+tile polls (wave tiles) or behind progress flags (row-per-thread tiles).
+Running the same field under different tile shapes (wave tiles or
 row-per-thread tiles) and different tile claim orders (another dependence
 order inside each block; independent blocks reversed) changes which
 workgroup runs which tile, when, and next to whom -- a missing wait or a
