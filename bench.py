@@ -164,6 +164,20 @@ def cpu_all_cores(x: np.ndarray, planes: int, kw: dict, workers: int):
                       f"decompress each, {wall:.2f} s wall including process start", **host_cpus()}
 
 
+SWEEP_STAGES = ("sweep_compress", "sweep_decompress")
+BREAKDOWN_STEPS = 3
+
+
+def merge_profiles(every_stage: dict, timed: dict) -> dict:
+    """Stage (ms, calls): the timed steps' figures where they were recorded,
+    else those of the untimed steps with every stage timed."""
+    out = dict(every_stage)
+    for k, (ms, calls) in timed.items():
+        if calls:
+            out[k] = (ms, calls)
+    return out
+
+
 def roundtrip(Z, torch, x, kw, steps=3, warmup=1):
     """Timed compress + decompress of a resident field through the C ABI;
     returns (row dict, reconstruction, stats)."""
@@ -177,7 +191,7 @@ def roundtrip(Z, torch, x, kw, steps=3, warmup=1):
     tc, td = [], []
     for i in range(warmup + steps):
         if i == warmup:
-            Z.sz_ctx_profile(ctx, True)
+            Z.sz_ctx_profile(ctx, True, stages=SWEEP_STAGES)
         t0 = time.perf_counter()
         rc, size, st = Z.sz_compress(ctx, p, x.data_ptr(), comp.data_ptr(), cap, st_)
         t1 = time.perf_counter()
@@ -190,7 +204,16 @@ def roundtrip(Z, torch, x, kw, steps=3, warmup=1):
         if i >= warmup:
             tc.append(t1 - t0)
             td.append(t2 - t1)
-    prof = Z.sz_ctx_profile_read(ctx)
+    prof_timed = Z.sz_ctx_profile_read(ctx)
+    Z.sz_ctx_profile(ctx, True)
+    for _ in range(min(steps, BREAKDOWN_STEPS)):
+        rc, size, st = Z.sz_compress(ctx, p, x.data_ptr(), comp.data_ptr(), cap, st_)
+        if rc:
+            raise Z.SzError(rc, "sz_compress")
+        rc = Z.sz_decompress(ctx, comp.data_ptr(), size, out.data_ptr(), S, st_)
+        if rc:
+            raise Z.SzError(rc, "sz_decompress")
+    prof = merge_profiles(Z.sz_ctx_profile_read(ctx), prof_timed)
     Z.sz_ctx_profile(ctx, False)
     t_c, t_d = float(np.median(tc)), float(np.median(td))
     row = {"GBps": round(2 * S / (t_c + t_d) / 1e9, 3), "compress_GBps": round(S / t_c / 1e9, 3),
@@ -541,7 +564,11 @@ def main():
     print("[bench] warmup", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
-    Z.sz_ctx_profile(ctx, True)
+    # Inside the timed steps only the two sweeps (one of which is the
+    # dominant kernel) record events: every timed stage adds two event
+    # records to the stream.  The other stages' times come from untimed steps
+    # with every stage timed.
+    Z.sz_ctx_profile(ctx, True, stages=SWEEP_STAGES)
     torch.cuda.synchronize()
     tc, td = [], []
     t_start = time.perf_counter()
@@ -551,9 +578,14 @@ def main():
         td.append(b)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
-    prof = Z.sz_ctx_profile_read(ctx)
-    Z.sz_ctx_profile(ctx, False)
+    prof_timed = Z.sz_ctx_profile_read(ctx)
     print(f"[bench] timed {args.steps} steps in {t_total:.3f} s", file=sys.stderr, flush=True)
+    Z.sz_ctx_profile(ctx, True)
+    for _ in range(BREAKDOWN_STEPS):
+        step()
+    torch.cuda.synchronize()
+    prof = merge_profiles(Z.sz_ctx_profile_read(ctx), prof_timed)
+    Z.sz_ctx_profile(ctx, False)
 
     # correctness guard on the last step: the bound holds everywhere
     err = (out.double() - xd.double()).abs().max().item()
@@ -615,7 +647,7 @@ def main():
         "m_used": int(st.m_used),
         "m_suggested": int(st.m_suggested),
         "device_copy_GBps": round(copy_gbps, 1),
-        "timing": "median per-step compress and decompress times over the timed steps",
+        "timing": "median per-step compress and decompress times over the timed steps; stage_ms of the sweeps from HIP events in the timed steps, of the other stages from 3 untimed steps with every stage timed",
         "hit_rate": st.hit_rate,
         "n_unpred": int(st.n_unpred),
         "quality": quality,

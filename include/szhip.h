@@ -187,11 +187,15 @@ const char* sz_strerror(int code);
 /* Instrumentation (for benchmarks; not needed by callers of the codec).
  * sz_ctx_profile(ctx, 1) resets and enables per-stage HIP-event timing of
  * the synchronous calls sz_compress / sz_decompress on their stream;
+ * sz_ctx_profile(ctx, SZ_PROFILE_STAGES | mask) times only the stages whose
+ * bits (in the order below) are set in mask, since every timed stage adds
+ * two event records to the stream; 0 disables; other values: SZ_EINVAL.
  * sz_ctx_profile_read fills up to n accumulated milliseconds and call
  * counts, in the order: value range + bound, compression sweep, codebook,
  * encoding + container, decode tables, Huffman decode, unpredictable values,
  * reconstruction sweep, code histogram (when it is a kernel of its own).
  * Returns the number of stages. */
+#define SZ_PROFILE_STAGES 0x10000
 int sz_ctx_profile(sz_ctx* ctx, int enable);
 /* Schedule-invariance check (for tests; not needed by callers of the codec).
  * Later calls on the context run their prediction and reconstruction sweeps

@@ -206,8 +206,12 @@ def sz_quantize(ctx, p: SzParams, d_in: int, d_codes: int, d_xprime: int = 0, st
     return rc, st
 
 
-def sz_ctx_profile(ctx, enable: bool = True) -> int:
-    return lib().sz_ctx_profile(C.c_void_p(ctx), int(enable))
+def sz_ctx_profile(ctx, enable: bool = True, stages=None) -> int:
+    """Per-stage event timing: off, every stage, or only the named stages."""
+    value = int(enable)
+    if enable and stages is not None:
+        value = 0x10000 | sum(1 << STAGES.index(name) for name in stages)
+    return lib().sz_ctx_profile(C.c_void_p(ctx), value)
 
 
 def sz_ctx_debug_sweep(ctx, schedule: int, claim_order: int) -> int:

@@ -92,7 +92,9 @@ int sz_ctx_profile(sz_ctx* c, int enable) {
     c->prof_calls[i] = 0;
     c->ev_used[i] = false;
   }
+  if ((enable & ~0x1FFFF) != 0 || (enable > 1 && !(enable & 0x10000))) return SZ_EINVAL;
   c->prof = enable != 0;
+  c->prof_mask = (enable & 0x10000) ? (uint32_t)(enable & 0xFFFF) : 0xFFFFu;
   return SZ_OK;
 }
 

@@ -35,6 +35,7 @@ enum Stage {
 struct sz_ctx {
   int device = 0;
   bool prof = false;
+  uint32_t prof_mask = 0xFFFFu;  // stages the profiler times (bit = Stage)
   hipEvent_t ev[2 * ST_COUNT] = {};
   bool ev_used[ST_COUNT] = {};
   double prof_ms[ST_COUNT] = {};
@@ -67,12 +68,12 @@ namespace {
   } while (0)
 
 void stage_begin(sz_ctx* c, int id, hipStream_t st) {
-  if (!c->prof) return;
+  if (!c->prof || !((c->prof_mask >> id) & 1u)) return;
   (void)hipEventRecord(c->ev[2 * id], st);
   c->ev_used[id] = true;
 }
 void stage_end(sz_ctx* c, int id, hipStream_t st) {
-  if (c->prof) (void)hipEventRecord(c->ev[2 * id + 1], st);
+  if (c->prof && ((c->prof_mask >> id) & 1u)) (void)hipEventRecord(c->ev[2 * id + 1], st);
 }
 // After the stream has been synchronised: accumulate the recorded stages.
 void stage_collect(sz_ctx* c) {

@@ -7,6 +7,8 @@
   and status it writes to device memory, sz_compress and the oracle.
 * sz_ctx_create / sz_ctx_destroy: contexts made and destroyed in turn (and
   several alive at once) give identical results; destroying NULL is a no-op.
+* sz_ctx_profile: a stage mask times only the stages it names; values it
+  does not define are rejected.
 """
 import sys
 
@@ -150,3 +152,42 @@ def test_ctx_create_destroy(Z, oracle):
         assert rc == 0 and out[:n].cpu().numpy().tobytes() == ref
         Z.sz_ctx_destroy(c)
     Z.sz_ctx_destroy(0)  # NULL: no-op
+
+
+def test_stage_profiler_mask(Z):
+    """sz_ctx_profile with a stage mask times only those stages; bad values
+    are rejected."""
+    import torch
+    ctx = Z.sz_ctx_create(0)
+    try:
+        x = torch.from_numpy(F.smooth3d((48, 40, 72))).cuda()
+        p = Z.make_params(tuple(x.shape), x.dtype, layers=1, m=8, eb_mode="rel", eb_rel=1e-4)
+        cap = Z.sz_compress_bound(p)
+        comp = torch.empty(cap, dtype=torch.uint8, device="cuda")
+        out = torch.empty_like(x)
+        st_ = torch.cuda.current_stream().cuda_stream
+
+        def roundtrip():
+            rc, size, _ = Z.sz_compress(ctx, p, x.data_ptr(), comp.data_ptr(), cap, st_)
+            assert rc == 0
+            assert Z.sz_decompress(ctx, comp.data_ptr(), size, out.data_ptr(), x.numel() * 4, st_) == 0
+
+        assert Z.sz_ctx_profile(ctx, True, stages=("sweep_compress", "sweep_decompress")) == 0
+        roundtrip()
+        prof = Z.sz_ctx_profile_read(ctx)
+        timed = {k for k, (ms, calls) in prof.items() if calls}
+        assert timed == {"sweep_compress", "sweep_decompress"}, prof
+        assert Z.sz_ctx_profile(ctx, True) == 0
+        roundtrip()
+        prof = Z.sz_ctx_profile_read(ctx)
+        assert {"range", "sweep_compress", "encode", "decode", "sweep_decompress"} <= \
+            {k for k, (ms, calls) in prof.items() if calls}
+        assert Z.sz_ctx_profile(ctx, False) == 0
+        roundtrip()
+        assert all(calls == 0 for ms, calls in Z.sz_ctx_profile_read(ctx).values())
+        L = Z.lib()
+        import ctypes as C
+        for bad in (2, 0x20000, -1, 0x10000 | 0x20000):
+            assert L.sz_ctx_profile(C.c_void_p(ctx), bad) == -1, bad
+    finally:
+        Z.sz_ctx_destroy(ctx)
