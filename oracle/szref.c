@@ -33,7 +33,7 @@
 #define HDR_SIZE 192u
 #define SECTION_ALIGN 64u
 #define MAGIC 0x31485A53u /* bytes "SZH1" */
-#define VERSION 1u
+#define VERSION 2u
 
 /* ------------------------------------------------------------------ layout */
 
@@ -481,6 +481,7 @@ static int compress_impl(const szref_params* p, const void* data, uint8_t** out,
 
   struct bitwriter bs = {0}, hd = {0}, tl = {0};
   uint32_t* chunk_bits = NULL;
+  uint16_t* chunk_mid = NULL;
   uint32_t* uchunk = NULL;
   uint8_t* len = NULL;
   uint32_t* cw = NULL;
@@ -520,11 +521,15 @@ static int compress_impl(const szref_params* p, const void* data, uint8_t** out,
   if (bw_init(&bs) || bw_init(&hd) || bw_init(&tl)) { rc = SZREF_ENOMEM; goto done; }
   uint64_t n_chunks = (n + C - 1) / C;
   chunk_bits = (uint32_t*)calloc(n_chunks, 4);
-  if (!chunk_bits) { rc = SZREF_ENOMEM; goto done; }
+  chunk_mid = (uint16_t*)calloc(n_chunks, 2);
+  if (!chunk_bits || !chunk_mid) { rc = SZREF_ENOMEM; goto done; }
   for (uint64_t i = 0; i < n; i++) {
     uint64_t before = bs.nbits;
     bw_put(&bs, cw[codes[i]], len[codes[i]]);
     chunk_bits[i / C] += (uint32_t)(bs.nbits - before);
+    /* reading A17: the bits of a chunk's first half, where a second decoder
+     * of the chunk starts (at most C/2 * LMAX < 2^16 bits) */
+    if (i % C < C / 2) chunk_mid[i / C] += (uint16_t)(bs.nbits - before);
   }
   const int xor_coding = p->unpred_coding == 1;
   if (xor_coding) {
@@ -558,7 +563,7 @@ static int compress_impl(const szref_params* p, const void* data, uint8_t** out,
   h.chunk = C; h.n_used = n_used; h.n_chunks = n_chunks;
   h.off_cb = HDR_SIZE;
   h.off_ch = align_up(h.off_cb + 3ull * n_used, SECTION_ALIGN);
-  h.off_bs = align_up(h.off_ch + 4ull * n_chunks, SECTION_ALIGN);
+  h.off_bs = align_up(h.off_ch + 6ull * n_chunks, SECTION_ALIGN);
   h.off_hd = align_up(h.off_bs + 4ull * ((bs.nbits + 31) / 32), SECTION_ALIGN);
   h.off_tl = align_up(h.off_hd + 4ull * ((hd.nbits + 31) / 32), SECTION_ALIGN);
   h.total = h.off_tl + 4ull * ((tl.nbits + 31) / 32);
@@ -593,6 +598,7 @@ static int compress_impl(const szref_params* p, const void* data, uint8_t** out,
       cb += 3;
     }
     for (uint64_t c = 0; c < n_chunks; c++) put_u32(buf + h.off_ch + 4 * c, chunk_bits[c]);
+    for (uint64_t c = 0; c < n_chunks; c++) put_u16(buf + h.off_ch + 4 * n_chunks + 2 * c, chunk_mid[c]);
     for (uint64_t wd = 0; wd < (bs.nbits + 31) / 32; wd++) put_u32(buf + h.off_bs + 4 * wd, bs.words[wd]);
     for (uint64_t wd = 0; wd < (hd.nbits + 31) / 32; wd++) put_u32(buf + h.off_hd + 4 * wd, hd.words[wd]);
     for (uint64_t wd = 0; wd < (tl.nbits + 31) / 32; wd++) put_u32(buf + h.off_tl + 4 * wd, tl.words[wd]);
@@ -614,6 +620,7 @@ static int compress_impl(const szref_params* p, const void* data, uint8_t** out,
   rc = SZREF_OK;
 done:
   free(chunk_bits);
+  free(chunk_mid);
   free(uchunk);
   free(bs.words); free(hd.words); free(tl.words);
   free(codes); free(xp); free(hist); free(len); free(cw);
@@ -689,7 +696,7 @@ int szref_decompress(const uint8_t* comp, size_t size, void* out, size_t cap) {
   const uint64_t max_tail = xor_coding ? (h.dtype ? 3 + 64 : 2 + 32) : (h.dtype ? 52 : 23);
   if (h.n_used > nsym || h.n_unpred > n || h.huff_bits > n * LMAX || h.tail_bits > h.n_unpred * max_tail)
     return SZREF_ECORRUPT;
-  if (!section_fits(h.off_cb, 3ull * h.n_used, h.total) || !section_fits(h.off_ch, 4ull * h.n_chunks, h.total) ||
+  if (!section_fits(h.off_cb, 3ull * h.n_used, h.total) || !section_fits(h.off_ch, 6ull * h.n_chunks, h.total) ||
       !section_fits(h.off_bs, 4ull * ((h.huff_bits + 31) / 32), h.total) ||
       !section_fits(h.off_hd, 4ull * ((head_bits + 31) / 32), h.total) ||
       !section_fits(h.off_tl, 4ull * ((h.tail_bits + 31) / 32), h.total))
@@ -720,12 +727,17 @@ int szref_decompress(const uint8_t* comp, size_t size, void* out, size_t cap) {
    * until it equals the code of some symbol of that length. */
   {
     struct bitreader br = {bsw, h.huff_bits, 0};
-    uint64_t nz = 0, want = 0;
+    uint64_t nz = 0, want = 0, cstart = 0;
     for (uint64_t i = 0; i < n; i++) {
       if (i % h.chunk == 0) {
         if (want != br.pos) goto out;
+        cstart = br.pos;
         want += get_u32(comp + h.off_ch + 4 * (i / h.chunk));
       }
+      /* reading A17: the stored start of the chunk's second half */
+      if (i % h.chunk == h.chunk / 2 &&
+          br.pos != cstart + get_u16(comp + h.off_ch + 4 * h.n_chunks + 2 * (i / h.chunk)))
+        goto out;
       uint32_t v = 0;
       int l = 0, found = -1;
       while (found < 0) {

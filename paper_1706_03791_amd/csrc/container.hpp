@@ -13,7 +13,8 @@
 // 120 u32 symbols per chunk    124 u32 codebook entries  128 u64 chunks
 // 136..176 u64 offsets: codebook, chunk table, bitstream, heads, tails, total
 // Sections: codebook (u16 symbol, u8 length) sorted by symbol; chunk table
-// (u32 bits per chunk); Huffman bitstream; heads (sign+exponent, 9 or 12
+// (u32 bits per chunk, then u16 bits of each chunk's first half of symbols,
+// where a second decoder of the chunk starts); Huffman bitstream; heads (sign+exponent, 9 or 12
 // bits each); tails (kept mantissa bits).  Bit streams are MSB-first in
 // little-endian u32 words.  A raw container (flag bit 0) is the header
 // followed by the field itself.  With flag bit 1 the unpredictable values
@@ -29,7 +30,7 @@
 namespace szh {
 
 constexpr uint32_t kMagic = 0x31485A53u;
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 constexpr uint32_t kHdr = 192;
 constexpr uint32_t kAlign = 64;
 constexpr uint32_t kDefaultChunk = 1024;
@@ -138,7 +139,7 @@ inline int check_sections(const Hdr& h) {
   // each term below is < 2^46, so none of the sums can wrap
   const uint64_t off_cb = kHdr;
   const uint64_t off_ch = hdr_align64(off_cb + 3ull * h.n_used);
-  const uint64_t off_bs = hdr_align64(off_ch + 4ull * h.n_chunks);
+  const uint64_t off_bs = hdr_align64(off_ch + 6ull * h.n_chunks);
   const uint64_t off_hd = hdr_align64(off_bs + 4ull * ((h.huff_bits + 31) / 32));
   const uint64_t off_tl = hdr_align64(off_hd + 4ull * ((head_bits + 31) / 32));
   const uint64_t total = off_tl + 4ull * ((h.tail_bits + 31) / 32);

@@ -1529,7 +1529,7 @@ __device__ __forceinline__ void layout_kernel_dev(LayoutArgs A) {
   P->tail_bits = *A.tot_tb;
   P->off_cb = kHdr;
   P->off_ch = align64(kHdr + 3ull * P->n_used);
-  P->off_bs = align64(P->off_ch + 4ull * A.n_chunks);
+  P->off_bs = align64(P->off_ch + 6ull * A.n_chunks);
   P->off_hd = align64(P->off_bs + 4ull * ((P->huff_bits + 31) / 32));
   P->off_tl = align64(P->off_hd + (A.xorc ? 4ull * A.n_chunks : 4ull * ((P->n_unpred * A.head_bits + 31) / 32)));
   P->total = P->off_tl + 4ull * ((P->tail_bits + 31) / 32);
@@ -1642,6 +1642,9 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
       if (lane == 0) hd[c] = tot;
     }
     const uint64_t bpos = (b0 & 31) + wave_exscan(mybits);
+    // the bits of the chunk's first half (lanes 0..31 hold its first C/2
+    // codes): where a second decoder of the chunk starts
+    if (lane == 32) ((uint16_t*)(ch + n_chunks))[c] = (uint16_t)(bpos - (b0 & 31));
     const uint64_t zpos = uoff[c] + wave_exscan(myz);
     const uint64_t tpos = toff[c] + wave_exscan(mytb);
     __builtin_amdgcn_wave_barrier();

@@ -32,10 +32,11 @@ MUTANTS = {
         "  UT prev = 0;\n  for (uint64_t c = 0; c * C < n; c++) {\n    const uint64_t before = recs->nbits;"),
     "xor leading byte cap": ("szref_traverse.inc", "while (lzb < BMAX &&", "while (lzb <= BMAX &&"),
     "xor record length": ("szref_traverse.inc", "const int nb = q - 8 * lzb;", "const int nb = q - 8 * lzb + 1;"),
+    "chunk half offset": ("szref.c", "if (i % C < C / 2) chunk_mid", "if (i % C <= C / 2) chunk_mid"),
 }
 
 FAST = ("table1 or lorenzo or finite_difference or theorem1 or hand or brute or m1_ or "
-        "truncation or tie_rule")
+        "truncation or tie_rule or half_offsets")
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))

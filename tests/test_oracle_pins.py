@@ -14,6 +14,7 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
+import fieldgen as F
 from conftest import golden
 
 # ----------------------------------------------------------- coefficients
@@ -169,6 +170,40 @@ def test_hand_1d_bitstream(oracle):
     cb = [struct.unpack_from("<HB", buf, off + 3 * i) for i in range(3)]
     assert cb == [(1, 2), (2, 1), (3, 2)]
     assert np.array_equal(oracle.decompress(buf), x)
+
+
+def test_chunk_half_offsets(oracle):
+    """Reading A17: after the u32 bit counts, the chunk table holds for each
+    chunk the bits of its first C/2 codes (all of them in a chunk of at most
+    C/2 codes).  Recomputed here from the codes and the code lengths of the
+    container's codebook; a wrong entry is rejected by the decompressor."""
+    C = 256
+    for n in (640, 700, 1024):
+        x = np.cumsum(F.rng(7).normal(0, 1, n)).astype(np.float32)
+        buf, st, codes, _ = oracle.compress(x, debug=True, m=6, eb_mode="abs", eb_abs=0.05, chunk=C)
+        assert st["raw_fallback"] == 0
+        nc = int.from_bytes(buf[128:136], "little")
+        assert nc == (n + C - 1) // C
+        off_cb = int.from_bytes(buf[136:144], "little")
+        off_ch = int.from_bytes(buf[144:152], "little")
+        n_used = int.from_bytes(buf[124:128], "little")
+        lens = np.zeros(1 << 6, np.int64)
+        for i in range(n_used):
+            sym, ln = struct.unpack_from("<HB", buf, off_cb + 3 * i)
+            lens[sym] = ln
+        bits = lens[codes.astype(np.int64)]
+        for c in range(nc):
+            lo, hi = c * C, min(n, (c + 1) * C)
+            total = int.from_bytes(buf[off_ch + 4 * c: off_ch + 4 * c + 4], "little")
+            half = int.from_bytes(buf[off_ch + 4 * nc + 2 * c: off_ch + 4 * nc + 2 * c + 2], "little")
+            assert total == int(bits[lo:hi].sum())
+            assert half == int(bits[lo:min(hi, lo + C // 2)].sum())
+        assert np.max(np.abs(oracle.decompress(buf).astype(np.float64) - x)) < 0.05
+        bad = bytearray(buf)
+        pos = off_ch + 4 * nc
+        bad[pos] = (bad[pos] + 1) & 0xFF
+        with pytest.raises(oracle.OracleError):
+            oracle.decompress(bytes(bad))
 
 
 def test_hand_1d_unpredictable(oracle):
