@@ -2056,6 +2056,14 @@ __global__ void __launch_bounds__(1024) dectab_kernel(const uint8_t* comp, uint6
 constexpr uint32_t kSymLds = 4096;
 constexpr int kDecRing = 16;    // words of bitstream per lane in LDS (1-byte codes)
 constexpr int kDecPeriod = 8;   // iterations between the reloads of all lanes
+// Decoder lanes: 1-byte codes run two lanes per chunk (one per half, the
+// second from the chunk's stored half offset) in 1024-thread workgroups, so
+// one copy of the decode tables serves four waves per SIMD; 2-byte codes
+// one lane per chunk in 256-thread workgroups.
+template <typename CT> struct DecShape {
+  static constexpr int NT = sizeof(CT) == 1 ? 1024 : 256;  // threads per workgroup
+  static constexpr int LPC = sizeof(CT) == 1 ? 2 : 1;      // lanes per chunk
+};
 
 __device__ __forceinline__ uint4 load_words4(const uint32_t* words, uint64_t nwords, uint64_t w) {
   if (w + 4 <= nwords) return *(const uint4*)(words + w);
@@ -2071,34 +2079,35 @@ __device__ __forceinline__ uint32_t pick4(const uint4& v, int i) {
 }
 
 template <typename CT>
-__global__ void __launch_bounds__(256) decode_kernel(const uint8_t* __restrict__ comp, uint64_t off_bs,
+__global__ void __launch_bounds__(DecShape<CT>::NT) decode_kernel(const uint8_t* __restrict__ comp, uint64_t off_bs,
                                                      uint64_t nwords, uint64_t n, uint32_t C, uint64_t n_chunks,
                                                      const uint32_t* cbits, const uint64_t* boff,
                                                      const DecTables* D, const uint32_t* sorted_syms,
                                                      CT* codes, uint32_t* segcnt, int64_t X, int64_t Bx,
                                                      int32_t nbx, DevPlan* P) {
+  constexpr int NT = DecShape<CT>::NT, LPC = DecShape<CT>::LPC;
   __shared__ uint32_t lut[4096];
   __shared__ uint32_t s_first[32], s_start[32], s_lim[32];
   constexpr uint32_t kSyms = sizeof(CT) == 1 ? 256 : kSymLds;
   __shared__ uint16_t s_syms[kSyms];
-  __shared__ uint32_t s_win[sizeof(CT) == 1 ? 1 : 4][256];  // each lane's current 16-byte group, word-major
+  __shared__ uint32_t s_win[sizeof(CT) == 1 ? 1 : 4][sizeof(CT) == 1 ? 1 : NT];  // each lane's current 16-byte group
   __shared__ uint32_t s_lut2[sizeof(CT) == 1 ? kLut2Max * 16 : 1];
   __shared__ uint2 s_mlut[sizeof(CT) == 1 ? 4096 : 1];
-  __shared__ uint32_t s_ring[sizeof(CT) == 1 ? kDecRing : 1][256];  // 1-byte codes: per-lane bitstream ring
+  __shared__ uint32_t s_ring[sizeof(CT) == 1 ? kDecRing : 1][sizeof(CT) == 1 ? NT : 1];  // 1-byte codes: per-lane bitstream ring
   const uint32_t nsorted = D->nsorted;
   const bool syms_lds = nsorted <= kSyms;
   const uint32_t n2 = sizeof(CT) == 1 ? D->lut2_n : 0u, p02 = sizeof(CT) == 1 ? D->lut2_p0 : 0u;
   if constexpr (sizeof(CT) == 1)
     if (n2)
-      for (uint32_t i = threadIdx.x; i < kLut2Max * 16; i += 256) s_lut2[i] = D->lut2[i];
-  for (int i = threadIdx.x; i < 4096; i += 256) lut[i] = D->lut[i];
+      for (uint32_t i = threadIdx.x; i < kLut2Max * 16; i += NT) s_lut2[i] = D->lut2[i];
+  for (int i = threadIdx.x; i < 4096; i += NT) lut[i] = D->lut[i];
   if constexpr (sizeof(CT) == 1)
-    for (int i = threadIdx.x; i < 4096; i += 256) {
+    for (int i = threadIdx.x; i < 4096; i += NT) {
       const uint64_t e = D->mlut[i];
       s_mlut[i] = make_uint2((uint32_t)e, (uint32_t)(e >> 32));
     }
   if (syms_lds)
-    for (uint32_t i = threadIdx.x; i < nsorted; i += 256) s_syms[i] = (uint16_t)sorted_syms[i];
+    for (uint32_t i = threadIdx.x; i < nsorted; i += NT) s_syms[i] = (uint16_t)sorted_syms[i];
   if (threadIdx.x < 32) {
     s_first[threadIdx.x] = D->first[threadIdx.x];
     s_start[threadIdx.x] = D->start[threadIdx.x];
@@ -2106,16 +2115,35 @@ __global__ void __launch_bounds__(256) decode_kernel(const uint8_t* __restrict__
   }
   __syncthreads();
   if (P->status) return;
-  const uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint64_t gl = (uint64_t)blockIdx.x * NT + threadIdx.x;
+  const uint64_t c = gl / LPC;
   if (c >= n_chunks) return;
+  const uint32_t hf = (uint32_t)(gl % LPC);  // half of the chunk (two lanes per chunk)
   const int t = threadIdx.x;
   // The bitstream is read in 16-byte aligned groups of 4 words: the group in
   // use sits in this lane's LDS slot, the next one is in flight in registers
   // (never copied, so its load is waited for only when it is needed).
   const uint32_t* words = (const uint32_t*)(comp + off_bs);  // 64-byte aligned section
+  // The lane's span of the chunk: the whole chunk, or with two lanes per
+  // chunk its first or second half, split at the stored half offset (the
+  // u16 table after the chunk bit counts).
   uint64_t pos = boff[c];
-  const uint64_t end = pos + cbits[c];
-  const uint64_t i0 = c * C, i1 = min(n, i0 + C);
+  uint64_t end = pos + cbits[c];
+  uint64_t i0 = c * C, i1 = min(n, i0 + C);
+  if constexpr (LPC == 2) {
+    const uint32_t mid = ((const uint16_t*)(cbits + n_chunks))[c];
+    if (mid > cbits[c]) {
+      set_status(P, SZ_ECORRUPT);
+      return;
+    }
+    if (hf == 0) {
+      end = pos + mid;
+      i1 = min(i1, i0 + C / 2);
+    } else {
+      pos += mid;
+      i0 = min(i1, i0 + C / 2);
+    }
+  }
   uint64_t wg = (pos >> 5) & ~3ull;
   uint4 pend = make_uint4(0, 0, 0, 0);
   int wi = 0;

@@ -781,16 +781,17 @@ int enqueue_decompress_t(sz_ctx* ctx, const Layout& L, const Hdr& h, const void*
   stage_end(ctx, ST_DECTAB, st);
   stage_begin(ctx, ST_DECODE, st);
   const uint64_t nwords = (h.huff_bits + 31) / 32;
-  const unsigned gdec = (unsigned)ceil_div(L.n_chunks, 256);
+  const unsigned gdec8 = (unsigned)ceil_div(L.n_chunks * DecShape<uint8_t>::LPC, DecShape<uint8_t>::NT);
+  const unsigned gdec16 = (unsigned)ceil_div(L.n_chunks * DecShape<uint16_t>::LPC, DecShape<uint16_t>::NT);
   const int64_t X = L.dims3[2], Bx = L.blk3[2];
   const int32_t nbx = L.g.nblk[2];
   if (L.cw == 1)
-    hipLaunchKernelGGL(decode_kernel<uint8_t>, dim3(gdec), dim3(256), 0, st, comp, h.off_bs, nwords,
+    hipLaunchKernelGGL(decode_kernel<uint8_t>, dim3(gdec8), dim3(DecShape<uint8_t>::NT), 0, st, comp, h.off_bs, nwords,
                        (uint64_t)L.n, L.chunk, L.n_chunks, (const uint32_t*)(comp + h.off_ch),
                        (const uint64_t*)W.boff, (const DecTables*)W.tabs, (const uint32_t*)W.sorted,
                        (uint8_t*)W.codes, W.segcnt, X, Bx, nbx, P);
   else
-    hipLaunchKernelGGL(decode_kernel<uint16_t>, dim3(gdec), dim3(256), 0, st, comp, h.off_bs, nwords,
+    hipLaunchKernelGGL(decode_kernel<uint16_t>, dim3(gdec16), dim3(DecShape<uint16_t>::NT), 0, st, comp, h.off_bs, nwords,
                        (uint64_t)L.n, L.chunk, L.n_chunks, (const uint32_t*)(comp + h.off_ch),
                        (const uint64_t*)W.boff, (const DecTables*)W.tabs, (const uint32_t*)W.sorted,
                        (uint16_t*)W.codes, W.segcnt, X, Bx, nbx, P);
