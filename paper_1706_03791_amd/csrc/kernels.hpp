@@ -1128,11 +1128,20 @@ __device__ __forceinline__ void lds_code4(const CT* sc, uint32_t k, uint32_t (&o
 // else from the global length array.
 template <bool LT>
 __device__ __forceinline__ uint32_t code_entry(uint32_t s, const uint32_t* s_tab, const uint8_t* len,
-                                               const uint32_t* cw) {
-  if constexpr (LT)
+                                               const uint32_t* cw, uint32_t tlo) {
+  if constexpr (LT) {
     return s_tab[s];
-  else
+  } else {
+    // an alphabet larger than the LDS table: the table holds the window
+    // [tlo, tlo + kTabLds) around the centre code, where most codes fall
+    const uint32_t r = s - tlo;
+    if (r < kTabLds) return s_tab[r];
     return cw ? cw[s] : ((uint32_t)len[s] << 27);  // cw holds len << 27 | code
+  }
+}
+// First symbol of the LDS window of a 2^m-symbol table (0 when it all fits).
+__host__ __device__ constexpr uint32_t tab_window(uint32_t m) {
+  return (1u << m) > kTabLds ? (1u << (m - 1)) - kTabLds / 2 : 0u;
 }
 
 // Bit fields appended MSB-first to a stream from bit `pos` on, gathered in a
@@ -1245,7 +1254,7 @@ template <typename T, typename CT, bool LT>
 __device__ __forceinline__ void chunk_stats_body(const CT* __restrict__ codes, const T* __restrict__ x,
                                                  const uint8_t* __restrict__ len, const uint32_t* s_tab,
                                                  CT* sc, uint64_t n, uint32_t C, uint32_t* cbits, uint32_t* cu,
-                                                 uint32_t* ctb, typename FTr<T>::U ebb) {
+                                                 uint32_t* ctb, typename FTr<T>::U ebb, uint32_t tlo) {
   const uint64_t n_chunks = (n + C - 1) / C;
   const int lane = threadIdx.x & 63;
   const uint32_t per = C / 64;
@@ -1263,7 +1272,7 @@ __device__ __forceinline__ void chunk_stats_body(const CT* __restrict__ codes, c
 #pragma unroll
         for (int k = 0; k < 4; k++) {
           const uint32_t sym = (wv[g] >> (8 * k)) & 0xFFu;
-          b += code_entry<LT>(sym, s_tab, len, nullptr) >> 27;
+          b += code_entry<LT>(sym, s_tab, len, nullptr, tlo) >> 27;
           anyz |= sym == 0;
         }
         if (anyz) {
@@ -1287,7 +1296,7 @@ __device__ __forceinline__ void chunk_stats_body(const CT* __restrict__ codes, c
 #pragma unroll
         for (int k = 0; k < 4; k++) {
           const bool real = k0 + j + k < cnt;
-          b += real ? (code_entry<LT>(sym[k], s_tab, len, nullptr) >> 27) : 0u;
+          b += real ? (code_entry<LT>(sym[k], s_tab, len, nullptr, tlo) >> 27) : 0u;
           anyz |= real && sym[k] == 0;
         }
         if (anyz) {
@@ -1322,7 +1331,7 @@ template <typename T, typename CT, bool LT>
 __device__ __forceinline__ void chunk_stats_xor_body(const CT* __restrict__ codes, const T* __restrict__ x,
                                                      const uint8_t* __restrict__ len, const uint32_t* s_tab,
                                                      CT* sc, uint64_t n, uint32_t C, uint32_t* cbits, uint32_t* cu,
-                                                     uint32_t* ctb, typename FTr<T>::U ebb) {
+                                                     uint32_t* ctb, typename FTr<T>::U ebb, uint32_t tlo) {
   using U = typename FTr<T>::U;
   using XR = XorRec<T>;
   const uint64_t n_chunks = (n + C - 1) / C;
@@ -1342,7 +1351,7 @@ __device__ __forceinline__ void chunk_stats_xor_body(const CT* __restrict__ code
 #pragma unroll
       for (int k = 0; k < 4; k++) {
         const bool real = k0 + j + k < cnt;
-        b += real ? (code_entry<LT>(sym[k], s_tab, len, nullptr) >> 27) : 0u;
+        b += real ? (code_entry<LT>(sym[k], s_tab, len, nullptr, tlo) >> 27) : 0u;
         anyz |= real && sym[k] == 0;
       }
       if (anyz) {
@@ -1399,20 +1408,20 @@ __device__ __forceinline__ void chunk_stats_kernel_dev(const CT* __restrict__ co
   if (P->status) return;
   const uint32_t nsym = 1u << P->m;
   const bool lt = nsym <= kTabLds;
-  if (lt)
-    for (uint32_t i = threadIdx.x; i < nsym; i += 256) s_tab[i] = (uint32_t)len[i] << 27;
+  const uint32_t tlo = tab_window(P->m);
+  for (uint32_t i = threadIdx.x; i < min(nsym, kTabLds); i += 256) s_tab[i] = (uint32_t)len[tlo + i] << 27;
   __syncthreads();
   CT* sc = (CT*)s_dyn + (size_t)(threadIdx.x >> 6) * C;
   const auto ebb = (typename FTr<T>::U)P->ebT_bits;
   if (P->xorc) {
     if (sizeof(CT) == 1 || lt)
-      chunk_stats_xor_body<T, CT, true>(codes, x, len, s_tab, sc, n, C, cbits, cu, ctb, ebb);
+      chunk_stats_xor_body<T, CT, true>(codes, x, len, s_tab, sc, n, C, cbits, cu, ctb, ebb, tlo);
     else
-      chunk_stats_xor_body<T, CT, false>(codes, x, len, s_tab, sc, n, C, cbits, cu, ctb, ebb);
+      chunk_stats_xor_body<T, CT, false>(codes, x, len, s_tab, sc, n, C, cbits, cu, ctb, ebb, tlo);
   } else if (sizeof(CT) == 1 || lt) {
-    chunk_stats_body<T, CT, true>(codes, x, len, s_tab, sc, n, C, cbits, cu, ctb, ebb);
+    chunk_stats_body<T, CT, true>(codes, x, len, s_tab, sc, n, C, cbits, cu, ctb, ebb, tlo);
   } else {
-    chunk_stats_body<T, CT, false>(codes, x, len, s_tab, sc, n, C, cbits, cu, ctb, ebb);
+    chunk_stats_body<T, CT, false>(codes, x, len, s_tab, sc, n, C, cbits, cu, ctb, ebb, tlo);
   }
 }
 template <typename T, typename CT>
@@ -1561,7 +1570,7 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
                                             const uint32_t* s_tab, uint32_t* words, CT* sc, uint64_t n,
                                             uint32_t C, const uint32_t* cbits, const uint64_t* boff,
                                             const uint64_t* uoff, const uint64_t* toff, uint8_t* out,
-                                            const DevPlan* P) {
+                                            const DevPlan* P, uint32_t tlo) {
   using U = typename FTr<T>::U;
   constexpr int MANT = FTr<T>::MANT;
   constexpr int HB = 1 + FTr<T>::EXPB;
@@ -1591,7 +1600,7 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
 #pragma unroll
       for (int k = 0; k < 4; k++) {
         const bool real = k0 + j + k < cnt;
-        mybits += real ? (code_entry<LT>(sym[k], s_tab, len, cw) >> 27) : 0u;
+        mybits += real ? (code_entry<LT>(sym[k], s_tab, len, cw, tlo) >> 27) : 0u;
         anyz |= real && sym[k] == 0;
       }
       if (anyz) {
@@ -1659,7 +1668,7 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
 #pragma unroll
       for (int k = 0; k < 4; k++) {
         if (k0 + j + k >= cnt) break;
-        const uint32_t e = code_entry<LT>(sym[k], s_tab, len, cw);
+        const uint32_t e = code_entry<LT>(sym[k], s_tab, len, cw, tlo);
         wb.put(e & 0x07FFFFFFu, (int)(e >> 27));
         anyz |= sym[k] == 0;
       }
@@ -1735,21 +1744,21 @@ __device__ __forceinline__ void encode_kernel_dev(const CT* __restrict__ codes, 
   if (P->status || P->raw) return;
   const uint32_t nsym = 1u << P->m;
   const bool lt = nsym <= kTab;
-  if (lt)
-    for (uint32_t i = threadIdx.x; i < nsym; i += kEncNT) s_tab[i] = cw[i];  // len << 27 | code
+  const uint32_t tlo = tab_window(P->m);
+  for (uint32_t i = threadIdx.x; i < min(nsym, kTab); i += kEncNT) s_tab[i] = cw[tlo + i];  // len << 27 | code
   __syncthreads();
   const int wv = threadIdx.x >> 6;
   uint32_t* words = (uint32_t*)s_dyn + (size_t)wv * enc_words_per_wave(C);
   CT* sc = (CT*)((uint32_t*)s_dyn + 4 * (size_t)enc_words_per_wave(C)) + (size_t)wv * C;
   if (P->xorc) {
     if (sizeof(CT) == 1 || lt)
-      encode_body<T, CT, true, true>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P);
+      encode_body<T, CT, true, true>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P, tlo);
     else
-      encode_body<T, CT, false, true>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P);
+      encode_body<T, CT, false, true>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P, tlo);
   } else if (sizeof(CT) == 1 || lt) {
-    encode_body<T, CT, true, false>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P);
+    encode_body<T, CT, true, false>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P, tlo);
   } else {
-    encode_body<T, CT, false, false>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P);
+    encode_body<T, CT, false, false>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P, tlo);
   }
 }
 template <typename T, typename CT>
