@@ -318,7 +318,7 @@ int build_plan(sz_batch* b, int cand, BPlan& P) {
   P.tstart[n] = t;
   P.tiles = t;
   P.lds_cs = 4u * b->cmax * (unsigned)b->cw;
-  P.lds_enc = enc_lds_bytes(b->cmax, (uint32_t)b->cw);
+  P.lds_enc = enc_lds_bytes(b->cmax, (uint32_t)b->cw, b->dtype == SZ_F32 ? 4u : 8u, true);
   if (b->dtype == SZ_F32)
     P.lds_sweep = c.nt == 512 ? (b->cw == 1 ? b_sweep_lds<float, uint8_t, 512>() : b_sweep_lds<float, uint16_t, 512>())
                               : (b->cw == 1 ? b_sweep_lds<float, uint8_t, 256>() : b_sweep_lds<float, uint16_t, 256>());

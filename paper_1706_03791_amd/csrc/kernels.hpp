@@ -1558,10 +1558,22 @@ __global__ void layout_kernel(LayoutArgs A) {
 // atomic OR, the rest with plain stores).  The (length, codeword) table sits
 // in LDS as (len << 27) | code when 2^m <= 4096.
 constexpr int kEncNT = 256;
-__host__ __device__ constexpr uint32_t enc_words_per_wave(uint32_t C) { return C * kLmax / 32 + 2; }
+// Unpredictable values per chunk above which their heads and tails are
+// staged in LDS (below it, per-lane bit writers to memory cost less).
+constexpr uint32_t kEncStageMin = 64;
+// LDS words per wave for the chunk's largest stream: its codes (at most kLmax
+// bits each), heads (9 or 12 bits each) or tails (kept mantissa bits, or
+// XOR records of at most 2 + 32 or 3 + 64 bits)
+__host__ __device__ constexpr uint32_t enc_words_per_wave(uint32_t C, uint32_t value_bytes, bool xorc) {
+  const uint32_t huff = C * kLmax / 32 + 2;
+  const uint32_t tail = C * (xorc ? (value_bytes == 8 ? 67u : 34u) : (value_bytes == 8 ? 52u : 23u)) / 32 + 2;
+  const uint32_t head = C * (value_bytes == 8 ? 12u : 9u) / 32 + 2;
+  return huff > tail ? (huff > head ? huff : head) : (tail > head ? tail : head);
+}
 // dynamic LDS of the encoder: per wave, the bit words then C codes of CT
-__host__ __device__ constexpr uint32_t enc_lds_bytes(uint32_t C, uint32_t code_bytes) {
-  return 4u * (enc_words_per_wave(C) * 4u + C * code_bytes);
+__host__ __device__ constexpr uint32_t enc_lds_bytes(uint32_t C, uint32_t code_bytes, uint32_t value_bytes,
+                                                     bool xorc) {
+  return 4u * (enc_words_per_wave(C, value_bytes, xorc) * 4u + C * code_bytes);
 }
 
 template <typename T, typename CT, bool LT, bool XORC>
@@ -1654,78 +1666,125 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
     // the bits of the chunk's first half (lanes 0..31 hold its first C/2
     // codes): where a second decoder of the chunk starts
     if (lane == 32) ((uint16_t*)(ch + n_chunks))[c] = (uint16_t)(bpos - (b0 & 31));
-    const uint64_t zpos = uoff[c] + wave_exscan(myz);
-    const uint64_t tpos = toff[c] + wave_exscan(mytb);
+    const uint64_t zex = wave_exscan(myz), tex = wave_exscan(mytb);
+    const uint32_t zch = wave_sum(myz), tch = wave_sum(mytb);  // the chunk's values and tail bits
     __builtin_amdgcn_wave_barrier();
-    // codes into the wave's LDS words; heads and tails of unpredictable
-    // values straight into their streams
-    BitWriter wb(words, bpos), wh(hd, zpos * HB), wt(tl, tpos);
-    U prev = prev0;
-    for (uint32_t j = 0; j < per; j += 4) {
-      uint32_t sym[4];
-      lds_code4<CT>(sc, k0 + j, sym);
-      bool anyz = false;
-#pragma unroll
-      for (int k = 0; k < 4; k++) {
-        if (k0 + j + k >= cnt) break;
-        const uint32_t e = code_entry<LT>(sym[k], s_tab, len, cw, tlo);
-        wb.put(e & 0x07FFFFFFu, (int)(e >> 27));
-        anyz |= sym[k] == 0;
+    // Three streams leave through the wave's LDS words in turn (codes, then
+    // heads, then tails): each is written bit by bit in LDS and then copied
+    // out in whole words, the words shared with the neighbouring chunks with
+    // an atomic OR; bit writers straight to memory would make every wave
+    // store touch a line per lane.
+    auto copy_out = [&](uint32_t* dst, uint64_t bit0, uint64_t nbits) {
+      const uint32_t nwo = (uint32_t)((((bit0 & 31) + nbits) + 31) / 32);
+      const uint64_t gw0 = bit0 >> 5, bend = bit0 + nbits;
+      __builtin_amdgcn_wave_barrier();
+      for (uint32_t w = lane; w < nwo; w += 64) {
+        const uint64_t gw = gw0 + w;
+        const bool full = (gw * 32 >= bit0) && (gw * 32 + 32 <= bend);
+        if (full)
+          dst[gw] = words[w];
+        else if (words[w])
+          atomicOr(&dst[gw], words[w]);
       }
-      if (anyz) {
-        T xv[4];
-        load4<T>(x, i0 + j, n, xv);
+      __builtin_amdgcn_wave_barrier();
+    };
+    auto clear_words = [&](uint64_t bit0, uint64_t nbits) {
+      const uint32_t nwo = (uint32_t)((((bit0 & 31) + nbits) + 31) / 32);
+      for (uint32_t w = lane; w < nwo; w += 64) words[w] = 0;
+      __builtin_amdgcn_wave_barrier();
+    };
+    {
+      BitWriter wb(words, bpos);
+      for (uint32_t j = 0; j < per; j += 4) {
+        uint32_t sym[4];
+        lds_code4<CT>(sc, k0 + j, sym);
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-          if (k0 + j + k >= cnt || sym[k] != 0) continue;
-          const U ub = to_bits<T>(truncate_unpred<T>(xv[k], ebb));
-          const int r = kept_bits<T>(xv[k], ebb);
-          if constexpr (XORC) {
-            // leading-byte count, then the significant bits after those bytes
-            using XR = XorRec<T>;
-            const int q = XR::HB + r;
-            const int lzb = XR::lead_bytes(ub ^ prev);
-            wt.put((uint32_t)lzb, XR::LZB);
-            const int nb = q - 8 * lzb;
-            if (nb > 0) {
-              const U v = (ub >> (XR::W - q)) & ((((U)1) << (nb - 1) << 1) - 1);
-              if (nb > 32) {
-                wt.put((uint32_t)((uint64_t)v >> 32), nb - 32);
-                wt.put((uint32_t)v, 32);
-              } else {
-                wt.put((uint32_t)v, nb);
-              }
-            }
-            prev = ub;
-          } else {
-            wh.put((uint32_t)(ub >> MANT), HB);
-            const U tail = (ub & ((((U)1) << MANT) - 1)) >> (MANT - r);  // the top r mantissa bits
-            if (r > 32) {
-              wt.put((uint32_t)((uint64_t)tail >> 32), r - 32);
-              wt.put((uint32_t)tail, 32);
-            } else {
-              wt.put((uint32_t)tail, r);
-            }
-          }
+          if (k0 + j + k >= cnt) break;
+          const uint32_t e = code_entry<LT>(sym[k], s_tab, len, cw, tlo);
+          wb.put(e & 0x07FFFFFFu, (int)(e >> 27));
         }
       }
-    }
-    wb.finish();
-    wh.finish();
-    wt.finish();
-    __builtin_amdgcn_wave_barrier();
-    const uint64_t gw0 = b0 >> 5;
-    const uint64_t bend = b0 + nb;
-    for (uint32_t w = lane; w < nw; w += 64) {
-      const uint64_t gw = gw0 + w;
-      const bool full = (gw * 32 >= b0) && (gw * 32 + 32 <= bend);
-      if (full)
-        bs[gw] = words[w];
-      else if (words[w])
-        atomicOr(&bs[gw], words[w]);
+      wb.finish();
+      copy_out(bs, b0, nb);
     }
     if (lane == 0) ch[c] = nb;
-    __builtin_amdgcn_wave_barrier();
+    if (zch) {
+      // The lane's unpredictable values, in order, as (reduced pattern, kept
+      // mantissa bits); `emit` takes each one.
+      auto each_unpred = [&](auto&& emit) {
+        for (uint32_t j = 0; j < per; j += 4) {
+          uint32_t sym[4];
+          lds_code4<CT>(sc, k0 + j, sym);
+          bool anyz = false;
+#pragma unroll
+          for (int k = 0; k < 4; k++) anyz |= k0 + j + k < cnt && sym[k] == 0;
+          if (!anyz) continue;
+          T xv[4];
+          load4<T>(x, i0 + j, n, xv);
+#pragma unroll
+          for (int k = 0; k < 4; k++)
+            if (k0 + j + k < cnt && sym[k] == 0)
+              emit(to_bits<T>(truncate_unpred<T>(xv[k], ebb)), kept_bits<T>(xv[k], ebb));
+        }
+      };
+      // tails: the kept mantissa bits, or the XOR records
+      U prev = prev0;
+      auto put_tail = [&](BitWriter& wt, U ub, int r) {
+        if constexpr (XORC) {
+          // leading-byte count, then the significant bits after those bytes
+          using XR = XorRec<T>;
+          const int q = XR::HB + r;
+          const int lzb = XR::lead_bytes(ub ^ prev);
+          wt.put((uint32_t)lzb, XR::LZB);
+          const int nbq = q - 8 * lzb;
+          if (nbq > 0) {
+            const U v = (ub >> (XR::W - q)) & ((((U)1) << (nbq - 1) << 1) - 1);
+            if (nbq > 32) {
+              wt.put((uint32_t)((uint64_t)v >> 32), nbq - 32);
+              wt.put((uint32_t)v, 32);
+            } else {
+              wt.put((uint32_t)v, nbq);
+            }
+          }
+          prev = ub;
+        } else {
+          const U tail = (ub & ((((U)1) << MANT) - 1)) >> (MANT - r);  // the top r mantissa bits
+          if (r > 32) {
+            wt.put((uint32_t)((uint64_t)tail >> 32), r - 32);
+            wt.put((uint32_t)tail, 32);
+          } else {
+            wt.put((uint32_t)tail, r);
+          }
+        }
+      };
+      if (zch <= kEncStageMin) {
+        // few values: their heads and tails go straight to memory
+        BitWriter wh(hd, (uoff[c] + zex) * HB), wt(tl, toff[c] + tex);
+        each_unpred([&](U ub, int r) {
+          if constexpr (!XORC) wh.put((uint32_t)(ub >> MANT), HB);
+          put_tail(wt, ub, r);
+        });
+        wh.finish();
+        wt.finish();
+      } else {
+        if constexpr (!XORC) {
+          // heads: sign and exponent of each value
+          const uint64_t hb0 = uoff[c] * HB;
+          clear_words(hb0, (uint64_t)zch * HB);
+          BitWriter wh(words, (hb0 & 31) + zex * HB);
+          each_unpred([&](U ub, int) { wh.put((uint32_t)(ub >> MANT), HB); });
+          wh.finish();
+          copy_out(hd, hb0, (uint64_t)zch * HB);
+        }
+        const uint64_t tb0 = toff[c];
+        clear_words(tb0, tch);
+        BitWriter wt(words, (tb0 & 31) + tex);
+        each_unpred([&](U ub, int r) { put_tail(wt, ub, r); });
+        wt.finish();
+        copy_out(tl, tb0, tch);
+      }
+    }
   }
 }
 
@@ -1748,8 +1807,9 @@ __device__ __forceinline__ void encode_kernel_dev(const CT* __restrict__ codes, 
   for (uint32_t i = threadIdx.x; i < min(nsym, kTab); i += kEncNT) s_tab[i] = cw[tlo + i];  // len << 27 | code
   __syncthreads();
   const int wv = threadIdx.x >> 6;
-  uint32_t* words = (uint32_t*)s_dyn + (size_t)wv * enc_words_per_wave(C);
-  CT* sc = (CT*)((uint32_t*)s_dyn + 4 * (size_t)enc_words_per_wave(C)) + (size_t)wv * C;
+  const uint32_t wpw = enc_words_per_wave(C, sizeof(T), P->xorc != 0);
+  uint32_t* words = (uint32_t*)s_dyn + (size_t)wv * wpw;
+  CT* sc = (CT*)((uint32_t*)s_dyn + 4 * (size_t)wpw) + (size_t)wv * C;
   if (P->xorc) {
     if (sizeof(CT) == 1 || lt)
       encode_body<T, CT, true, true>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P, tlo);

@@ -613,7 +613,7 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
     hipLaunchKernelGGL(container_prep_kernel<T>, dim3((unsigned)std::max(gz, gr)), dim3(256), 0, st, (const T*)d_in,
                        (uint8_t*)d_out, (uint64_t)L.n, (const DevPlan*)P);
   }
-  const unsigned enc_lds = enc_lds_bytes(L.chunk, (uint32_t)L.cw);
+  const unsigned enc_lds = enc_lds_bytes(L.chunk, (uint32_t)L.cw, (uint32_t)L.ts, L.xorc != 0);
   if (L.cw == 1) {
     (void)hipFuncSetAttribute((const void*)encode_kernel<T, uint8_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)enc_lds);
