@@ -2441,75 +2441,6 @@ __global__ void __launch_bounds__(DecShape<CT>::NT) decode_kernel(const uint8_t*
 }
 
 // K9a: kept-bit count of every unpredictable value, summed per group of 1024.
-template <typename T>
-__global__ void __launch_bounds__(1024) unpred_sums_kernel(const uint8_t* comp, uint64_t off_hd, uint64_t hd_words,
-                                                           uint64_t U, uint64_t ebT_bits, uint32_t* rsum,
-                                                           const DevPlan* P) {
-  constexpr int HB = 1 + FTr<T>::EXPB, MANT = FTr<T>::MANT, EMAX = FTr<T>::EMAX;
-  __shared__ uint32_t red[16];
-  if (P->status) return;
-  const uint64_t j = (uint64_t)blockIdx.x * 1024 + threadIdx.x;
-  uint32_t r = 0;
-  if (j < U) {
-    const uint64_t head = read_bits((const uint32_t*)(comp + off_hd), hd_words, j * HB, HB);
-    const int e = (int)(head & EMAX);
-    const int e_eb = (int)((ebT_bits >> MANT) & (uint64_t)EMAX);
-    if (e_eb == 0 || e == EMAX) r = MANT;
-    else if (e == 0 || e < e_eb) r = 0;
-    else r = (uint32_t)min(e - e_eb, MANT);
-  }
-  r = block_sum<1024, uint32_t>(r, red);
-  if (threadIdx.x == 0) rsum[blockIdx.x] = r;
-}
-
-// K9b: rebuild each unpredictable value from its head and kept tail bits.
-template <typename T>
-__global__ void __launch_bounds__(1024) unpred_values_kernel(const uint8_t* comp, uint64_t off_hd, uint64_t hd_words,
-                                                             uint64_t off_tl, uint64_t tl_words, uint64_t U,
-                                                             uint64_t ebT_bits, const uint64_t* roff,
-                                                             uint64_t tail_bits, T* vals, DevPlan* P) {
-  using UT = typename FTr<T>::U;
-  constexpr int HB = 1 + FTr<T>::EXPB, MANT = FTr<T>::MANT, EMAX = FTr<T>::EMAX;
-  __shared__ uint64_t red[16];
-  if (P->status) return;
-  const uint64_t j = (uint64_t)blockIdx.x * 1024 + threadIdx.x;
-  uint64_t head = 0;
-  int r = 0;
-  if (j < U) {
-    head = read_bits((const uint32_t*)(comp + off_hd), hd_words, j * HB, HB);
-    const int e = (int)(head & EMAX);
-    const int e_eb = (int)((ebT_bits >> MANT) & (uint64_t)EMAX);
-    if (e_eb == 0 || e == EMAX) r = MANT;
-    else if (e == 0 || e < e_eb) r = 0;
-    else r = min(e - e_eb, MANT);
-  }
-  uint64_t tot;
-  const uint64_t pos = roff[blockIdx.x] + block_exscan<1024, uint64_t>((uint64_t)r, red, &tot);
-  if (j < U) {
-    const uint64_t tail = r ? read_bits((const uint32_t*)(comp + off_tl), tl_words, pos, r) : 0;
-    const UT u = ((UT)head << MANT) | ((UT)tail << (MANT - r));
-    vals[j] = bits_to<T>(u);
-    if (j == U - 1 && pos + r != tail_bits) set_status(P, SZ_ECORRUPT);
-  }
-}
-
-// ------------------------- XOR-coded unpredictable values (flag bit 1)
-// Zero codes of each chunk of the decoded code array (one wave per chunk).
-template <typename CT>
-__global__ void __launch_bounds__(256) chunk_zeros_kernel(const CT* __restrict__ codes, uint64_t n, uint32_t C,
-                                                          uint32_t* cz, const DevPlan* P) {
-  if (P->status) return;
-  const uint64_t n_chunks = (n + C - 1) / C;
-  const int lane = threadIdx.x & 63;
-  for (uint64_t c = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < n_chunks; c += (uint64_t)gridDim.x * 4) {
-    const uint64_t i0 = c * C, i1 = min(n, i0 + C);
-    uint32_t z = 0;
-    for (uint64_t i = i0 + lane; i < i1; i += 64) z += codes[i] == 0;
-    z = wave_sum(z);
-    if (lane == 0) cz[c] = z;
-  }
-}
-
 // MSB-first bits of a stream read in order through a 64-bit buffer.
 struct SeqBits {
   const uint32_t* w;
@@ -2543,6 +2474,111 @@ struct SeqBits {
     return (hi << 32) | get(32);
   }
 };
+
+template <typename T>
+__device__ __forceinline__ int unpred_kept_bits(uint32_t head, uint64_t ebT_bits) {
+  constexpr int MANT = FTr<T>::MANT, EMAX = FTr<T>::EMAX;
+  const int e = (int)(head & EMAX);
+  const int e_eb = (int)((ebT_bits >> MANT) & (uint64_t)EMAX);
+  if (e_eb == 0 || e == EMAX) return MANT;
+  if (e == 0 || e < e_eb) return 0;
+  return min(e - e_eb, MANT);
+}
+
+// Unpredictable values per thread of the two kernels below (at most kUpt,
+// `upt` of a launch): each thread reads its values' heads (and then tails)
+// in order through a bit buffer, so with many values a block of 256 threads
+// covers 4096 of them with one scan; few values run one per thread.
+constexpr int kUpt = 16;
+inline uint32_t unpred_per_thread(uint64_t U) { return U >= (1u << 20) ? (uint32_t)kUpt : 1u; }
+
+template <typename T>
+__global__ void __launch_bounds__(256) unpred_sums_kernel(const uint8_t* comp, uint64_t off_hd, uint64_t hd_words,
+                                                          uint64_t U, uint64_t ebT_bits, uint32_t upt,
+                                                          uint32_t* rsum, const DevPlan* P) {
+  constexpr int HB = 1 + FTr<T>::EXPB;
+  __shared__ uint32_t red[4];
+  if (P->status) return;
+  const uint64_t j0 = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * upt;
+  uint32_t r = 0;
+  if (j0 < U) {
+    SeqBits hb((const uint32_t*)(comp + off_hd), hd_words, j0 * HB);
+    const int cnt = (int)min((uint64_t)upt, U - j0);
+    for (int k = 0; k < cnt; k++) r += (uint32_t)unpred_kept_bits<T>(hb.get(HB), ebT_bits);
+  }
+  r = block_sum<256, uint32_t>(r, red);
+  if (threadIdx.x == 0) rsum[blockIdx.x] = r;
+}
+
+// K9b: rebuild each unpredictable value from its head and kept tail bits.
+template <typename T>
+__global__ void __launch_bounds__(256) unpred_values_kernel(const uint8_t* comp, uint64_t off_hd, uint64_t hd_words,
+                                                            uint64_t off_tl, uint64_t tl_words, uint64_t U,
+                                                            uint64_t ebT_bits, uint32_t upt, const uint64_t* roff,
+                                                            uint64_t tail_bits, T* vals, DevPlan* P) {
+  using UT = typename FTr<T>::U;
+  constexpr int HB = 1 + FTr<T>::EXPB, MANT = FTr<T>::MANT;
+  __shared__ uint64_t red[4];
+  if (P->status) return;
+  const uint64_t j0 = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * upt;
+  const int cnt = j0 < U ? (int)min((uint64_t)upt, U - j0) : 0;
+  uint32_t head[kUpt];
+  uint64_t r_tot = 0;
+  {
+    SeqBits hb((const uint32_t*)(comp + off_hd), hd_words, cnt ? j0 * HB : 0);
+#pragma unroll
+    for (int k = 0; k < kUpt; k++) {
+      head[k] = k < cnt ? hb.get(HB) : 0u;
+      r_tot += k < cnt ? (uint64_t)unpred_kept_bits<T>(head[k], ebT_bits) : 0ull;
+    }
+  }
+  uint64_t tot;
+  const uint64_t pos = roff[blockIdx.x] + block_exscan<256, uint64_t>(r_tot, red, &tot);
+  if (!cnt) return;
+  SeqBits tb((const uint32_t*)(comp + off_tl), tl_words, pos);
+  UT u[kUpt];
+#pragma unroll
+  for (int k = 0; k < kUpt; k++) {
+    const int r = k < cnt ? unpred_kept_bits<T>(head[k], ebT_bits) : 0;
+    const uint64_t tail = tb.get64(r);
+    u[k] = ((UT)head[k] << MANT) | (r ? (UT)tail << (MANT - r) : (UT)0);
+  }
+  if (cnt == kUpt) {
+    // 16 values from a multiple of 16: aligned 16-byte stores
+    constexpr int E = 16 / (int)sizeof(T);
+#pragma unroll
+    for (int q = 0; q < kUpt / E; q++) {
+      uint4 v;
+      if constexpr (sizeof(T) == 4)
+        v = make_uint4((uint32_t)u[E * q], (uint32_t)u[E * q + 1], (uint32_t)u[E * q + 2], (uint32_t)u[E * q + 3]);
+      else
+        v = make_uint4((uint32_t)u[E * q], (uint32_t)((uint64_t)u[E * q] >> 32), (uint32_t)u[E * q + 1],
+                       (uint32_t)((uint64_t)u[E * q + 1] >> 32));
+      *(uint4*)(vals + j0 + E * q) = v;
+    }
+  } else {
+    for (int k = 0; k < cnt; k++) vals[j0 + k] = bits_to<T>(u[k]);
+  }
+  if (j0 + cnt == U && pos + r_tot != tail_bits) set_status(P, SZ_ECORRUPT);
+}
+
+// ------------------------- XOR-coded unpredictable values (flag bit 1)
+// Zero codes of each chunk of the decoded code array (one wave per chunk).
+template <typename CT>
+__global__ void __launch_bounds__(256) chunk_zeros_kernel(const CT* __restrict__ codes, uint64_t n, uint32_t C,
+                                                          uint32_t* cz, const DevPlan* P) {
+  if (P->status) return;
+  const uint64_t n_chunks = (n + C - 1) / C;
+  const int lane = threadIdx.x & 63;
+  for (uint64_t c = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); c < n_chunks; c += (uint64_t)gridDim.x * 4) {
+    const uint64_t i0 = c * C, i1 = min(n, i0 + C);
+    uint32_t z = 0;
+    for (uint64_t i = i0 + lane; i < i1; i += 64) z += codes[i] == 0;
+    z = wave_sum(z);
+    if (lane == 0) cz[c] = z;
+  }
+}
+
 
 // One thread per chunk parses the chunk's records in order: the leading
 // bytes come from the previous value of the chunk, sign and exponent are

@@ -714,7 +714,7 @@ size_t carve_dec(const Layout& L, uint64_t U, uint8_t* base, DecWs* W, size_t re
   Carve c{base};
   DecWs w;
   w.xchg = c.take<uint8_t>(std::max<uint64_t>(xchg_need(L), reserve));
-  const uint64_t ngr = ceil_div(U, 1024) + 1;
+  const uint64_t ngr = ceil_div(U, 256) + 1;  // unpredictable-value blocks (256 threads, one value each at most)
   w.codes = c.take<uint8_t>((L.n + 64) * L.cw);
   w.boff = c.take<uint64_t>(L.n_chunks * 8);
   w.tsum_b = c.take<uint64_t>((ceil_div(L.n_chunks, 4096) + 1) * 8);
@@ -817,13 +817,14 @@ int enqueue_decompress_t(sz_ctx* ctx, const Layout& L, const Hdr& h, const void*
                        (const uint64_t*)W.xuoff, L.n_chunks, h.ebT_bits, (T*)W.uvals, P);
   } else if (U) {
     constexpr int HB = 1 + FTr<T>::EXPB;
-    const uint64_t ngr = ceil_div(U, 1024);
+    const uint32_t upt = unpred_per_thread(U);
+    const uint64_t ngr = ceil_div(U, 256ull * upt);
     const uint64_t hdw = (U * HB + 31) / 32, tlw = (h.tail_bits + 31) / 32;
-    hipLaunchKernelGGL(unpred_sums_kernel<T>, dim3((unsigned)ngr), dim3(1024), 0, st, comp, h.off_hd, hdw, U,
-                       h.ebT_bits, W.rsum, (const DevPlan*)P);
+    hipLaunchKernelGGL(unpred_sums_kernel<T>, dim3((unsigned)ngr), dim3(256), 0, st, comp, h.off_hd, hdw, U,
+                       h.ebT_bits, upt, W.rsum, (const DevPlan*)P);
     scan_u32(W.rsum, ngr, W.roff, W.tsum_r, W.tot + 2, st);
-    hipLaunchKernelGGL(unpred_values_kernel<T>, dim3((unsigned)ngr), dim3(1024), 0, st, comp, h.off_hd, hdw,
-                       h.off_tl, tlw, U, h.ebT_bits, (const uint64_t*)W.roff, h.tail_bits, (T*)W.uvals, P);
+    hipLaunchKernelGGL(unpred_values_kernel<T>, dim3((unsigned)ngr), dim3(256), 0, st, comp, h.off_hd, hdw,
+                       h.off_tl, tlw, U, h.ebT_bits, upt, (const uint64_t*)W.roff, h.tail_bits, (T*)W.uvals, P);
   }
   stage_end(ctx, ST_UNPRED, st);
   stage_begin(ctx, ST_SWEEP_D, st);
