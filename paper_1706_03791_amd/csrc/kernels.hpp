@@ -2125,13 +2125,12 @@ __global__ void __launch_bounds__(1024) dectab_kernel(const uint8_t* comp, uint6
 constexpr uint32_t kSymLds = 4096;
 constexpr int kDecRing = 16;    // words of bitstream per lane in LDS (1-byte codes)
 constexpr int kDecPeriod = 8;   // iterations between the reloads of all lanes
-// Decoder lanes: 1-byte codes run two lanes per chunk (one per half, the
-// second from the chunk's stored half offset) in 1024-thread workgroups, so
-// one copy of the decode tables serves four waves per SIMD; 2-byte codes
-// one lane per chunk in 256-thread workgroups.
+// Decoder lanes: two lanes per chunk (one per half, the second from the
+// chunk's stored half offset) in 1024-thread workgroups, so one copy of the
+// decode tables serves four waves per SIMD.
 template <typename CT> struct DecShape {
-  static constexpr int NT = sizeof(CT) == 1 ? 1024 : 256;  // threads per workgroup
-  static constexpr int LPC = sizeof(CT) == 1 ? 2 : 1;      // lanes per chunk
+  static constexpr int NT = 1024;  // threads per workgroup
+  static constexpr int LPC = 2;    // lanes per chunk
 };
 
 __device__ __forceinline__ uint4 load_words4(const uint32_t* words, uint64_t nwords, uint64_t w) {
