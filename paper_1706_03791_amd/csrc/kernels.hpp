@@ -851,12 +851,13 @@ __device__ __forceinline__ uint32_t wave_exscan(uint32_t v) { return wave_inscan
 
 // ------------------------------------------------ K3: code histogram
 // Histogram of the codes of a sweep (the wave-tiled sweep writes codes
-// only).  The centre and zero codes, the most frequent ones, are counted in
-// registers.  With 1-byte codes (m <= 8) every bin lives in LDS, in 32
-// copies (one per lane pair of a wave, rows padded to 257 words so the
-// copies of one bin sit in different banks): the codes next to the centre
-// are frequent too, and lanes that add to one bin in one copy would
-// serialise.  With 2-byte codes a window of up to 16384 bins around the
+// only).  With 1-byte codes (m <= 8) every bin lives in LDS, in 32 copies
+// (one per lane pair of a wave, rows padded to 257 words so the copies of
+// one bin sit in different banks), and every code is one LDS add without a
+// branch: the codes at and next to the centre are the frequent ones, and
+// lanes that add to one bin in one copy would serialise.  With 2-byte codes
+// the centre and zero codes, the most frequent ones, are counted in
+// registers.  With 2-byte codes a window of up to 16384 bins around the
 // centre lives in LDS and codes outside it go straight to global atomics.
 // A block's counts reach the histogram by atomics, or, with 1-byte codes and
 // a partials array `hpart` (kHistBlocks rows of 256 bins), by plain stores
@@ -883,7 +884,9 @@ __device__ __forceinline__ void hist_kernel_dev(const CT* __restrict__ codes, ui
   uint32_t* hc = kCopies ? h + (threadIdx.x & (kHistCopies - 1)) * kHistRow : h;  // this lane's copy
   uint32_t c_center = 0, c_zero = 0;
   auto count = [&](uint32_t code) {
-    if (code == half) {
+    if constexpr (kCopies) {
+      atomicAdd(&hc[code], 1u);  // every 1-byte code has a bin in the row
+    } else if (code == half) {
       c_center++;
     } else if (code == 0) {
       c_zero++;
@@ -2249,28 +2252,48 @@ __global__ void __launch_bounds__(DecShape<CT>::NT) decode_kernel(const uint8_t*
     // also wait for the code stores before them) then come once per period
     // for the whole wave rather than whenever one lane runs out.  A lane
     // that still runs out loads its next word directly (rare).
-    uint64_t acc8 = 0;
-    int nab = 0;         // codes pending in acc8 (< 8)
-    uint64_t gpos = i0;  // position of the first pending code, a multiple of 8
-    uint64_t i = i0;
+    // Every counter in the loop is a 32-bit offset from the lane's first
+    // code, first word or first bit (a lane spans at most one chunk).
+    const uint32_t ni = (uint32_t)(i1 - i0);  // codes of this lane
+    CT* const cbase = codes + i0;
     const uint64_t w0 = pos >> 5;
+    const uint32_t* const wbase = words + w0;
+    // words readable from w0 on (a lane reads fewer than 2^30)
+    const uint32_t rnw = w0 < nwords ? (uint32_t)min(nwords - w0, (uint64_t)1 << 30) : 0u;
+    auto ld4 = [&](uint32_t r) -> uint4 {
+      if (r + 4 <= rnw) return *(const uint4*)(wbase + r);
+      uint4 v;
+      v.x = (r + 0 < rnw) ? wbase[r + 0] : 0u;
+      v.y = (r + 1 < rnw) ? wbase[r + 1] : 0u;
+      v.z = (r + 2 < rnw) ? wbase[r + 2] : 0u;
+      v.w = (r + 3 < rnw) ? wbase[r + 3] : 0u;
+      return v;
+    };
+    // the end of the current row segment, and the end of what one table
+    // read may take (the segment's end or the lane's, whichever is first)
+    uint32_t send = (uint32_t)min(rem, (int64_t)ni + 1);
+    uint32_t lim = min(send, ni);
+    uint64_t acc8 = 0;
+    int nab = 0;      // codes pending in acc8 (< 8)
+    uint32_t rg = 0;  // offset of the first pending code, a multiple of 8
+    uint32_t ri = 0;  // codes decoded
+    uint32_t rb = 0;  // bits consumed
 #pragma unroll
     for (int q = 0; q < kDecRing / 4; q++) {
-      const uint4 g = load_words4(words, nwords, w0 + 4 * q);
-      s_ring[(w0 + 4 * q + 0) & (kDecRing - 1)][t] = g.x;
-      s_ring[(w0 + 4 * q + 1) & (kDecRing - 1)][t] = g.y;
-      s_ring[(w0 + 4 * q + 2) & (kDecRing - 1)][t] = g.z;
-      s_ring[(w0 + 4 * q + 3) & (kDecRing - 1)][t] = g.w;
+      const uint4 g = ld4(4 * q);
+      s_ring[4 * q + 0][t] = g.x;
+      s_ring[4 * q + 1][t] = g.y;
+      s_ring[4 * q + 2][t] = g.z;
+      s_ring[4 * q + 3][t] = g.w;
     }
-    uint64_t fland = w0 + kDecRing;  // words landed in the ring: [fland - kDecRing, fland)
-    uint64_t fiss = fland;           // words requested (landed or in flight)
+    // word offsets: landed in the ring [fland - kDecRing, fland), requested
+    // up to fiss, next to take into buf rword; word r sits in slot r % kDecRing
+    uint32_t fland = kDecRing, fiss = kDecRing, rword = 1;
     uint4 p0 = make_uint4(0, 0, 0, 0), p1 = p0;  // in-flight words [fland, fland + 8)
-    // the ring slot of word w is w % kDecRing
-    buf = ((uint64_t)s_ring[w0 & (kDecRing - 1)][t] << 32) << (pos & 31);
+    buf = ((uint64_t)s_ring[0][t] << 32) << (pos & 31);
     nb = 32 - (int)(pos & 31);
-    uint64_t rword = w0 + 1;  // next word to take into buf
     uint32_t it = 0;
-    while (i < i1) {
+    while (ri < ni) {
       if ((it++ & (kDecPeriod - 1)) == 0) {
         if (fiss > fland) {
           const uint32_t wv[8] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
@@ -2278,15 +2301,15 @@ __global__ void __launch_bounds__(DecShape<CT>::NT) decode_kernel(const uint8_t*
           for (int q = 0; q < 8; q++) s_ring[(fland + q) & (kDecRing - 1)][t] = wv[q];
           fland += 8;
         }
-        if (fland - rword <= (uint64_t)(kDecRing - 8)) {
-          p0 = load_words4(words, nwords, fland);
-          p1 = load_words4(words, nwords, fland + 4);
+        if (fland - rword <= (uint32_t)(kDecRing - 8)) {
+          p0 = ld4(fland);
+          p1 = ld4(fland + 4);
           fiss = fland + 8;
         }
       }
       if (nb < 32 && rword >= fland) {
         // ran out: take the next word directly into its slot
-        s_ring[rword & (kDecRing - 1)][t] = rword < nwords ? words[rword] : 0u;
+        s_ring[rword & (kDecRing - 1)][t] = rword < rnw ? wbase[rword] : 0u;
         __asm__ volatile("" ::: "memory");
       }
       {
@@ -2302,7 +2325,7 @@ __global__ void __launch_bounds__(DecShape<CT>::NT) decode_kernel(const uint8_t*
       const uint2 me = s_mlut[w12];
       const uint32_t e = lut[w12];
       const uint32_t k = me.y & 0xF;
-      const bool fast = k != 0 && (int64_t)k <= rem && i + k <= i1;
+      const bool fast = k != 0 && ri + k <= lim;
       uint32_t sym = e & 0xFFFF, l1 = e >> 16;
       uint32_t e2 = 0;
       if (e == 0 && n2) {
@@ -2336,31 +2359,32 @@ __global__ void __launch_bounds__(DecShape<CT>::NT) decode_kernel(const uint8_t*
       const uint32_t kk = fast ? k : 1u;
       buf <<= l;
       nb -= (int)l;
-      pos += l;
+      rb += l;
       zc += nz;
       acc8 |= (uint64_t)syms << (8 * nab);
       if (nab + (int)kk >= 8) {
-        *(uint64_t*)(codes + gpos) = acc8;
+        *(uint64_t*)(cbase + rg) = acc8;
         acc8 = (nab + (int)kk > 8) ? ((uint64_t)syms >> (8 * (8 - nab))) : 0ull;
         nab = nab + (int)kk - 8;
-        gpos += 8;
+        rg += 8;
       } else {
         nab += (int)kk;
       }
-      i += kk;
-      rem -= (int64_t)kk;
-      if (rem == 0) {
+      ri += kk;
+      if (ri == send) {
         if (zc) atomicAdd(&segcnt[seg], zc);
         zc = 0;
         seg++;
         if (++bx == nbx) bx = 0;
-        rem = min(X, (bx + 1) * Bx) - bx * Bx;
+        const int64_t seglen = min(X, (bx + 1) * Bx) - bx * Bx;
+        send = (uint32_t)min((int64_t)send + seglen, (int64_t)ni + 1);
+        lim = min(send, ni);
       }
     }
     if (zc && !bad) atomicAdd(&segcnt[seg], zc);
     if (!bad)
-      for (int q = 0; q < nab; q++) codes[gpos + q] = (CT)(acc8 >> (8 * q));
-    if (bad || pos != end) set_status(P, SZ_ECORRUPT);
+      for (int q = 0; q < nab; q++) cbase[rg + q] = (CT)(acc8 >> (8 * q));
+    if (bad || (uint64_t)rb != end - pos) set_status(P, SZ_ECORRUPT);
   } else {
   uint64_t acc_lo = 0, acc_hi = 0;
   int nacc = 0;
