@@ -1136,11 +1136,23 @@ __device__ __forceinline__ uint32_t code_entry(uint32_t s, const uint32_t* s_tab
     return s_tab[s];
   } else {
     // an alphabet larger than the LDS table: the table holds the window
-    // [tlo, tlo + kTabLds) around the centre code, where most codes fall
+    // [tlo, tlo + kTabLds) around the centre code, where most codes fall,
+    // then at kTabLds the entry of code 0 (every unpredictable value)
     const uint32_t r = s - tlo;
-    if (r < kTabLds) return s_tab[r];
+    const uint32_t k = r < kTabLds ? r : (s == 0 ? kTabLds : kTabLds + 1);
+    if (k <= kTabLds) return s_tab[k];
     return cw ? cw[s] : ((uint32_t)len[s] << 27);  // cw holds len << 27 | code
   }
+}
+// Code length of symbol s for the chunk totals: MODE 1 the whole table in
+// LDS, MODE 0 its window (as code_entry), MODE 2 one byte per symbol in LDS.
+template <int MODE>
+__device__ __forceinline__ uint32_t code_len(uint32_t s, const uint32_t* s_tab, const uint8_t* s_len8,
+                                             const uint8_t* len, uint32_t tlo) {
+  if constexpr (MODE == 2)
+    return s_len8[s];
+  else
+    return code_entry<MODE == 1>(s, s_tab, len, nullptr, tlo) >> 27;
 }
 // First symbol of the LDS window of a 2^m-symbol table (0 when it all fits).
 __host__ __device__ constexpr uint32_t tab_window(uint32_t m) {
@@ -1253,10 +1265,10 @@ __device__ __forceinline__ U wave_prev_present(bool has, U last) {
   return (U)((lane > 0 && hp) ? vp : 0ull);
 }
 
-template <typename T, typename CT, bool LT>
+template <typename T, typename CT, int MODE>
 __device__ __forceinline__ void chunk_stats_body(const CT* __restrict__ codes, const T* __restrict__ x,
                                                  const uint8_t* __restrict__ len, const uint32_t* s_tab,
-                                                 CT* sc, uint64_t n, uint32_t C, uint32_t* cbits, uint32_t* cu,
+                                                 const uint8_t* s_len8, CT* sc, uint64_t n, uint32_t C, uint32_t* cbits, uint32_t* cu,
                                                  uint32_t* ctb, typename FTr<T>::U ebb, uint32_t tlo) {
   const uint64_t n_chunks = (n + C - 1) / C;
   const int lane = threadIdx.x & 63;
@@ -1275,7 +1287,7 @@ __device__ __forceinline__ void chunk_stats_body(const CT* __restrict__ codes, c
 #pragma unroll
         for (int k = 0; k < 4; k++) {
           const uint32_t sym = (wv[g] >> (8 * k)) & 0xFFu;
-          b += code_entry<LT>(sym, s_tab, len, nullptr, tlo) >> 27;
+          b += code_len<MODE>(sym, s_tab, s_len8, len, tlo);
           anyz |= sym == 0;
         }
         if (anyz) {
@@ -1299,7 +1311,7 @@ __device__ __forceinline__ void chunk_stats_body(const CT* __restrict__ codes, c
 #pragma unroll
         for (int k = 0; k < 4; k++) {
           const bool real = k0 + j + k < cnt;
-          b += real ? (code_entry<LT>(sym[k], s_tab, len, nullptr, tlo) >> 27) : 0u;
+          b += real ? code_len<MODE>(sym[k], s_tab, s_len8, len, tlo) : 0u;
           anyz |= real && sym[k] == 0;
         }
         if (anyz) {
@@ -1330,10 +1342,10 @@ __device__ __forceinline__ void chunk_stats_body(const CT* __restrict__ codes, c
 // chunk's records instead of its tail bits.  Two passes over each lane's
 // codes: the first finds the lane's last unpredictable pattern (its
 // successor lanes' starting point), the second sizes the records.
-template <typename T, typename CT, bool LT>
+template <typename T, typename CT, int MODE>
 __device__ __forceinline__ void chunk_stats_xor_body(const CT* __restrict__ codes, const T* __restrict__ x,
                                                      const uint8_t* __restrict__ len, const uint32_t* s_tab,
-                                                     CT* sc, uint64_t n, uint32_t C, uint32_t* cbits, uint32_t* cu,
+                                                     const uint8_t* s_len8, CT* sc, uint64_t n, uint32_t C, uint32_t* cbits, uint32_t* cu,
                                                      uint32_t* ctb, typename FTr<T>::U ebb, uint32_t tlo) {
   using U = typename FTr<T>::U;
   using XR = XorRec<T>;
@@ -1354,7 +1366,7 @@ __device__ __forceinline__ void chunk_stats_xor_body(const CT* __restrict__ code
 #pragma unroll
       for (int k = 0; k < 4; k++) {
         const bool real = k0 + j + k < cnt;
-        b += real ? (code_entry<LT>(sym[k], s_tab, len, nullptr, tlo) >> 27) : 0u;
+        b += real ? code_len<MODE>(sym[k], s_tab, s_len8, len, tlo) : 0u;
         anyz |= real && sym[k] == 0;
       }
       if (anyz) {
@@ -1401,38 +1413,48 @@ __device__ __forceinline__ void chunk_stats_xor_body(const CT* __restrict__ code
   }
 }
 
-template <typename T, typename CT>
+// L8 (2-byte codes with alphabets that may outgrow the LDS table): the code
+// lengths as one byte per symbol in dynamic LDS after the codes, so that
+// every length comes from LDS (65,536 bytes at m = 16).
+template <typename T, typename CT, bool L8 = false>
 __device__ __forceinline__ void chunk_stats_kernel_dev(const CT* __restrict__ codes, const T* __restrict__ x,
                                                           const uint8_t* __restrict__ len, uint64_t n,
                                                           uint32_t C, uint32_t* cbits, uint32_t* cu,
                                                           uint32_t* ctb, const DevPlan* P) {
-  extern __shared__ uint4 s_dyn[];  // [4][C] codes, one slice per wave
-  __shared__ uint32_t s_tab[kTabLds];
+  extern __shared__ uint4 s_dyn[];  // [4][C] codes, one slice per wave (then the L8 lengths)
+  __shared__ uint32_t s_tab[L8 ? 1 : kTabLds + 1];
   if (P->status) return;
   const uint32_t nsym = 1u << P->m;
   const bool lt = nsym <= kTabLds;
   const uint32_t tlo = tab_window(P->m);
-  for (uint32_t i = threadIdx.x; i < min(nsym, kTabLds); i += 256) s_tab[i] = (uint32_t)len[tlo + i] << 27;
+  uint8_t* s_len8 = (uint8_t*)((CT*)s_dyn + 4 * (size_t)C);
+  if constexpr (L8) {
+    for (uint32_t i = threadIdx.x; i < (nsym + 3) / 4; i += 256) ((uint32_t*)s_len8)[i] = ((const uint32_t*)len)[i];
+  } else {
+    for (uint32_t i = threadIdx.x; i < min(nsym, kTabLds); i += 256) s_tab[i] = (uint32_t)len[tlo + i] << 27;
+    if (!lt && threadIdx.x == 0) s_tab[kTabLds] = (uint32_t)len[0] << 27;
+  }
   __syncthreads();
   CT* sc = (CT*)s_dyn + (size_t)(threadIdx.x >> 6) * C;
   const auto ebb = (typename FTr<T>::U)P->ebT_bits;
+  constexpr int MW = L8 ? 2 : 0;  // the mode when the alphabet outgrows the table
   if (P->xorc) {
-    if (sizeof(CT) == 1 || lt)
-      chunk_stats_xor_body<T, CT, true>(codes, x, len, s_tab, sc, n, C, cbits, cu, ctb, ebb, tlo);
+    if (!L8 && (sizeof(CT) == 1 || lt))
+      chunk_stats_xor_body<T, CT, 1>(codes, x, len, s_tab, s_len8, sc, n, C, cbits, cu, ctb, ebb, tlo);
     else
-      chunk_stats_xor_body<T, CT, false>(codes, x, len, s_tab, sc, n, C, cbits, cu, ctb, ebb, tlo);
-  } else if (sizeof(CT) == 1 || lt) {
-    chunk_stats_body<T, CT, true>(codes, x, len, s_tab, sc, n, C, cbits, cu, ctb, ebb, tlo);
+      chunk_stats_xor_body<T, CT, MW>(codes, x, len, s_tab, s_len8, sc, n, C, cbits, cu, ctb, ebb, tlo);
+  } else if (!L8 && (sizeof(CT) == 1 || lt)) {
+    chunk_stats_body<T, CT, 1>(codes, x, len, s_tab, s_len8, sc, n, C, cbits, cu, ctb, ebb, tlo);
   } else {
-    chunk_stats_body<T, CT, false>(codes, x, len, s_tab, sc, n, C, cbits, cu, ctb, ebb, tlo);
+    chunk_stats_body<T, CT, MW>(codes, x, len, s_tab, s_len8, sc, n, C, cbits, cu, ctb, ebb, tlo);
   }
 }
-template <typename T, typename CT>
+template <typename T, typename CT, bool L8 = false>
 __global__ void __launch_bounds__(256) chunk_stats_kernel(const CT* __restrict__ codes, const T* __restrict__ x,
                                                           const uint8_t* __restrict__ len, uint64_t n,
                                                           uint32_t C, uint32_t* cbits, uint32_t* cu,
                                                           uint32_t* ctb, const DevPlan* P) {
-  chunk_stats_kernel_dev<T, CT>(codes, x, len, n, C, cbits, cu, ctb, P);
+  chunk_stats_kernel_dev<T, CT, L8>(codes, x, len, n, C, cbits, cu, ctb, P);
 }
 
 
@@ -1579,7 +1601,7 @@ __host__ __device__ constexpr uint32_t enc_lds_bytes(uint32_t C, uint32_t code_b
   return 4u * (enc_words_per_wave(C, value_bytes, xorc) * 4u + C * code_bytes);
 }
 
-template <typename T, typename CT, bool LT, bool XORC>
+template <typename T, typename CT, bool LT, bool XORC, int PR>
 __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const T* __restrict__ x,
                                             const uint8_t* __restrict__ len, const uint32_t* __restrict__ cw,
                                             const uint32_t* s_tab, uint32_t* words, CT* sc, uint64_t n,
@@ -1606,43 +1628,48 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
     const uint32_t k0 = (uint32_t)lane * per;
     const uint64_t i0 = c * C + k0;  // a multiple of 4
     uint32_t mybits = 0, myz = 0, mytb = 0;
-    bool has = false;
-    U last = 0;
-    for (uint32_t j = 0; j < per; j += 4) {
-      uint32_t sym[4];
-      lds_code4<CT>(sc, k0 + j, sym);
-      bool anyz = false;
+    // PR > 0 (a lane holds at most PR codes): the lane's unpredictable
+    // values are loaded once, with every load in flight together, and kept
+    // in registers for the passes below; otherwise each pass loads them.
+    T xr[PR > 0 ? PR / 4 : 1][4];
+    uint32_t zmask = 0;  // PR > 0: bit q set when the lane's code q is 0
+    if constexpr (PR > 0) {
 #pragma unroll
-      for (int k = 0; k < 4; k++) {
-        const bool real = k0 + j + k < cnt;
-        mybits += real ? (code_entry<LT>(sym[k], s_tab, len, cw, tlo) >> 27) : 0u;
-        anyz |= real && sym[k] == 0;
-      }
-      if (anyz) {
-        // unpredictable values come four at a time (16-byte aligned loads)
-        T xv[4];
-        load4<T>(x, i0 + j, n, xv);
+      for (int g = 0; g < PR / 4; g++) {
+        if ((uint32_t)(4 * g) < per) {
+          uint32_t sym[4];
+          lds_code4<CT>(sc, k0 + 4 * g, sym);
 #pragma unroll
-        for (int k = 0; k < 4; k++)
-          if (k0 + j + k < cnt && sym[k] == 0) {
-            myz++;
-            if constexpr (XORC) {
-              has = true;
-              last = to_bits<T>(truncate_unpred<T>(xv[k], ebb));
-            } else {
-              mytb += (uint32_t)kept_bits<T>(xv[k], ebb);
-            }
+          for (int k = 0; k < 4; k++) {
+            const bool real = k0 + 4 * g + k < cnt;
+            mybits += real ? (code_entry<LT>(sym[k], s_tab, len, cw, tlo) >> 27) : 0u;
+            zmask |= (real && sym[k] == 0) ? 1u << (4 * g + k) : 0u;
           }
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < PR / 4; g++)
+        if ((zmask >> (4 * g)) & 15u) load4<T>(x, i0 + 4 * g, n, xr[g]);
+    } else {
+      for (uint32_t j = 0; j < per; j += 4) {
+        uint32_t sym[4];
+        lds_code4<CT>(sc, k0 + j, sym);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          const bool real = k0 + j + k < cnt;
+          mybits += real ? (code_entry<LT>(sym[k], s_tab, len, cw, tlo) >> 27) : 0u;
+        }
       }
     }
-    // XOR coding: the chunk's previous pattern before the lane's first value
-    // (the last of the lanes before it), then the sizes of the lane's records
-    U prev0 = 0;
-    if constexpr (XORC) {
-      using XR = XorRec<T>;
-      prev0 = wave_prev_present<U>(has, last);
-      U prev = prev0;
-      if (myz) {
+    // The lane's unpredictable values, in order, as (reduced pattern, kept
+    // mantissa bits); `emit` takes each one.
+    auto each_unpred = [&](auto&& emit) {
+      if constexpr (PR > 0) {
+#pragma unroll
+        for (int q = 0; q < PR; q++)
+          if ((zmask >> q) & 1u)
+            emit(to_bits<T>(truncate_unpred<T>(xr[q / 4][q % 4], ebb)), kept_bits<T>(xr[q / 4][q % 4], ebb));
+      } else {
         for (uint32_t j = 0; j < per; j += 4) {
           uint32_t sym[4];
           lds_code4<CT>(sc, k0 + j, sym);
@@ -1650,17 +1677,39 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
 #pragma unroll
           for (int k = 0; k < 4; k++) anyz |= k0 + j + k < cnt && sym[k] == 0;
           if (!anyz) continue;
+          // unpredictable values come four at a time (16-byte aligned loads)
           T xv[4];
           load4<T>(x, i0 + j, n, xv);
 #pragma unroll
           for (int k = 0; k < 4; k++)
-            if (k0 + j + k < cnt && sym[k] == 0) {
-              const U u = to_bits<T>(truncate_unpred<T>(xv[k], ebb));
-              mytb += (uint32_t)XR::bits(u, prev, XR::HB + kept_bits<T>(xv[k], ebb));
-              prev = u;
-            }
+            if (k0 + j + k < cnt && sym[k] == 0)
+              emit(to_bits<T>(truncate_unpred<T>(xv[k], ebb)), kept_bits<T>(xv[k], ebb));
         }
       }
+    };
+    bool has = false;
+    U last = 0;
+    each_unpred([&](U ub, int r) {
+      myz++;
+      if constexpr (XORC) {
+        has = true;
+        last = ub;
+      } else {
+        mytb += (uint32_t)r;
+      }
+    });
+    // XOR coding: the chunk's previous pattern before the lane's first value
+    // (the last of the lanes before it), then the sizes of the lane's records
+    U prev0 = 0;
+    if constexpr (XORC) {
+      using XR = XorRec<T>;
+      prev0 = wave_prev_present<U>(has, last);
+      U prev = prev0;
+      if (myz)
+        each_unpred([&](U u, int r) {
+          mytb += (uint32_t)XR::bits(u, prev, XR::HB + r);
+          prev = u;
+        });
       // the chunk's entry of the table of record bits (the heads section)
       const uint32_t tot = wave_sum(mytb);
       if (lane == 0) hd[c] = tot;
@@ -1713,24 +1762,6 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
     }
     if (lane == 0) ch[c] = nb;
     if (zch) {
-      // The lane's unpredictable values, in order, as (reduced pattern, kept
-      // mantissa bits); `emit` takes each one.
-      auto each_unpred = [&](auto&& emit) {
-        for (uint32_t j = 0; j < per; j += 4) {
-          uint32_t sym[4];
-          lds_code4<CT>(sc, k0 + j, sym);
-          bool anyz = false;
-#pragma unroll
-          for (int k = 0; k < 4; k++) anyz |= k0 + j + k < cnt && sym[k] == 0;
-          if (!anyz) continue;
-          T xv[4];
-          load4<T>(x, i0 + j, n, xv);
-#pragma unroll
-          for (int k = 0; k < 4; k++)
-            if (k0 + j + k < cnt && sym[k] == 0)
-              emit(to_bits<T>(truncate_unpred<T>(xv[k], ebb)), kept_bits<T>(xv[k], ebb));
-        }
-      };
       // tails: the kept mantissa bits, or the XOR records
       U prev = prev0;
       auto put_tail = [&](BitWriter& wt, U ub, int r) {
@@ -1791,7 +1822,9 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
   }
 }
 
-template <typename T, typename CT>
+// PR: 0, or 16 for chunks of at most 1024 codes (the unpredictable values
+// of each lane held in registers; more registers, fewer loads).
+template <typename T, typename CT, int PR = 0>
 __device__ __forceinline__ void encode_kernel_dev(const CT* __restrict__ codes, const T* __restrict__ x,
                                                         const uint8_t* __restrict__ len,
                                                         const uint32_t* __restrict__ cw, uint64_t n, uint32_t C,
@@ -1802,12 +1835,13 @@ __device__ __forceinline__ void encode_kernel_dev(const CT* __restrict__ codes, 
   // 1-byte codes have at most 256 symbols: a table that small leaves room
   // for a second workgroup per CU
   constexpr uint32_t kTab = sizeof(CT) == 1 ? 256 : kTabLds;
-  __shared__ uint32_t s_tab[kTab];
+  __shared__ uint32_t s_tab[kTab + 1];
   if (P->status || P->raw) return;
   const uint32_t nsym = 1u << P->m;
   const bool lt = nsym <= kTab;
   const uint32_t tlo = tab_window(P->m);
   for (uint32_t i = threadIdx.x; i < min(nsym, kTab); i += kEncNT) s_tab[i] = cw[tlo + i];  // len << 27 | code
+  if (!lt && threadIdx.x == 0) s_tab[kTab] = cw[0];  // code 0 beside the window
   __syncthreads();
   const int wv = threadIdx.x >> 6;
   const uint32_t wpw = enc_words_per_wave(C, sizeof(T), P->xorc != 0);
@@ -1815,23 +1849,31 @@ __device__ __forceinline__ void encode_kernel_dev(const CT* __restrict__ codes, 
   CT* sc = (CT*)((uint32_t*)s_dyn + 4 * (size_t)wpw) + (size_t)wv * C;
   if (P->xorc) {
     if (sizeof(CT) == 1 || lt)
-      encode_body<T, CT, true, true>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P, tlo);
+      encode_body<T, CT, true, true, PR>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P,
+                                         tlo);
     else
-      encode_body<T, CT, false, true>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P, tlo);
+      encode_body<T, CT, false, true, PR>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P,
+                                          tlo);
   } else if (sizeof(CT) == 1 || lt) {
-    encode_body<T, CT, true, false>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P, tlo);
+    encode_body<T, CT, true, false, PR>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P,
+                                        tlo);
   } else {
-    encode_body<T, CT, false, false>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P, tlo);
+    encode_body<T, CT, false, false, PR>(codes, x, len, cw, s_tab, words, sc, n, C, cbits, boff, uoff, toff, out, P,
+                                         tlo);
   }
 }
-template <typename T, typename CT>
+template <typename T, typename CT, int PR>
 __global__ void __launch_bounds__(kEncNT) encode_kernel(const CT* __restrict__ codes, const T* __restrict__ x,
                                                         const uint8_t* __restrict__ len,
                                                         const uint32_t* __restrict__ cw, uint64_t n, uint32_t C,
                                                         const uint32_t* cbits, const uint64_t* boff,
                                                         const uint64_t* uoff, const uint64_t* toff,
-                                                        uint8_t* out, const DevPlan* P) {
-  encode_kernel_dev<T, CT>(codes, x, len, cw, n, C, cbits, boff, uoff, toff, out, P);
+                                                        uint8_t* out, const DevPlan* P, uint32_t by_share) {
+  // by_share: both forms are launched and only one runs, the register form
+  // when more than one value in 16 is unpredictable (its extra registers
+  // cost occupancy that only such fields win back)
+  if (by_share && ((P->n_unpred * 16 > n) != (PR > 0))) return;
+  encode_kernel_dev<T, CT, PR>(codes, x, len, cw, n, C, cbits, boff, uoff, toff, out, P);
 }
 
 

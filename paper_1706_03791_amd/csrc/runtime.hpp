@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -586,10 +587,22 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
     hipLaunchKernelGGL((chunk_stats_kernel<T, uint8_t>), dim3(nch), dim3(256), cs_lds, st, (const uint8_t*)W.codes,
                        (const T*)d_in, (const uint8_t*)W.len, (uint64_t)L.n, L.chunk, W.cbits, W.cu, W.ctb,
                        (const DevPlan*)P);
-  else
+  else if (L.m_req != 0 && L.m_req <= 12)
     hipLaunchKernelGGL((chunk_stats_kernel<T, uint16_t>), dim3(nch), dim3(256), cs_lds, st, (const uint16_t*)W.codes,
                        (const T*)d_in, (const uint8_t*)W.len, (uint64_t)L.n, L.chunk, W.cbits, W.cu, W.ctb,
                        (const DevPlan*)P);
+  else {
+    // alphabets that may outgrow the LDS table: every code length in LDS as
+    // a byte (two workgroups per CU, each over many chunks, so that few
+    // workgroups load the 64 KiB of lengths)
+    const unsigned lds8 = cs_lds + 65536u;
+    const unsigned nch8 = (unsigned)std::min<uint64_t>(ceil_div(L.n_chunks, 4), 512);
+    (void)hipFuncSetAttribute((const void*)chunk_stats_kernel<T, uint16_t, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds8);
+    hipLaunchKernelGGL((chunk_stats_kernel<T, uint16_t, true>), dim3(nch8), dim3(256), lds8, st,
+                       (const uint16_t*)W.codes, (const T*)d_in, (const uint8_t*)W.len, (uint64_t)L.n, L.chunk,
+                       W.cbits, W.cu, W.ctb, (const DevPlan*)P);
+  }
   {
     // bit, unpredictable and tail-bit offsets of every chunk
     const Scan3 S{{W.cbits, W.cu, W.ctb}, {W.boff, W.uoff, W.toff}, {W.tsum_b, W.tsum_u, W.tsum_t},
@@ -614,21 +627,35 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
                        (uint8_t*)d_out, (uint64_t)L.n, (const DevPlan*)P);
   }
   const unsigned enc_lds = enc_lds_bytes(L.chunk, (uint32_t)L.cw, (uint32_t)L.ts, L.xorc != 0);
-  if (L.cw == 1) {
-    (void)hipFuncSetAttribute((const void*)encode_kernel<T, uint8_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)enc_lds);
-    hipLaunchKernelGGL((encode_kernel<T, uint8_t>), dim3(nch), dim3(kEncNT), enc_lds, st, (const uint8_t*)W.codes,
+  // One encoder form per call: values of unpredictable-heavy chunks held in
+  // registers (f64 always; f32 when the share found on the device asks for
+  // it, the other form returning at once) or loaded by each pass.  The f32
+  // register form runs on a grid that fits the GPU at once (its waves loop
+  // over the chunks), so that returning costs a single round of workgroups.
+  auto launch_enc = [&](auto ct, auto pr, uint32_t by_share, unsigned grid) {
+    using CT = std::remove_pointer_t<decltype(ct)>;
+    constexpr int PR = decltype(pr)::value;
+    (void)hipFuncSetAttribute((const void*)encode_kernel<T, CT, PR>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)enc_lds);
+    hipLaunchKernelGGL((encode_kernel<T, CT, PR>), dim3(grid), dim3(kEncNT), enc_lds, st, (const CT*)W.codes,
                        (const T*)d_in, (const uint8_t*)W.len, (const uint32_t*)W.cw, (uint64_t)L.n, L.chunk,
                        (const uint32_t*)W.cbits, (const uint64_t*)W.boff, (const uint64_t*)W.uoff,
-                       (const uint64_t*)W.toff, (uint8_t*)d_out, (const DevPlan*)P);
-  } else {
-    (void)hipFuncSetAttribute((const void*)encode_kernel<T, uint16_t>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)enc_lds);
-    hipLaunchKernelGGL((encode_kernel<T, uint16_t>), dim3(nch), dim3(kEncNT), enc_lds, st, (const uint16_t*)W.codes,
-                       (const T*)d_in, (const uint8_t*)W.len, (const uint32_t*)W.cw, (uint64_t)L.n, L.chunk,
-                       (const uint32_t*)W.cbits, (const uint64_t*)W.boff, (const uint64_t*)W.uoff,
-                       (const uint64_t*)W.toff, (uint8_t*)d_out, (const DevPlan*)P);
-  }
+                       (const uint64_t*)W.toff, (uint8_t*)d_out, (const DevPlan*)P, by_share);
+  };
+  auto enc_forms = [&](auto ct) {
+    if (L.chunk > 1024) {
+      launch_enc(ct, std::integral_constant<int, 0>{}, 0u, nch);
+    } else if (sizeof(T) == 8) {
+      launch_enc(ct, std::integral_constant<int, 16>{}, 0u, nch);
+    } else {
+      launch_enc(ct, std::integral_constant<int, 0>{}, 1u, nch);
+      launch_enc(ct, std::integral_constant<int, 16>{}, 1u, std::min(nch, 1024u));
+    }
+  };
+  if (L.cw == 1)
+    enc_forms((uint8_t*)nullptr);
+  else
+    enc_forms((uint16_t*)nullptr);
   HeaderArgs h;
   h.out = (uint8_t*)d_out;
   h.len = W.len;
