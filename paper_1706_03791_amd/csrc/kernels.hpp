@@ -1650,16 +1650,6 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
 #pragma unroll
       for (int g = 0; g < PR / 4; g++)
         if ((zmask >> (4 * g)) & 15u) load4<T>(x, i0 + 4 * g, n, xr[g]);
-    } else {
-      for (uint32_t j = 0; j < per; j += 4) {
-        uint32_t sym[4];
-        lds_code4<CT>(sc, k0 + j, sym);
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-          const bool real = k0 + j + k < cnt;
-          mybits += real ? (code_entry<LT>(sym[k], s_tab, len, cw, tlo) >> 27) : 0u;
-        }
-      }
     }
     // The lane's unpredictable values, in order, as (reduced pattern, kept
     // mantissa bits); `emit` takes each one.
@@ -1689,7 +1679,7 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
     };
     bool has = false;
     U last = 0;
-    each_unpred([&](U ub, int r) {
+    auto count_unpred = [&](U ub, int r) {
       myz++;
       if constexpr (XORC) {
         has = true;
@@ -1697,7 +1687,31 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
       } else {
         mytb += (uint32_t)r;
       }
-    });
+    };
+    if constexpr (PR > 0) {
+      each_unpred(count_unpred);
+    } else {
+      // code lengths and the unpredictable values in one pass
+      for (uint32_t j = 0; j < per; j += 4) {
+        uint32_t sym[4];
+        lds_code4<CT>(sc, k0 + j, sym);
+        bool anyz = false;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+          const bool real = k0 + j + k < cnt;
+          mybits += real ? (code_entry<LT>(sym[k], s_tab, len, cw, tlo) >> 27) : 0u;
+          anyz |= real && sym[k] == 0;
+        }
+        if (anyz) {
+          T xv[4];
+          load4<T>(x, i0 + j, n, xv);
+#pragma unroll
+          for (int k = 0; k < 4; k++)
+            if (k0 + j + k < cnt && sym[k] == 0)
+              count_unpred(to_bits<T>(truncate_unpred<T>(xv[k], ebb)), kept_bits<T>(xv[k], ebb));
+        }
+      }
+    }
     // XOR coding: the chunk's previous pattern before the lane's first value
     // (the last of the lanes before it), then the sizes of the lane's records
     U prev0 = 0;
