@@ -1949,17 +1949,52 @@ __device__ __forceinline__ void header_kernel_dev(HeaderArgs A) {
   const uint32_t nsym = 1u << P->m;
   const uint32_t per = (nsym + 255) / 256;
   const uint32_t lo = min(nsym, tid * per), hi = min(nsym, lo + per);
-  uint32_t cnt = 0;
-  for (uint32_t q = lo; q < hi; q++) cnt += A.len[q] != 0;
-  uint32_t pos = block_exscan<256, uint32_t>(cnt, red, nullptr);
   uint8_t* cb = A.out + P->off_cb;
-  for (uint32_t q = lo; q < hi; q++) {
-    const uint8_t l = A.len[q];
-    if (!l) continue;
+  auto put = [&](uint32_t q, uint32_t l, uint32_t& pos) {
     cb[3 * pos + 0] = (uint8_t)(q & 0xFF);
     cb[3 * pos + 1] = (uint8_t)(q >> 8);
-    cb[3 * pos + 2] = l;
+    cb[3 * pos + 2] = (uint8_t)l;
     pos++;
+  };
+  if (per % 16 == 0) {
+    // 16 lengths per load (the length array is 256-byte aligned), four
+    // loads in flight: a thread's 256 lengths at m = 16 are 16 loads, not 256
+    const uint4* L4 = (const uint4*)(A.len + lo);
+    const uint32_t nv = per / 16;
+    auto nz = [](uint32_t w) {
+      return (uint32_t)((w & 0xFFu) != 0) + ((w & 0xFF00u) != 0) + ((w & 0xFF0000u) != 0) + ((w >> 24) != 0);
+    };
+    uint32_t cnt = 0;
+    for (uint32_t v0 = 0; v0 < nv; v0 += 4) {
+      uint4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) v[u] = v0 + u < nv ? L4[v0 + u] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < 4; u++) cnt += nz(v[u].x) + nz(v[u].y) + nz(v[u].z) + nz(v[u].w);
+    }
+    uint32_t pos = block_exscan<256, uint32_t>(cnt, red, nullptr);
+    for (uint32_t v0 = 0; v0 < nv; v0 += 4) {
+      uint4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) v[u] = v0 + u < nv ? L4[v0 + u] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const uint32_t w[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+        for (int e = 0; e < 16; e++) {
+          const uint32_t l = (w[e / 4] >> (8 * (e % 4))) & 0xFFu;
+          if (l) put(lo + 16 * (v0 + u) + e, l, pos);
+        }
+      }
+    }
+  } else {
+    uint32_t cnt = 0;
+    for (uint32_t q = lo; q < hi; q++) cnt += A.len[q] != 0;
+    uint32_t pos = block_exscan<256, uint32_t>(cnt, red, nullptr);
+    for (uint32_t q = lo; q < hi; q++) {
+      const uint8_t l = A.len[q];
+      if (l) put(q, l, pos);
+    }
   }
 }
 __global__ void __launch_bounds__(256) header_kernel(HeaderArgs A) {
