@@ -134,6 +134,25 @@ def test_chunk_sizes(Z, oracle, chunk):
     check(Z, oracle, x, layers=1, m=8, eb_mode="rel", eb_rel=1e-4, chunk=chunk)
 
 
+@pytest.mark.parametrize("xorc", [0, 1], ids=["kept-bits", "xor"])
+@pytest.mark.parametrize("chunk", [256, 512, 1024, 2048])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64], ids=["f32", "f64"])
+def test_dense_unpredictable_encoder_forms(Z, oracle, dtype, chunk, xorc):
+    """Fields with most values unpredictable (a random walk along x plus
+    sparse noise, 16 bins): chunks of up to 1024 codes take the encoder form
+    that keeps each lane's values in registers (f64 always, f32 when more
+    than one value in 16 is unpredictable), longer chunks the form that loads
+    them in every pass.  Both give the oracle's bytes (Sec. IV-B, Algorithm 1
+    step storing the unpredictable value)."""
+    rng = np.random.default_rng(11 + chunk)
+    shape = (24, 30, 37)
+    walk = np.cumsum(rng.normal(0, 1, shape), axis=2)
+    x = (walk + rng.normal(0, 0.5, shape) * (rng.random(shape) < 0.3)).astype(dtype)
+    s = check(Z, oracle, x, layers=1, m=4, eb_mode="rel", eb_rel=1e-3, chunk=chunk, unpred_coding=xorc)
+    assert s["n_unpred"] * 16 > x.size
+    assert s["n_unpred"] < x.size
+
+
 def test_constant_field(Z, oracle):
     x = np.full((20, 30, 40), 3.25, np.float32)
     check(Z, oracle, x, layers=1, m=8, eb_mode="abs", eb_abs=1e-3)
