@@ -12,6 +12,24 @@ namespace szh {
 // carries its own copy.
 namespace {
 
+// ------------------------------------------------------------ wave peers
+// The lanes (among the `ok` ones) whose B-bit key equals this lane's, from
+// B ballots.  Counting a key once per group, by the group's highest lane,
+// replaces same-address LDS atomics, which serialise over the lanes.
+template <int B>
+__device__ __forceinline__ uint64_t wave_peers(bool ok, uint32_t key) {
+  uint64_t peers = __ballot(ok);
+#pragma unroll
+  for (int b = 0; b < B; b++) {
+    const uint64_t bb = __ballot(ok && ((key >> b) & 1u));
+    peers &= ((key >> b) & 1u) ? bb : ~bb;
+  }
+  return peers;
+}
+__device__ __forceinline__ bool peers_last(uint64_t peers) {
+  return (peers >> (threadIdx.x & 63)) == 1ull;
+}
+
 // ------------------------------------------------------------ block scans
 // Exclusive scan over a workgroup of NT threads (NT a multiple of 64).
 template <int NT, typename V>
@@ -506,9 +524,13 @@ __device__ __forceinline__ void rank_by_length(uint32_t n, const G& get_len, con
   __syncthreads();
   const uint32_t sg = (n + NWV - 1) / NWV;
   const uint32_t g0 = min(n, (uint32_t)wv * sg), g1 = min(n, g0 + sg);
-  for (uint32_t q = g0 + lane; q < g1; q += 64) {
-    const uint32_t l = get_len(q);
-    if (l) atomicAdd(&lc[wv][l], 1u);
+  for (uint32_t q0 = g0; q0 < g1; q0 += 64) {
+    // a few lengths take most items: each length present is added once
+    const uint32_t q = q0 + lane;
+    const uint32_t l = q < g1 ? get_len(q) : 0u;
+    const uint64_t peers = wave_peers<5>(l != 0, l);
+    if (l && peers_last(peers)) lc[wv][l] += (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
   if (tid >= 1 && tid < 32) {
@@ -2087,17 +2109,21 @@ __global__ void __launch_bounds__(1024) dectab_kernel(const uint8_t* comp, uint6
   // address LDS or global memory compiles to slower generic ones).
   auto build = [&](uint64_t* K, bool lds) {
     for (uint32_t e = tid; e < np2; e += 1024) {
+      uint32_t l = 0;
       if (e < n_used) {
         const uint8_t* b = comp + off_cb + 3ull * e;
         const uint32_t sym = b[0] | (b[1] << 8);
-        const uint32_t l = b[2];
+        l = b[2];
         if (sym >= nsym || l == 0 || l > kLmax) s_bad = 1;
         if (e > 0) {
           const uint8_t* pb = b - 3;
           if ((uint32_t)(pb[0] | (pb[1] << 8)) >= sym) s_bad = 1;
         }
-        if (l >= 1 && l <= kLmax) atomicAdd(&s_cnt[l], 1u);
       }
+      // one atomic per length present in the wave
+      const bool okl = l >= 1 && l <= kLmax;
+      const uint64_t peers = wave_peers<5>(okl, l);
+      if (okl && peers_last(peers)) atomicAdd(&s_cnt[l], (uint32_t)__popcll(peers));
     }
     __syncthreads();
     if (tid == 0) {
