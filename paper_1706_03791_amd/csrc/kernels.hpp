@@ -416,6 +416,7 @@ constexpr uint32_t kCbLdsSyms = 2048;
 // Rounds of the parallel construction: the lightest available weight at
 // least doubles per round and all weights sum to N < 2^40, so 41 suffice.
 constexpr int kCbMaxRounds = 96;
+constexpr int kCbBatch = 8;  // key loads a sort thread keeps in flight
 
 // Entries of the nondecreasing sequence get(lo .. hi-1) below x (LE: not
 // above x), by binary search.
@@ -442,10 +443,9 @@ __device__ __forceinline__ uint32_t cb_count(const G& get, uint32_t lo, uint32_t
 // the wave's offset for that digit on, so every pass keeps the order of
 // equal digits.
 __device__ void cb_radix_sort(uint64_t* k, uint64_t* tmp, uint32_t n, uint32_t* cnt, uint32_t* off,
-                              uint32_t* red, uint32_t* s_max) {
+                              uint32_t* red, uint32_t* s_max, uint32_t mx) {
+  // mx: the largest frequency among the keys this thread wrote
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  uint32_t mx = 0;
-  for (uint32_t i = tid; i < n; i += kCbNT) mx = max(mx, (uint32_t)(k[i] >> 16));
   for (int o = 32; o >= 1; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, o, 64));
   if (tid == 0) *s_max = 0;
   __syncthreads();
@@ -460,7 +460,25 @@ __device__ void cb_radix_sort(uint64_t* k, uint64_t* tmp, uint32_t n, uint32_t* 
   for (int shift = 16; shift < 16 + nbits; shift += 8) {
     for (int e = tid; e < kCbNW * 256; e += kCbNT) cnt[e] = 0;
     __syncthreads();
-    for (uint32_t i = s0 + lane; i < s1; i += 64) atomicAdd(&cnt[w * 256 + ((src[i] >> shift) & 255)], 1u);
+    for (uint32_t i0 = s0; i0 < s1; i0 += 64 * kCbBatch) {
+      uint64_t kb[kCbBatch];
+#pragma unroll
+      for (int u = 0; u < kCbBatch; u++) kb[u] = i0 + 64 * u + lane < s1 ? src[i0 + 64 * u + lane] : 0ull;
+#pragma unroll
+      for (int u = 0; u < kCbBatch; u++) {
+        const bool ok = i0 + 64 * u + lane < s1;
+        const uint32_t d = (uint32_t)((kb[u] >> shift) & 255);
+        // the high digits of small frequencies are all 0: a batch of one
+        // digit is one add, not 64 adds to one address
+        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+        const uint64_t okm = __ballot(ok);  // (a ballot inside the lane-0 branch would see lane 0 only)
+        if (__ballot(ok && d != d0) == 0) {
+          if (lane == 0 && ok) atomicAdd(&cnt[w * 256 + d0], (uint32_t)__popcll(okm));
+        } else if (ok) {
+          atomicAdd(&cnt[w * 256 + d], 1u);
+        }
+      }
+    }
     __syncthreads();
     // exclusive scan in (digit, wave) order: element e = digit * kCbNW + wave
     static_assert(kCbNW * 256 == 4 * kCbNT, "four scan elements per thread");
@@ -479,10 +497,19 @@ __device__ void cb_radix_sort(uint64_t* k, uint64_t* tmp, uint32_t n, uint32_t* 
       base += v[q];
     }
     __syncthreads();
+    uint64_t kb[kCbBatch];
     for (uint32_t i0 = s0; i0 < s1; i0 += 64) {
       const uint32_t i = i0 + lane;
       const bool ok = i < s1;
-      const uint64_t key = ok ? src[i] : 0ull;
+      // the next kCbBatch batches are loaded together (src and dst differ)
+      const uint32_t u = ((i0 - s0) / 64) % kCbBatch;
+      if (u == 0) {
+#pragma unroll
+        for (int q = 0; q < kCbBatch; q++) kb[q] = i + 64 * q < s1 ? src[i + 64 * q] : 0ull;
+      }
+      uint64_t key = kb[0];
+#pragma unroll
+      for (int q = 1; q < kCbBatch; q++) key = u == (uint32_t)q ? kb[q] : key;
       const uint32_t d = (uint32_t)((key >> shift) & 255);
       uint64_t peers = __ballot(ok);
 #pragma unroll
@@ -640,13 +667,17 @@ __device__ __forceinline__ void codebook_kernel_dev(CodebookArgs A) {
                      bool lds) {
       uint32_t np2 = 1;
       while (np2 < s) np2 <<= 1;
+      uint32_t kmax = 0;  // this thread's largest leaf frequency
       for (int halvings = 0; halvings < 64; halvings++) {
         // leaves with frequencies max(1, f >> halvings), in symbol order
         {
           uint32_t pos = pos0;
+          kmax = 0;
           for (uint32_t q = lo; q < hi; q++) {
             const uint32_t f = A.hist[q];
-            if (f) K[pos++] = ((uint64_t)max(1u, f >> min(halvings, 31)) << 16) | q;
+            const uint32_t fh = max(1u, f >> min(halvings, 31));
+            if (f) K[pos++] = ((uint64_t)fh << 16) | q;
+            if (f) kmax = max(kmax, fh);
           }
           if (lds)
             for (uint32_t i = s + tid; i < np2; i += kCbNT) K[i] = ~0ull;
@@ -655,7 +686,7 @@ __device__ __forceinline__ void codebook_kernel_dev(CodebookArgs A) {
         if (lds)
           bitonic_sort<kCbNT>(K, np2);
         else
-          cb_radix_sort(K, IW, s, s_mid, s_dep, s_red, &s_maxd);
+          cb_radix_sort(K, IW, s, s_mid, s_dep, s_red, &s_maxd, kmax);
         // rounds
         if (tid == 0) {
           s_a = 0;
