@@ -774,14 +774,47 @@ __device__ __forceinline__ void codebook_kernel_dev(CodebookArgs A) {
           const uint32_t r0 = s_rs[r], r1 = s_rs[r + 1];
           if (tid == 0 && r1 - 1 != cend - 1) DEP[s + r1 - 1] = DEP[PAR[s + r1 - 1]] + 1;
           __syncthreads();
-          for (uint32_t v = r0 + tid; v + 1 < r1; v += kCbNT) DEP[s + v] = DEP[PAR[s + v]] + 1;
+          if (lds) {
+            for (uint32_t v = r0 + tid; v + 1 < r1; v += kCbNT) DEP[s + v] = DEP[PAR[s + v]] + 1;
+          } else {
+            for (uint32_t v0 = r0 + tid; v0 + 1 < r1; v0 += kCbNT * kCbBatch) {
+              // a round's nodes hang below later rounds only (its last node,
+              // the one its first may hang below, is set above), so the
+              // parents of kCbBatch nodes are loaded together
+              uint32_t pa[kCbBatch], dd[kCbBatch];
+#pragma unroll
+              for (int u = 0; u < kCbBatch; u++) pa[u] = v0 + u * kCbNT + 1 < r1 ? PAR[s + v0 + u * kCbNT] : 0u;
+#pragma unroll
+              for (int u = 0; u < kCbBatch; u++) dd[u] = v0 + u * kCbNT + 1 < r1 ? DEP[pa[u]] + 1 : 0u;
+#pragma unroll
+              for (int u = 0; u < kCbBatch; u++)
+                if (v0 + u * kCbNT + 1 < r1) DEP[s + v0 + u * kCbNT] = dd[u];
+            }
+          }
           __syncthreads();
         }
         uint32_t md = 0;
-        for (uint32_t i = tid; i < s; i += kCbNT) {
-          const uint32_t d = DEP[PAR[i]] + 1;
-          DEP[i] = d;
-          md = max(md, d);
+        if (lds) {
+          for (uint32_t i = tid; i < s; i += kCbNT) {
+            const uint32_t d = DEP[PAR[i]] + 1;
+            DEP[i] = d;
+            md = max(md, d);
+          }
+        } else {
+          for (uint32_t i0 = tid; i0 < s; i0 += kCbNT * kCbBatch) {
+            // leaves read internal depths only: kCbBatch parents loaded together
+            uint32_t pa[kCbBatch], dd[kCbBatch];
+#pragma unroll
+            for (int u = 0; u < kCbBatch; u++) pa[u] = i0 + u * kCbNT < s ? PAR[i0 + u * kCbNT] : 0u;
+#pragma unroll
+            for (int u = 0; u < kCbBatch; u++) dd[u] = i0 + u * kCbNT < s ? DEP[pa[u]] + 1 : 0u;
+#pragma unroll
+            for (int u = 0; u < kCbBatch; u++)
+              if (i0 + u * kCbNT < s) {
+                DEP[i0 + u * kCbNT] = dd[u];
+                md = max(md, dd[u]);
+              }
+          }
         }
         for (int o = 32; o >= 1; o >>= 1) md = max(md, (uint32_t)__shfl_xor(md, o, 64));
         if (tid == 0) s_maxd = 0;
