@@ -2509,29 +2509,32 @@ __global__ void __launch_bounds__(DecShape<CT>::NT) decode_kernel(const uint8_t*
       const bool fast = k != 0 && ri + k <= lim;
       uint32_t sym = e & 0xFFFF, l1 = e >> 16;
       uint32_t e2 = 0;
-      if (e == 0 && n2) {
-        // a code of 13..16 bits: the second table, by prefix and next 4 bits
-        e2 = s_lut2[(w12 - p02) * 16 + (uint32_t)((buf >> (64 - 16)) & 15)];
-        sym = e2 & 0xFFFF;
-        l1 = e2 >> 16;
-      }
-      if (e == 0 && e2 == 0) {
-        // a code longer than the tables: its length is the count of limits
-        // its 27-bit window reaches
-        const uint32_t v27 = (uint32_t)(buf >> (64 - kLmax));
-        l1 = kLutBits + 1;
-#pragma unroll
-        for (int q = kLutBits + 1; q < kLmax; q++) l1 += (v27 >= s_lim[q]) ? 1u : 0u;
-        if (v27 >= s_lim[kLmax]) {
-          bad = true;
-          break;
+      if (e == 0) {
+        // (one branch for both rare cases: the common path passes a single test)
+        if (n2) {
+          // a code of 13..16 bits: the second table, by prefix and next 4 bits
+          e2 = s_lut2[(w12 - p02) * 16 + (uint32_t)((buf >> (64 - 16)) & 15)];
+          sym = e2 & 0xFFFF;
+          l1 = e2 >> 16;
         }
-        const uint32_t idx = s_start[l1] + ((v27 >> (kLmax - l1)) - s_first[l1]);
-        if (syms_lds) {
-          sym = s_syms[idx];
-        } else {
-          sym = sorted_syms[idx];
-          __builtin_amdgcn_s_waitcnt(0x0F70);
+        if (e2 == 0) {
+          // a code longer than the tables: its length is the count of limits
+          // its 27-bit window reaches
+          const uint32_t v27 = (uint32_t)(buf >> (64 - kLmax));
+          l1 = kLutBits + 1;
+#pragma unroll
+          for (int q = kLutBits + 1; q < kLmax; q++) l1 += (v27 >= s_lim[q]) ? 1u : 0u;
+          if (v27 >= s_lim[kLmax]) {
+            bad = true;
+            break;
+          }
+          const uint32_t idx = s_start[l1] + ((v27 >> (kLmax - l1)) - s_first[l1]);
+          if (syms_lds) {
+            sym = s_syms[idx];
+          } else {
+            sym = sorted_syms[idx];
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+          }
         }
       }
       const uint32_t syms = fast ? me.x : sym;
