@@ -1719,16 +1719,22 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
     // in registers for the passes below; otherwise each pass loads them.
     T xr[PR > 0 ? PR / 4 : 1][4];
     uint32_t zmask = 0;  // PR > 0: bit q set when the lane's code q is 0
+    // PR > 0: the code entries (len << 27 | code) as well, for the bitstream
+    // pass (0 past the chunk: a field of no bits)
+    uint32_t ent[PR > 0 ? PR : 1];
     if constexpr (PR > 0) {
 #pragma unroll
       for (int g = 0; g < PR / 4; g++) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) ent[4 * g + k] = 0u;
         if ((uint32_t)(4 * g) < per) {
           uint32_t sym[4];
           lds_code4<CT>(sc, k0 + 4 * g, sym);
 #pragma unroll
           for (int k = 0; k < 4; k++) {
             const bool real = k0 + 4 * g + k < cnt;
-            mybits += real ? (code_entry<LT>(sym[k], s_tab, len, cw, tlo) >> 27) : 0u;
+            ent[4 * g + k] = real ? code_entry<LT>(sym[k], s_tab, len, cw, tlo) : 0u;
+            mybits += ent[4 * g + k] >> 27;
             zmask |= (real && sym[k] == 0) ? 1u << (4 * g + k) : 0u;
           }
         }
@@ -1847,14 +1853,19 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
     };
     {
       BitWriter wb(words, bpos);
-      for (uint32_t j = 0; j < per; j += 4) {
-        uint32_t sym[4];
-        lds_code4<CT>(sc, k0 + j, sym);
+      if constexpr (PR > 0) {
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-          if (k0 + j + k >= cnt) break;
-          const uint32_t e = code_entry<LT>(sym[k], s_tab, len, cw, tlo);
-          wb.put(e & 0x07FFFFFFu, (int)(e >> 27));
+        for (int q = 0; q < PR; q++) wb.put(ent[q] & 0x07FFFFFFu, (int)(ent[q] >> 27));
+      } else {
+        for (uint32_t j = 0; j < per; j += 4) {
+          uint32_t sym[4];
+          lds_code4<CT>(sc, k0 + j, sym);
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            if (k0 + j + k >= cnt) break;
+            const uint32_t e = code_entry<LT>(sym[k], s_tab, len, cw, tlo);
+            wb.put(e & 0x07FFFFFFu, (int)(e >> 27));
+          }
         }
       }
       wb.finish();
