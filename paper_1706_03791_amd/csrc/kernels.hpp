@@ -1719,9 +1719,11 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
     // in registers for the passes below; otherwise each pass loads them.
     T xr[PR > 0 ? PR / 4 : 1][4];
     uint32_t zmask = 0;  // PR > 0: bit q set when the lane's code q is 0
-    // PR > 0: the code entries (len << 27 | code) as well, for the bitstream
-    // pass (0 past the chunk: a field of no bits)
-    uint32_t ent[PR > 0 ? PR : 1];
+    // PR != 0: the code entries (len << 27 | code) as well, for the bitstream
+    // pass (0 past the chunk: a field of no bits); PR < 0 keeps the -PR
+    // entries of a lane but loads the values in every pass
+    constexpr int NE = PR < 0 ? -PR : PR;
+    uint32_t ent[NE > 0 ? NE : 1];
     if constexpr (PR > 0) {
 #pragma unroll
       for (int g = 0; g < PR / 4; g++) {
@@ -1782,6 +1784,34 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
     };
     if constexpr (PR > 0) {
       each_unpred(count_unpred);
+    } else if constexpr (PR < 0) {
+      // code entries and the unpredictable values in one pass
+#pragma unroll
+      for (int g = 0; g < NE / 4; g++) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) ent[4 * g + k] = 0u;
+        if ((uint32_t)(4 * g) < per) {
+          const uint32_t j = 4 * g;
+          uint32_t sym[4];
+          lds_code4<CT>(sc, k0 + j, sym);
+          bool anyz = false;
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            const bool real = k0 + j + k < cnt;
+            ent[4 * g + k] = real ? code_entry<LT>(sym[k], s_tab, len, cw, tlo) : 0u;
+            mybits += ent[4 * g + k] >> 27;
+            anyz |= real && sym[k] == 0;
+          }
+          if (anyz) {
+            T xv[4];
+            load4<T>(x, i0 + j, n, xv);
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+              if (k0 + j + k < cnt && sym[k] == 0)
+                count_unpred(to_bits<T>(truncate_unpred<T>(xv[k], ebb)), kept_bits<T>(xv[k], ebb));
+          }
+        }
+      }
     } else {
       // code lengths and the unpredictable values in one pass
       for (uint32_t j = 0; j < per; j += 4) {
@@ -1853,9 +1883,9 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
     };
     {
       BitWriter wb(words, bpos);
-      if constexpr (PR > 0) {
+      if constexpr (NE > 0) {
 #pragma unroll
-        for (int q = 0; q < PR; q++) wb.put(ent[q] & 0x07FFFFFFu, (int)(ent[q] >> 27));
+        for (int q = 0; q < NE; q++) wb.put(ent[q] & 0x07FFFFFFu, (int)(ent[q] >> 27));
       } else {
         for (uint32_t j = 0; j < per; j += 4) {
           uint32_t sym[4];
@@ -1933,8 +1963,9 @@ __device__ __forceinline__ void encode_body(const CT* __restrict__ codes, const 
   }
 }
 
-// PR: 0, or 16 for chunks of at most 1024 codes (the unpredictable values
-// of each lane held in registers; more registers, fewer loads).
+// PR: 0; 16 for chunks of at most 1024 codes (the unpredictable values and
+// code entries of each lane held in registers; more registers, fewer loads);
+// -16 for such chunks with the code entries only in registers.
 template <typename T, typename CT, int PR = 0>
 __device__ __forceinline__ void encode_kernel_dev(const CT* __restrict__ codes, const T* __restrict__ x,
                                                         const uint8_t* __restrict__ len,

@@ -629,7 +629,8 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
   const unsigned enc_lds = enc_lds_bytes(L.chunk, (uint32_t)L.cw, (uint32_t)L.ts, L.xorc != 0);
   // One encoder form per call: values of unpredictable-heavy chunks held in
   // registers (f64 always; f32 when the share found on the device asks for
-  // it, the other form returning at once) or loaded by each pass.  The f32
+  // it, the other form returning at once) or loaded by each pass (with the
+  // code entries still kept in registers for chunks of up to 1024).  The f32
   // register form runs on a grid that fits the GPU at once (its waves loop
   // over the chunks), so that returning costs a single round of workgroups.
   auto launch_enc = [&](auto ct, auto pr, uint32_t by_share, unsigned grid) {
@@ -648,7 +649,7 @@ int enqueue_compress_t(sz_ctx* ctx, const Layout& L, const sz_params* p, const v
     } else if (sizeof(T) == 8) {
       launch_enc(ct, std::integral_constant<int, 16>{}, 0u, nch);
     } else {
-      launch_enc(ct, std::integral_constant<int, 0>{}, 1u, nch);
+      launch_enc(ct, std::integral_constant<int, -16>{}, 1u, nch);
       launch_enc(ct, std::integral_constant<int, 16>{}, 1u, std::min(nch, 1024u));
     }
   };
