@@ -436,7 +436,7 @@ void launch_hist(const Layout& L, const void* codes, uint32_t* hist, uint32_t* h
     (void)hipFuncSetAttribute((const void*)hist2_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     hipLaunchKernelGGL(hist2_kernel, dim3(nb, 2), dim3(1024), lds, st, (const uint16_t*)codes, (uint64_t)L.n, hpart,
                        P, pass2);
-    hipLaunchKernelGGL(hist2_reduce_kernel, dim3(65536 / 256), dim3(256), 0, st, (const uint32_t*)hpart, nb, hist,
+    hipLaunchKernelGGL(hist2_reduce_kernel, dim3(65536 / 256), dim3(1024), 0, st, (const uint32_t*)hpart, nb, hist,
                        P, pass2);
     return;
   }
