@@ -2359,7 +2359,10 @@ __global__ void __launch_bounds__(1024) dectab_kernel(const uint8_t* comp, uint6
 // bitstream is read in 16-byte groups one group ahead of use, the decoded
 // codes leave in 16-byte stores, and unpredictable codes are counted per
 // row segment (block row) with the segment tracked incrementally.
-constexpr uint32_t kSymLds = 4096;
+// 2-byte codes: the decoder runs one 1024-thread workgroup per CU, so its LDS
+// can hold the symbols of all but the longest 4096 codes (tables 16 KiB,
+// bitstream windows 16 KiB, symbols 120 KiB).
+constexpr uint32_t kSymLds = 61440;
 constexpr int kDecRing = 16;    // words of bitstream per lane in LDS (1-byte codes)
 constexpr int kDecPeriod = 8;   // iterations between the reloads of all lanes
 // Decoder lanes: two lanes per chunk (one per half, the second from the
@@ -2400,7 +2403,7 @@ __global__ void __launch_bounds__(DecShape<CT>::NT) decode_kernel(const uint8_t*
   __shared__ uint2 s_mlut[sizeof(CT) == 1 ? 4096 : 1];
   __shared__ uint32_t s_ring[sizeof(CT) == 1 ? kDecRing : 1][sizeof(CT) == 1 ? NT : 1];  // 1-byte codes: per-lane bitstream ring
   const uint32_t nsorted = D->nsorted;
-  const bool syms_lds = nsorted <= kSyms;
+  const uint32_t nsl = min(nsorted, kSyms);  // symbols held in LDS (the shortest codes')
   const uint32_t n2 = sizeof(CT) == 1 ? D->lut2_n : 0u, p02 = sizeof(CT) == 1 ? D->lut2_p0 : 0u;
   if constexpr (sizeof(CT) == 1)
     if (n2)
@@ -2411,8 +2414,7 @@ __global__ void __launch_bounds__(DecShape<CT>::NT) decode_kernel(const uint8_t*
       const uint64_t e = D->mlut[i];
       s_mlut[i] = make_uint2((uint32_t)e, (uint32_t)(e >> 32));
     }
-  if (syms_lds)
-    for (uint32_t i = threadIdx.x; i < nsorted; i += NT) s_syms[i] = (uint16_t)sorted_syms[i];
+  for (uint32_t i = threadIdx.x; i < nsl; i += NT) s_syms[i] = (uint16_t)sorted_syms[i];
   if (threadIdx.x < 32) {
     s_first[threadIdx.x] = D->first[threadIdx.x];
     s_start[threadIdx.x] = D->start[threadIdx.x];
@@ -2582,7 +2584,7 @@ __global__ void __launch_bounds__(DecShape<CT>::NT) decode_kernel(const uint8_t*
             break;
           }
           const uint32_t idx = s_start[l1] + ((v27 >> (kLmax - l1)) - s_first[l1]);
-          if (syms_lds) {
+          if (idx < nsl) {
             sym = s_syms[idx];
           } else {
             sym = sorted_syms[idx];
@@ -2658,7 +2660,7 @@ __global__ void __launch_bounds__(DecShape<CT>::NT) decode_kernel(const uint8_t*
         break;
       }
       const uint32_t idx = s_start[l] + ((v27 >> (kLmax - l)) - s_first[l]);
-      if (syms_lds) {
+      if (idx < nsl) {
         sym = s_syms[idx];
       } else {
         sym = sorted_syms[idx];
